@@ -1,0 +1,162 @@
+"""FP64 CPU oracle for the short-characteristics radiation transport solve.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg are its only users.  It is independent of the HIP library:
+this wrapper loads `liboracle.so`, built from `rts_oracle.cpp` with g++, and
+passes plain float64 numpy arrays.  It never imports the product package.
+
+Each function states the computation it performs; the underlying C++ cites the
+paper's passages (arXiv 2107.08145, section "Summary of the Radiation Transport
+Solver" and the RTS core-loop figure).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rts_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_CXXFLAGS = ["-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+             "-fno-fast-math", "-fopenmp"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (the plain serial-order build, OpenMP over plane cells)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["g++", *_CXXFLAGS, "-o", tmp, _SRC], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        d, i, p, i64 = ctypes.c_double, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64
+        head = [i, i, i, d, d, d, i, i, p, p, p, i, i, d, i]
+        lib.oracle_solve.argtypes = head + [p, p, p, p, p, p, i]
+        lib.oracle_solve_chi.argtypes = head + [p, p, p, p, p, i]
+        lib.oracle_adjoint.argtypes = head + [p, p, p, p, p, p, p, i]
+        lib.oracle_complex_step.argtypes = head + [p, p, i, i64, d, p, p, p, i]
+        lib.oracle_ray.argtypes = [i, i, i, d, d, d, p, i, i, d, i, p, p, p]
+        lib.oracle_weights.argtypes = [d, p, p, p, p]
+        for f in ("oracle_solve", "oracle_solve_chi", "oracle_adjoint",
+                  "oracle_complex_step", "oracle_ray"):
+            getattr(lib, f).restype = i
+        lib.oracle_weights.restype = None
+        _lib = lib
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _head(p):
+    mu, w, qw = _f64(p.mu), _f64(p.w), _f64(p.qweight)
+    keep = (mu, w, qw)
+    return keep, [p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.nbands, p.nrays,
+                  _ptr(mu), _ptr(w), _ptr(qw), p.bot, p.top, p.i_bot, p.n_iter]
+
+
+def solve(p, threads: int = 1, chi=None):
+    """Forward solve of problem `p` (see paper_2107_08145_amd.inputs.Problem).
+
+    Returns (Q [nz,ny,nx], J [B,nz,ny,nx], I_top [B,n_up,ny,nx]) in float64.
+    With `chi` given, it replaces kappa * rho (shape [B,nz,ny,nx]).
+    """
+    lib = _load()
+    keep, head = _head(p)
+    B, N = p.nbands, p.ncells
+    Q = np.empty((p.nz, p.ny, p.nx))
+    J = np.empty((B, p.nz, p.ny, p.nx))
+    It = np.empty((B, p.n_up, p.ny, p.nx))
+    S = _f64(p.S)
+    if chi is None:
+        kap, rho = _f64(p.kappa), _f64(p.rho)
+        rc = lib.oracle_solve(*head, _ptr(kap), _ptr(rho), _ptr(S), _ptr(Q), _ptr(J), _ptr(It),
+                              threads)
+    else:
+        c = _f64(chi)
+        rc = lib.oracle_solve_chi(*head, _ptr(c), _ptr(S), _ptr(Q), _ptr(J), _ptr(It), threads)
+    if rc:
+        raise ValueError("oracle rejected the problem")
+    del keep
+    return Q, J, It
+
+
+def chi_of(p):
+    """Extinction per band, chi_b = kappa_b * rho (float64)."""
+    return _f64(p.kappa) * _f64(p.rho)[None]
+
+
+def adjoint(p, gQ=None, gJ=None, gItop=None, threads: int = 1, chi=None):
+    """Gradients (dL/dS [B,...], dL/dchi [B,...]) of L = <gQ,Q> + <gJ,J> + <gItop,I_top>."""
+    lib = _load()
+    keep, head = _head(p)
+    c = chi_of(p) if chi is None else _f64(chi)
+    S = _f64(p.S)
+    gq = None if gQ is None else _f64(gQ)
+    gj = None if gJ is None else _f64(gJ)
+    gi = None if gItop is None else _f64(gItop)
+    dS = np.empty_like(S)
+    dc = np.empty_like(S)
+    rc = lib.oracle_adjoint(*head, _ptr(c), _ptr(S), _ptr(gq), _ptr(gj), _ptr(gi),
+                            _ptr(dS), _ptr(dc), threads)
+    if rc:
+        raise ValueError("oracle rejected the problem")
+    del keep
+    return dS, dc
+
+
+def complex_step(p, which: str, index: int, h: float = 1e-30, chi=None, threads: int = 1):
+    """Exact directional derivatives of (Q, J, I_top) w.r.t. S or chi at flat index
+    `index` of the [B,N] array, by the complex-step method."""
+    lib = _load()
+    keep, head = _head(p)
+    c = chi_of(p) if chi is None else _f64(chi)
+    S = _f64(p.S)
+    dQ = np.empty((p.nz, p.ny, p.nx))
+    dJ = np.empty((p.nbands, p.nz, p.ny, p.nx))
+    dI = np.empty((p.nbands, p.n_up, p.ny, p.nx))
+    rc = lib.oracle_complex_step(*head, _ptr(c), _ptr(S), 1 if which == "chi" else 0,
+                                 int(index), h, _ptr(dQ), _ptr(dJ), _ptr(dI), threads)
+    if rc:
+        raise ValueError("oracle rejected the problem")
+    del keep
+    return dQ, dJ, dI
+
+
+def ray_intensity(nx, ny, nz, dx, dy, dz, mu3, chi, S, bot=0, top=0, i_bot=0.0, n_iter=3):
+    """Intensity field [nz,ny,nx] of one ray after all of its sweeps."""
+    lib = _load()
+    m = _f64(mu3)
+    c, s = _f64(chi), _f64(S)
+    out = np.empty((nz, ny, nx))
+    rc = lib.oracle_ray(nx, ny, nz, dx, dy, dz, _ptr(m), bot, top, i_bot, n_iter,
+                        _ptr(c), _ptr(s), _ptr(out))
+    if rc:
+        raise ValueError("oracle rejected the ray")
+    return out
+
+
+def weights(x: float):
+    """(e, w0, w1, w1/x) of the linear-source formal solution at optical depth x."""
+    lib = _load()
+    out = [ctypes.c_double() for _ in range(4)]
+    lib.oracle_weights(float(x), *[ctypes.byref(o) for o in out])
+    return tuple(o.value for o in out)

@@ -1,0 +1,537 @@
+// FP64 CPU oracle for the short-characteristics radiation transport solve of
+// arXiv 2107.08145 (MURaM), section "Summary of the Radiation Transport Solver"
+// and the RTS core loop figure (per ray: interpolate, then iterate
+// integrate / write buffer / exchange, then flux).
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+// HIP library is checked against.  Only the tests, the smoke check and the
+// benchmark's CPU-baseline leg may load it.  It shares no code with the HIP
+// path (no headers, helpers, tables or generators); it sees only the problem
+// statement as plain arrays.
+//
+// What is computed (the readings of the paper's unstated details are listed
+// in the design notes of the repository):
+//   * chi_b = kappa_b * rho, the extinction per unit length.
+//   * Per ray (unit direction mu, weight w): ds = min over axes d with
+//     mu_d != 0 of delta_d / |mu_d|; the arg-min is the dominant axis (ties go
+//     to z, then y, then x).  Each cell's upwind point lies ds back along the
+//     ray, in the previous grid plane along the dominant axis, between the
+//     four cells offset by 0 / -sign(mu_e) along the two in-plane axes e, at
+//     fractions f_e = ds |mu_e| / delta_e ("up to four" upwind points in the
+//     wavefront-dependency figure).  I, S and chi there are bilinear in those
+//     four cells.
+//   * Optical depth of the segment: trapezoid, dtau = ds/2 (chi_p + chi_u).
+//   * Formal solution with S linear in optical depth between u and p,
+//     integrated exactly against exp(-t):
+//        I_p = e I_u + w0 S_p + w1 S_u,  e = exp(-x),
+//        w0 = (x - 1 + e)/x,  w1 = (1 - e (1 + x))/x,  x = dtau,
+//     with the power series below x = 0.5 (where the closed forms cancel).
+//   * Boundaries: x and y periodic; rays with mu_z > 0 start from the bottom
+//     layer k = 0 (I = S, or a fixed I), rays with mu_z < 0 from the top layer
+//     k = nz-1 (I = 0, or I = S).  These layers are set, not integrated.
+//   * Periodic boundary iteration (the paper's "3 to 4 iterations" of
+//     boundary intensities, exchanged through buffers): a ray whose dominant
+//     axis is x or y reads its first plane's upwind intensities from a ghost
+//     plane.  The ghost starts at I = S (boundary-layer cells at their boundary
+//     value) and is overwritten with the last swept plane after each of the
+//     n_iter sweeps.  Rays with a z dominant axis need no ghost: one sweep.
+//   * Flux: J_b = sum_r w_r I_r after the last sweep; I_top = I in the top
+//     layer for mu_z > 0 rays; Q = sum_b qweight_b 4 pi chi_b (J_b - S_b).
+//   * Adjoint: the reverse-mode derivative of the above (downwind to upwind,
+//     last sweep first, ghost sensitivities carried into the previous sweep).
+//
+// Build: g++ -O2 -std=c++17 -fPIC -shared -ffp-contract=off -fno-fast-math -fopenmp
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+using cplx = std::complex<double>;
+
+inline double re(double v) { return v; }
+inline double re(const cplx& v) { return v.real(); }
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSeriesBelow = 0.5;  // closed forms lose < 2e-15 relative above this
+
+// Problem statement.
+struct Desc {
+  int n[3];          // nx, ny, nz
+  double d[3];       // dx, dy, dz
+  int nb, nr;        // bands, rays
+  const double* mu;  // [nr][3]
+  const double* w;   // [nr]
+  const double* qw;  // [nb]
+  int bot, top;      // 0: thermal bottom / zero top, 1: fixed bottom / thermal top
+  double ibot;
+  int n_iter;
+  int64_t cells() const { return (int64_t)n[0] * n[1] * n[2]; }
+  int64_t at(int i, int j, int k) const { return ((int64_t)k * n[1] + j) * n[0] + i; }
+};
+
+// Linear-source weights (e, w0, w1) for optical depth x.
+template <class T>
+struct Wts { T e, w0, w1; };
+
+template <class T>
+Wts<T> weights(const T& x) {
+  Wts<T> r;
+  r.e = std::exp(-x);
+  if (re(x) < kSeriesBelow) {
+    // w0 = sum_{n>=2} (-1)^n x^(n-1)/n!,  w1 = sum_{n>=2} (-1)^n (n-1) x^(n-1)/n!
+    T term = x / 2.0;
+    T w0 = 0.0, w1 = 0.0;
+    for (int n = 2; n <= 22; ++n) {
+      w0 += term;
+      w1 += double(n - 1) * term;
+      term *= -x / double(n + 1);
+    }
+    r.w0 = w0;
+    r.w1 = w1;
+  } else {
+    r.w0 = (x - 1.0 + r.e) / x;
+    r.w1 = (1.0 - r.e * (1.0 + x)) / x;
+  }
+  return r;
+}
+
+// w1 / x, which is dw0/dx; dw1/dx = e - w1/x.
+double w1_over_x(double x, double e) {
+  if (x < kSeriesBelow) {
+    // sum_{n>=2} (-1)^n (n-1) x^(n-2) / n!
+    double term = 0.5, s = 0.0;
+    for (int n = 2; n <= 23; ++n) {
+      s += double(n - 1) * term;
+      term *= -x / double(n + 1);
+    }
+    return s;
+  }
+  return (1.0 - e * (1.0 + x)) / (x * x);
+}
+
+// Per-ray geometry.
+struct Ray {
+  int axis, sa;      // dominant axis and its sign
+  int ea, eb;        // in-plane axes, ea < eb
+  int sea, seb;      // signs along them
+  double fa, fb;     // upwind fractions along them
+  double ds;         // path length to the upwind plane
+  bool up;           // mu_z > 0
+};
+
+bool make_ray(const Desc& D, const double* mu, Ray& r) {
+  if (mu[2] == 0.0) return false;
+  double best = INFINITY;
+  r.axis = -1;
+  for (int d = 0; d < 3; ++d) {
+    if (mu[d] == 0.0) continue;
+    double s = D.d[d] / std::fabs(mu[d]);
+    if (s <= best) { best = s; r.axis = d; }  // later axis wins ties: z, then y, then x
+  }
+  r.ds = best;
+  r.sa = mu[r.axis] > 0 ? 1 : -1;
+  int e[2], m = 0;
+  for (int d = 0; d < 3; ++d) if (d != r.axis) e[m++] = d;
+  r.ea = e[0]; r.eb = e[1];
+  r.sea = mu[r.ea] >= 0 ? 1 : -1;
+  r.seb = mu[r.eb] >= 0 ? 1 : -1;
+  r.fa = r.ds * std::fabs(mu[r.ea]) / D.d[r.ea];
+  r.fb = r.ds * std::fabs(mu[r.eb]) / D.d[r.eb];
+  r.up = mu[2] > 0;
+  return true;
+}
+
+inline int wrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Boundary-layer intensity for a cell with source function s.
+template <class T>
+T bc_value(const Desc& D, const Ray& r, const T& s) {
+  if (r.up) return D.bot == 0 ? s : T(D.ibot);
+  return D.top == 0 ? T(0.0) : s;
+}
+
+inline bool is_bc_layer(const Desc& D, const Ray& r, int k) {
+  return r.up ? (k == 0) : (k == D.n[2] - 1);
+}
+
+// One ray of one band: n_sweeps sweeps (1 for z-dominant rays), I overwritten.
+// If `store` is given, the intensities after every sweep are appended to it.
+template <class T>
+void solve_ray(const Desc& D, const Ray& r, const T* chi, const T* S, T* I,
+               std::vector<std::vector<T>>* store, int nt) {
+  const int na = D.n[r.axis], nA = D.n[r.ea], nB = D.n[r.eb];
+  const bool periodic = r.axis != 2;
+  const int sweeps = periodic ? D.n_iter : 1;
+  auto cell = [&](int q, int a, int b) {
+    int c[3];
+    c[r.axis] = q; c[r.ea] = a; c[r.eb] = b;
+    return D.at(c[0], c[1], c[2]);
+  };
+  auto kz = [&](int q, int a, int b) {
+    int c[3];
+    c[r.axis] = q; c[r.ea] = a; c[r.eb] = b;
+    return c[2];
+  };
+  const double b00 = (1 - r.fa) * (1 - r.fb), b10 = r.fa * (1 - r.fb);
+  const double b01 = (1 - r.fa) * r.fb, b11 = r.fa * r.fb;
+  const int q_first = r.sa > 0 ? 0 : na - 1;
+  const int q_last = r.sa > 0 ? na - 1 : 0;
+
+  // Boundary layer: set, not integrated.
+  for (int q = 0; q < na; ++q)
+    for (int a = 0; a < nA; ++a)
+      for (int b = 0; b < nB; ++b)
+        if (is_bc_layer(D, r, kz(q, a, b))) {
+          int64_t p = cell(q, a, b);
+          I[p] = bc_value(D, r, S[p]);
+        }
+
+  // Ghost plane for periodic sweeps: I = S of the wrapped upwind plane.
+  std::vector<T> ghost;
+  if (periodic) {
+    ghost.resize((size_t)nA * nB);
+    for (int a = 0; a < nA; ++a)
+      for (int b = 0; b < nB; ++b) {
+        int64_t p = cell(q_last, a, b);
+        ghost[(size_t)a * nB + b] =
+            is_bc_layer(D, r, kz(q_last, a, b)) ? bc_value(D, r, S[p]) : S[p];
+      }
+  }
+
+  for (int sweep = 0; sweep < sweeps; ++sweep) {
+    // z-dominant rays start one plane in: their first plane is the boundary layer.
+    for (int t = periodic ? 0 : 1; t < na; ++t) {
+      const int q = q_first + r.sa * t;
+      const int qu = wrap(q - r.sa, na);
+      const bool from_ghost = periodic && t == 0;
+#pragma omp parallel for collapse(2) num_threads(nt) schedule(static)
+      for (int a = 0; a < nA; ++a)
+        for (int b = 0; b < nB; ++b) {
+          if (is_bc_layer(D, r, kz(q, a, b))) continue;
+          const int64_t p = cell(q, a, b);
+          // upwind corners (in-plane z never leaves the grid for a non-boundary cell)
+          const int a1 = r.ea == 2 ? a - r.sea : wrap(a - r.sea, nA);
+          const int b1 = r.eb == 2 ? b - r.seb : wrap(b - r.seb, nB);
+          const int64_t u00 = cell(qu, a, b), u10 = cell(qu, a1, b);
+          const int64_t u01 = cell(qu, a, b1), u11 = cell(qu, a1, b1);
+          T i00, i10, i01, i11;
+          if (from_ghost) {
+            i00 = ghost[(size_t)a * nB + b];  i10 = ghost[(size_t)a1 * nB + b];
+            i01 = ghost[(size_t)a * nB + b1]; i11 = ghost[(size_t)a1 * nB + b1];
+          } else {
+            i00 = I[u00]; i10 = I[u10]; i01 = I[u01]; i11 = I[u11];
+          }
+          const T iu = b00 * i00 + b10 * i10 + b01 * i01 + b11 * i11;
+          const T su = b00 * S[u00] + b10 * S[u10] + b01 * S[u01] + b11 * S[u11];
+          const T cu = b00 * chi[u00] + b10 * chi[u10] + b01 * chi[u01] + b11 * chi[u11];
+          const T x = 0.5 * r.ds * (chi[p] + cu);
+          const Wts<T> wt = weights(x);
+          I[p] = wt.e * iu + wt.w0 * S[p] + wt.w1 * su;
+        }
+    }
+    if (periodic) {  // exchange: the outflow plane becomes the next sweep's ghost
+      for (int a = 0; a < nA; ++a)
+        for (int b = 0; b < nB; ++b) ghost[(size_t)a * nB + b] = I[cell(q_last, a, b)];
+    }
+    if (store) store->emplace_back(I, I + D.cells());
+  }
+}
+
+template <class T>
+int forward(const Desc& D, const T* chi, const T* S, T* Q, T* J, T* Itop, int nt,
+            std::vector<std::vector<T>>* store, std::vector<T>* Jall) {
+  const int64_t N = D.cells();
+  std::vector<Ray> rays(D.nr);
+  for (int r = 0; r < D.nr; ++r)
+    if (!make_ray(D, D.mu + 3 * r, rays[r])) return -1;
+  for (int64_t p = 0; p < N; ++p) Q[p] = 0.0;
+  std::vector<T> I(N), Jb(N);
+  const int64_t plane = (int64_t)D.n[0] * D.n[1];
+  int nup = 0;
+  for (int r = 0; r < D.nr; ++r) nup += rays[r].up;
+  for (int b = 0; b < D.nb; ++b) {
+    const T* chib = chi + b * N;
+    const T* Sb = S + b * N;
+    for (int64_t p = 0; p < N; ++p) Jb[p] = 0.0;
+    int ru = 0;
+    for (int r = 0; r < D.nr; ++r) {
+      solve_ray(D, rays[r], chib, Sb, I.data(), store, nt);
+      for (int64_t p = 0; p < N; ++p) Jb[p] += D.w[r] * I[p];
+      if (rays[r].up) {
+        if (Itop) {
+          T* dst = Itop + ((int64_t)b * nup + ru) * plane;
+          for (int64_t p = 0; p < plane; ++p) dst[p] = I[(int64_t)(D.n[2] - 1) * plane + p];
+        }
+        ++ru;
+      }
+    }
+    const double qf = 4.0 * kPi * D.qw[b];
+    for (int64_t p = 0; p < N; ++p) Q[p] += qf * chib[p] * (Jb[p] - Sb[p]);
+    if (J) std::memcpy(J + b * N, Jb.data(), sizeof(T) * N);
+    if (Jall) Jall->insert(Jall->end(), Jb.begin(), Jb.end());
+  }
+  return 0;
+}
+
+// Reverse-mode derivative of forward() for T = double.
+int adjoint(const Desc& D, const double* chi, const double* S, const double* gQ,
+            const double* gJ, const double* gItop, double* dS, double* dchi, int nt) {
+  const int64_t N = D.cells();
+  std::vector<Ray> rays(D.nr);
+  for (int r = 0; r < D.nr; ++r)
+    if (!make_ray(D, D.mu + 3 * r, rays[r])) return -1;
+  std::vector<std::vector<double>> store;
+  std::vector<double> Q(N), Jall;
+  {
+    // Forward with every sweep kept.
+    int rc = forward<double>(D, chi, S, Q.data(), nullptr, nullptr, nt, &store, &Jall);
+    if (rc) return rc;
+  }
+  const int64_t plane = (int64_t)D.n[0] * D.n[1];
+  int nup = 0;
+  for (int r = 0; r < D.nr; ++r) nup += rays[r].up;
+  size_t si = 0;  // index into store
+  std::vector<double> gJt(N), lam(N), lam_prev(N);
+  for (int b = 0; b < D.nb; ++b) {
+    const double* chib = chi + b * N;
+    const double* Sb = S + b * N;
+    const double* Jb = Jall.data() + b * N;
+    double* dSb = dS + b * N;
+    double* dcb = dchi + b * N;
+    const double qf = 4.0 * kPi * D.qw[b];
+    for (int64_t p = 0; p < N; ++p) {
+      const double g = gQ ? gQ[p] : 0.0;
+      gJt[p] = qf * chib[p] * g + (gJ ? gJ[b * N + p] : 0.0);
+      dcb[p] = qf * (Jb[p] - Sb[p]) * g;
+      dSb[p] = -qf * chib[p] * g;
+    }
+    int ru = 0;
+    for (int r = 0; r < D.nr; ++r) {
+      const Ray& R = rays[r];
+      const int na = D.n[R.axis], nA = D.n[R.ea], nB = D.n[R.eb];
+      const bool periodic = R.axis != 2;
+      const int sweeps = periodic ? D.n_iter : 1;
+      const size_t first_store = si;
+      si += sweeps;
+      auto cell = [&](int q, int a, int bb) {
+        int c[3];
+        c[R.axis] = q; c[R.ea] = a; c[R.eb] = bb;
+        return D.at(c[0], c[1], c[2]);
+      };
+      auto kz = [&](int q, int a, int bb) {
+        int c[3];
+        c[R.axis] = q; c[R.ea] = a; c[R.eb] = bb;
+        return c[2];
+      };
+      const double b00 = (1 - R.fa) * (1 - R.fb), b10 = R.fa * (1 - R.fb);
+      const double b01 = (1 - R.fa) * R.fb, b11 = R.fa * R.fb;
+      const int q_first = R.sa > 0 ? 0 : na - 1;
+      const int q_last = R.sa > 0 ? na - 1 : 0;
+      // seeds of the last sweep
+      for (int64_t p = 0; p < N; ++p) lam[p] = D.w[r] * gJt[p];
+      if (R.up) {
+        if (gItop) {
+          const double* g = gItop + ((int64_t)b * nup + ru) * plane;
+          for (int64_t p = 0; p < plane; ++p) lam[(int64_t)(D.n[2] - 1) * plane + p] += g[p];
+        }
+        ++ru;
+      }
+      std::vector<double> lamG(periodic ? (size_t)nA * nB : 0);
+      for (int sweep = sweeps - 1; sweep >= 0; --sweep) {
+        const std::vector<double>& I = store[first_store + sweep];
+        const std::vector<double>* Iprev = sweep > 0 ? &store[first_store + sweep - 1] : nullptr;
+        std::fill(lamG.begin(), lamG.end(), 0.0);
+        for (int t = na - 1; t >= (periodic ? 0 : 1); --t) {
+          const int q = q_first + R.sa * t;
+          const int qu = wrap(q - R.sa, na);
+          const bool from_ghost = periodic && t == 0;
+          for (int a = 0; a < nA; ++a)
+            for (int bb = 0; bb < nB; ++bb) {
+              const int64_t p = cell(q, a, bb);
+              const double lp = lam[p];
+              if (is_bc_layer(D, R, kz(q, a, bb))) continue;  // handled below
+              if (lp == 0.0) continue;
+              const int a1 = R.ea == 2 ? a - R.sea : wrap(a - R.sea, nA);
+              const int b1 = R.eb == 2 ? bb - R.seb : wrap(bb - R.seb, nB);
+              const int64_t u[4] = {cell(qu, a, bb), cell(qu, a1, bb), cell(qu, a, b1), cell(qu, a1, b1)};
+              const double beta[4] = {b00, b10, b01, b11};
+              const size_t gidx[4] = {(size_t)a * nB + bb, (size_t)a1 * nB + bb,
+                                      (size_t)a * nB + b1, (size_t)a1 * nB + b1};
+              double iu = 0, su = 0, cu = 0;
+              for (int c = 0; c < 4; ++c) {
+                double iv;
+                if (from_ghost) {
+                  if (Iprev) iv = (*Iprev)[u[c]];  // ghost = previous sweep's outflow plane (qu is the outflow plane)
+                  else {
+                    const int kc = (int)(u[c] / plane);
+                    iv = is_bc_layer(D, R, kc) ? bc_value(D, R, Sb[u[c]]) : Sb[u[c]];
+                  }
+                } else {
+                  iv = I[u[c]];
+                }
+                iu += beta[c] * iv;
+                su += beta[c] * Sb[u[c]];
+                cu += beta[c] * chib[u[c]];
+              }
+              const double x = 0.5 * R.ds * (chib[p] + cu);
+              const Wts<double> wt = weights(x);
+              const double wx = w1_over_x(x, wt.e);
+              // I_p = e iu + w0 S_p + w1 su
+              const double gx = lp * (-wt.e * iu + wx * Sb[p] + (wt.e - wx) * su);
+              dSb[p] += wt.w0 * lp;
+              dcb[p] += 0.5 * R.ds * gx;
+              for (int c = 0; c < 4; ++c) {
+                if (from_ghost) lamG[gidx[c]] += beta[c] * wt.e * lp;
+                else lam[u[c]] += beta[c] * wt.e * lp;
+                dSb[u[c]] += beta[c] * wt.w1 * lp;
+                dchi[b * N + u[c]] += beta[c] * 0.5 * R.ds * gx;
+              }
+            }
+        }
+        // Boundary-layer cells of this sweep: I = S contributes to dS.
+        for (int q = 0; q < na; ++q)
+          for (int a = 0; a < nA; ++a)
+            for (int bb = 0; bb < nB; ++bb)
+              if (is_bc_layer(D, R, kz(q, a, bb))) {
+                const bool thermal = R.up ? D.bot == 0 : D.top == 1;
+                if (thermal) dSb[cell(q, a, bb)] += lam[cell(q, a, bb)];
+              }
+        if (!periodic) break;
+        // Ghost sensitivities flow into the previous sweep's outflow plane, or
+        // into the initial ghost (I = S of the wrapped plane).
+        std::fill(lam.begin(), lam.end(), 0.0);
+        for (int a = 0; a < nA; ++a)
+          for (int bb = 0; bb < nB; ++bb) {
+            const double g = lamG[(size_t)a * nB + bb];
+            const int64_t p = cell(q_last, a, bb);
+            if (sweep > 0) {
+              lam[p] += g;
+            } else if (is_bc_layer(D, R, kz(q_last, a, bb))) {
+              const bool thermal = R.up ? D.bot == 0 : D.top == 1;
+              if (thermal) dSb[p] += g;
+            } else {
+              dSb[p] += g;
+            }
+          }
+      }
+    }
+  }
+  return 0;
+}
+
+Desc make_desc(int nx, int ny, int nz, double dx, double dy, double dz, int nb, int nr,
+               const double* mu, const double* w, const double* qw, int bot, int top,
+               double ibot, int n_iter) {
+  Desc D;
+  D.n[0] = nx; D.n[1] = ny; D.n[2] = nz;
+  D.d[0] = dx; D.d[1] = dy; D.d[2] = dz;
+  D.nb = nb; D.nr = nr; D.mu = mu; D.w = w; D.qw = qw;
+  D.bot = bot; D.top = top; D.ibot = ibot; D.n_iter = n_iter;
+  return D;
+}
+
+bool valid(const Desc& D) {
+  for (int d = 0; d < 3; ++d)
+    if (D.n[d] < 2 || !(D.d[d] > 0)) return false;
+  return D.nb >= 1 && D.nr >= 1 && D.n_iter >= 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Forward solve from extinction chi [nb][N] and source S [nb][N] (C order
+// [z][y][x]).  Q [N] is written; J [nb][N] and Itop [nb][n_up][ny][nx] if not
+// null.  Returns 0, or -1 on invalid input.
+int oracle_solve_chi(int nx, int ny, int nz, double dx, double dy, double dz, int nb, int nr,
+                     const double* mu, const double* w, const double* qw, int bot, int top,
+                     double ibot, int n_iter, const double* chi, const double* S, double* Q,
+                     double* J, double* Itop, int nthreads) {
+  Desc D = make_desc(nx, ny, nz, dx, dy, dz, nb, nr, mu, w, qw, bot, top, ibot, n_iter);
+  if (!valid(D)) return -1;
+  return forward<double>(D, chi, S, Q, J, Itop, nthreads > 0 ? nthreads : 1, nullptr, nullptr);
+}
+
+// Same, from kappa [nb][N] and rho [N]: chi_b = kappa_b * rho.
+int oracle_solve(int nx, int ny, int nz, double dx, double dy, double dz, int nb, int nr,
+                 const double* mu, const double* w, const double* qw, int bot, int top,
+                 double ibot, int n_iter, const double* kappa, const double* rho,
+                 const double* S, double* Q, double* J, double* Itop, int nthreads) {
+  Desc D = make_desc(nx, ny, nz, dx, dy, dz, nb, nr, mu, w, qw, bot, top, ibot, n_iter);
+  if (!valid(D)) return -1;
+  const int64_t N = D.cells();
+  std::vector<double> chi((size_t)nb * N);
+  for (int b = 0; b < nb; ++b)
+    for (int64_t p = 0; p < N; ++p) chi[b * N + p] = kappa[b * N + p] * rho[p];
+  return forward<double>(D, chi.data(), S, Q, J, Itop, nthreads > 0 ? nthreads : 1, nullptr,
+                         nullptr);
+}
+
+// Intensity of one ray for one band (I [N]) after all its sweeps.
+int oracle_ray(int nx, int ny, int nz, double dx, double dy, double dz, const double* mu3,
+               int bot, int top, double ibot, int n_iter, const double* chi, const double* S,
+               double* I) {
+  const double w1 = 1.0, q1 = 1.0;
+  Desc D = make_desc(nx, ny, nz, dx, dy, dz, 1, 1, mu3, &w1, &q1, bot, top, ibot, n_iter);
+  if (!valid(D)) return -1;
+  Ray r;
+  if (!make_ray(D, mu3, r)) return -1;
+  solve_ray<double>(D, r, chi, S, I, nullptr, 1);
+  return 0;
+}
+
+// Linear-source weights, exposed for the weight-function pins.
+void oracle_weights(double x, double* e, double* w0, double* w1, double* w1x) {
+  Wts<double> wt = weights(x);
+  *e = wt.e; *w0 = wt.w0; *w1 = wt.w1;
+  *w1x = w1_over_x(x, wt.e);
+}
+
+// Reverse-mode gradients of L = sum(gQ Q) + sum(gJ J) + sum(gItop Itop) with
+// respect to S [nb][N] and chi [nb][N].  gQ, gJ, gItop may be null.
+int oracle_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, int nb, int nr,
+                   const double* mu, const double* w, const double* qw, int bot, int top,
+                   double ibot, int n_iter, const double* chi, const double* S,
+                   const double* gQ, const double* gJ, const double* gItop, double* dS,
+                   double* dchi, int nthreads) {
+  Desc D = make_desc(nx, ny, nz, dx, dy, dz, nb, nr, mu, w, qw, bot, top, ibot, n_iter);
+  if (!valid(D)) return -1;
+  return adjoint(D, chi, S, gQ, gJ, gItop, dS, dchi, nthreads > 0 ? nthreads : 1);
+}
+
+// Complex-step directional derivative: chi or S (which = 1 or 0) at flat index
+// `idx` of the [nb][N] array is perturbed by i*h; the imaginary parts of Q, J
+// and Itop divided by h are returned (J, Itop may be null).
+int oracle_complex_step(int nx, int ny, int nz, double dx, double dy, double dz, int nb,
+                        int nr, const double* mu, const double* w, const double* qw, int bot,
+                        int top, double ibot, int n_iter, const double* chi, const double* S,
+                        int which, int64_t idx, double h, double* dQ, double* dJ,
+                        double* dItop, int nthreads) {
+  Desc D = make_desc(nx, ny, nz, dx, dy, dz, nb, nr, mu, w, qw, bot, top, ibot, n_iter);
+  if (!valid(D)) return -1;
+  const int64_t N = D.cells();
+  std::vector<cplx> c(chi, chi + nb * N), s(S, S + nb * N), Q(N), J((size_t)nb * N);
+  int nup = 0;
+  for (int r = 0; r < nr; ++r) nup += mu[3 * r + 2] > 0;
+  const int64_t plane = (int64_t)nx * ny;
+  std::vector<cplx> It((size_t)nb * nup * plane);
+  if (which) c[idx] += cplx(0.0, h);
+  else s[idx] += cplx(0.0, h);
+  int rc = forward<cplx>(D, c.data(), s.data(), Q.data(), J.data(), It.data(),
+                         nthreads > 0 ? nthreads : 1, nullptr, nullptr);
+  if (rc) return rc;
+  for (int64_t p = 0; p < N; ++p) dQ[p] = Q[p].imag() / h;
+  if (dJ)
+    for (int64_t p = 0; p < nb * N; ++p) dJ[p] = J[p].imag() / h;
+  if (dItop)
+    for (size_t p = 0; p < It.size(); ++p) dItop[p] = It[p].imag() / h;
+  return 0;
+}
+
+}  // extern "C"
