@@ -1,0 +1,173 @@
+/*
+ * rts.h -- C ABI of librts, an MI355X (gfx950) short-characteristics radiation
+ * transport solver (RTS) after arXiv 2107.08145 (MURaM), section "Summary of
+ * the Radiation Transport Solver":
+ *
+ *   For every ray of a three-rays-per-octant angular quadrature and every
+ *   frequency band, the transfer equation is integrated along short
+ *   characteristics, upwind to downwind, plane by plane (the wavefront
+ *   dependency figure: each point depends on up to four points of the previous
+ *   plane).  Boundary intensities of the periodic horizontal directions are
+ *   iterated a fixed number of times (the paper reports 3 to 4 iterations).
+ *   The mean intensity J and the radiative heating Q are formed from the
+ *   converged intensities (the "flux" step of the RTS core loop).
+ *
+ * Discretisation (shared with the CPU oracle by specification only):
+ *   chi_b = kappa_b * rho;  dtau = ds/2 (chi_p + chi_u) with bilinear upwind
+ *   values;  I_p = e I_u + w0 S_p + w1 S_u (S linear in tau), e = exp(-dtau);
+ *   J_b = sum_r w_r I_r;  Q = sum_b qweight_b * 4 pi * chi_b * (J_b - S_b).
+ *   The library sweeps D = I - S, an exact rewrite of the same recursion:
+ *   D_p = e D_u + c (S_u - S_p), c = (1 - e)/dtau.
+ *
+ * Conventions
+ *   - Arrays are C order [z][y][x], x fastest, k = 0 the bottom layer.
+ *     N = nx*ny*nz.  Multi-band arrays are [band][z][y][x].
+ *   - Array pointers in rts_inputs / rts_outputs / rts_seeds / rts_grads and the
+ *     workspace are DEVICE pointers owned by the caller.  Pointers inside
+ *     rts_desc (mu, w, qweight) are HOST pointers, read during
+ *     rts_plan_create only.
+ *   - The element type of kappa, rho, S, J, I_top, dS, dchi is double for
+ *     RTS_FP64 and float for RTS_FP32; Q (and gQ) are always double.
+ *   - All calls return an int status: RTS_OK (0) or a negative RTS_E_* code.
+ *     No C++ exception crosses the ABI.  rts_status_string() describes a code;
+ *     after RTS_E_HIP it also carries the HIP error text of the calling thread.
+ *   - The library allocates no device memory.  Scratch space is the caller's
+ *     workspace of at least rts_workspace_bytes() bytes, 256-byte aligned.
+ *   - Work is enqueued on `hip_stream` (a hipStream_t, NULL = legacy default)
+ *     and is asynchronous.  Outputs are overwritten, never accumulated.  For a
+ *     fixed plan, results are bitwise reproducible.
+ *   - A plan and its workspace must not be used by two calls in flight at the
+ *     same time (they share the workspace's queue counters and flags).
+ */
+#ifndef RTS_H
+#define RTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define RTS_OK 0
+#define RTS_E_ARG (-1)         /* invalid argument: null pointer, bad size, mu_z == 0, ... */
+#define RTS_E_UNSUPPORTED (-2) /* valid but not supported by this build (e.g. nx > 1024)  */
+#define RTS_E_WORKSPACE (-3)   /* workspace null, misaligned or too small                  */
+#define RTS_E_HIP (-4)         /* a HIP runtime call failed                                */
+#define RTS_E_DEADLOCK (-5)    /* the sweep's neighbour wait timed out (device status)     */
+#define RTS_E_NOT_BUILT (-6)   /* no device code for the current GPU                       */
+
+typedef enum { RTS_FP64 = 0, RTS_FP32 = 1 } rts_precision;
+/* Vertical boundaries (x and y are always periodic). */
+typedef enum { RTS_BOT_THERMAL = 0 /* I = S */, RTS_BOT_FIXED = 1 /* I = i_bot */ } rts_bot_bc;
+typedef enum { RTS_TOP_ZERO = 0 /* I = 0 */, RTS_TOP_THERMAL = 1 /* I = S */ } rts_top_bc;
+/* Operations for rts_workspace_bytes. */
+typedef enum { RTS_OP_SOLVE = 0, RTS_OP_ADJOINT = 1 } rts_op;
+
+typedef struct {
+  int32_t nx, ny, nz; /* >= 2 each; nx, ny <= 1024 */
+  double dx, dy, dz;  /* > 0 */
+} rts_grid;
+
+/* One box (one independent problem).  Paper: rays per octant, bands, boundary
+ * iteration count and the radiative heating output ("Summary of the Radiation
+ * Transport Solver"). */
+typedef struct {
+  rts_grid g;
+  int32_t nbands;         /* >= 1 */
+  int32_t nrays;          /* >= 1, <= 64 */
+  const double* mu;       /* HOST [nrays][3]: unit direction vectors, mu_z != 0 */
+  const double* w;        /* HOST [nrays]: quadrature weights, J = sum_r w_r I_r */
+  const double* qweight;  /* HOST [nbands] or NULL (all 1): weight of band b in Q */
+  int32_t bot;            /* rts_bot_bc, boundary of rays with mu_z > 0 (layer k = 0) */
+  int32_t top;            /* rts_top_bc, boundary of rays with mu_z < 0 (layer k = nz-1) */
+  double i_bot;           /* intensity for RTS_BOT_FIXED */
+  int32_t n_iter;         /* >= 1: sweeps of rays whose dominant axis is x or y */
+  int32_t prec;           /* rts_precision */
+} rts_desc;
+
+typedef struct {
+  const void* kappa; /* [nbands][N] opacity per unit mass */
+  const void* rho;   /* [N] density */
+  const void* S;     /* [nbands][N] source function */
+} rts_inputs;
+
+typedef struct {
+  double* Q;   /* [N] radiative heating, always written */
+  void* J;     /* [nbands][N] mean intensity, or NULL */
+  void* I_top; /* [nbands][n_up][ny][nx] intensity of the top layer for the n_up rays with
+                  mu_z > 0 (in ray order), or NULL */
+} rts_outputs;
+
+/* Adjoint seeds: L = <gQ, Q> + <gJ, J> + <gItop, I_top>; any may be NULL. */
+typedef struct {
+  const double* gQ;  /* [N] */
+  const void* gJ;    /* [nbands][N] */
+  const void* gItop; /* [nbands][n_up][ny][nx] */
+} rts_seeds;
+
+/* Adjoint results, overwritten: dL/dS_b and dL/dchi_b (chi_b = kappa_b * rho).
+ * The caller applies dL/dkappa_b = rho dL/dchi_b, dL/drho = sum_b kappa_b dL/dchi_b. */
+typedef struct {
+  void* dS;   /* [nbands][N] */
+  void* dchi; /* [nbands][N] */
+} rts_grads;
+
+/* Schedule knobs (chosen by the plan; settable for tuning). */
+typedef struct {
+  int32_t rows_per_strip; /* rows of the sweep plane per workgroup: 2, 4, 6 or 8 */
+  int32_t max_workgroups; /* 0 = as many as are co-resident */
+  int32_t order;          /* 0: longest sweeps first, 1: input order */
+  int32_t use_graph;      /* 1: rts_solve_batched replays a captured hipGraph */
+} rts_schedule;
+
+/* Create a plan for `nbox` boxes (host only; validates every field; the
+ * descs and their host arrays may be freed afterwards).  All boxes of one plan
+ * share `prec`.  On success *out receives the plan. */
+int rts_plan_create(const rts_desc* descs, int32_t nbox, void** out);
+
+/* Bytes of device workspace needed by `op` (rts_op) on this plan. */
+int rts_workspace_bytes(void* plan, int32_t op, size_t* bytes);
+
+/* Forward solve of box 0 of the plan (paper: the RTS call of one time step). */
+int rts_solve(void* plan, const rts_inputs* in, const rts_outputs* out, void* ws,
+              size_t ws_bytes, void* hip_stream);
+
+/* Forward solve of all `nbox` boxes (nbox must equal the plan's box count):
+ * every band, ray and box in one persistent sweep launch fed by a device-side
+ * work queue; captured once into a hipGraph and replayed when the schedule's
+ * use_graph is set. */
+int rts_solve_batched(void* plan, int32_t nbox, const rts_inputs* in, const rts_outputs* out,
+                      void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Reverse-mode gradients of L (rts_seeds) w.r.t. S and chi for every box of
+ * the plan; `in`, `g`, `d` point to arrays of nbox entries. */
+int rts_adjoint(void* plan, int32_t nbox, const rts_inputs* in, const rts_seeds* g,
+                const rts_grads* d, void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Synchronise `hip_stream` and read the device status word left in `ws` by
+ * the last call: RTS_OK, or RTS_E_DEADLOCK if a neighbour wait timed out. */
+int rts_check_status(void* plan, const void* ws, void* hip_stream);
+
+int rts_plan_get_schedule(void* plan, rts_schedule* s);
+int rts_plan_set_schedule(void* plan, const rts_schedule* s);
+
+/* Device-side timing of the last call's sweep kernel (ms), recorded with HIP
+ * events on the call's stream when timing is enabled; -1 if unavailable. */
+int rts_plan_enable_timing(void* plan, int32_t on);
+int rts_plan_last_timing(void* plan, double* sweep_ms, double* total_ms);
+
+/* In-bounds lane-layout check of the DPP whole-wave shifts the sweep relies
+ * on, for one wave: out[i] = in[i-1] (out[0] = -1) and out[64+i] = in[i+1]
+ * (out[127] = -2).  `in` holds 64 floats, `out` 128 (device pointers). */
+int rts_selftest_dpp(const float* in, float* out, void* hip_stream);
+
+void rts_plan_destroy(void* plan);
+const char* rts_status_string(int status);
+const char* rts_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTS_H */

@@ -1,0 +1,718 @@
+// Host side of librts: the C ABI declared in include/rts.h.
+//
+// Validates the problem statement, turns every box's rays into sweep tasks
+// (rays grouped by dominant axis and direction, at most four per task, as the
+// paper's ray groups of "a similar dependency pattern"), lays out the caller's
+// workspace, and enqueues prep -> sweep -> reduce on the caller's stream
+// (optionally as one replayed hipGraph).  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/rts.h"
+#include "rts_internal.h"
+
+namespace rts {
+// kernels (rts_kernels.hip)
+template <class Real>
+hipError_t launch_prep(const void*, const void*, const void*, void*, int64_t, int64_t, int64_t,
+                       int, int, int, int, hipStream_t);
+hipError_t launch_zero(int*, int64_t, hipStream_t);
+template <class Real, int H>
+size_t sweep_lds_bytes(int threads);
+template <class Real, int H, bool UNI>
+const void* sweep_fn();
+template <class Real, int H, bool UNI>
+hipError_t launch_sweep_h(const SweepArgs&, int, int, hipStream_t);
+template <class Real>
+hipError_t launch_reduce(const char*, const Task*, const BoxGeo&, const BoxPtrs&, hipStream_t);
+hipError_t launch_dpp_selftest(const float*, float*, hipStream_t);
+}  // namespace rts
+
+using namespace rts;
+
+namespace {
+
+thread_local std::string g_last_hip;
+
+int hip_fail(hipError_t e, const char* where) {
+  g_last_hip = std::string(where) + ": " + hipGetErrorString(e);
+  return RTS_E_HIP;
+}
+
+#define RTS_HIP(call)                              \
+  do {                                             \
+    hipError_t _e = (call);                        \
+    if (_e != hipSuccess) return hip_fail(_e, #call); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct RayGeo {
+  int axis, sa;
+  double ds;
+  double mu[3];
+};
+
+// Dominant axis: the one reached first along the ray (smallest delta/|mu|);
+// ties prefer z, then y, then x.
+RayGeo ray_geo(const rts_grid& g, const double* m) {
+  const double d[3] = {g.dx, g.dy, g.dz};
+  RayGeo r;
+  r.axis = -1;
+  r.ds = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    r.mu[a] = m[a];
+    if (m[a] == 0.0) continue;
+    const double s = d[a] / std::fabs(m[a]);
+    if (s <= r.ds) { r.ds = s; r.axis = a; }
+  }
+  r.sa = m[r.axis] > 0 ? 1 : -1;
+  return r;
+}
+
+struct Box {
+  rts_desc d;
+  std::vector<double> mu, w, qw;
+  int64_t N = 0;
+  int n_up = 0;
+  int tasks_per_band = 0;
+  std::vector<std::array<int, 4>> groups;  // ray index per slot (-1 unused), same for every band
+  int64_t chi_off = 0, chiT_off = 0, sT_off = 0;  // Real-element offsets
+};
+
+struct Plan {
+  std::vector<Box> boxes;
+  int prec = RTS_FP64;
+  size_t esz = 8;
+  rts_schedule sched{4, 0, 0, 0};
+  // layout (bytes)
+  size_t off_flags = 0, off_tasks = 0, off_queue = 0, off_data = 0, total = 0;
+  std::vector<Task> tasks;
+  std::vector<int32_t> queue;
+  int total_strips = 0;
+  int threads = 64;
+  bool uni = true;  // every task's four slots share f1, f2, ds and w
+  // device-dependent state, filled on first use
+  bool dev_ready = false;
+  int device = -1, cus = 0, occupancy_blocks = 0;
+  int64_t timeout_ticks = 0;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  std::vector<void*> old_pinned;
+  const void* uploaded_ws = nullptr;
+  // graph cache
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<const void*> gkey;
+  // timing
+  bool timing = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool ev_valid = false;
+};
+
+bool finite(double v) { return std::isfinite(v); }
+
+int validate_desc(const rts_desc& d) {
+  const rts_grid& g = d.g;
+  if (g.nx < 2 || g.ny < 2 || g.nz < 2) return RTS_E_ARG;
+  if (!(g.dx > 0) || !(g.dy > 0) || !(g.dz > 0) || !finite(g.dx) || !finite(g.dy) ||
+      !finite(g.dz))
+    return RTS_E_ARG;
+  if (d.nbands < 1 || d.nrays < 1 || !d.mu || !d.w) return RTS_E_ARG;
+  if (d.n_iter < 1) return RTS_E_ARG;
+  if (d.bot != RTS_BOT_THERMAL && d.bot != RTS_BOT_FIXED) return RTS_E_ARG;
+  if (d.top != RTS_TOP_ZERO && d.top != RTS_TOP_THERMAL) return RTS_E_ARG;
+  if (d.prec != RTS_FP64 && d.prec != RTS_FP32) return RTS_E_ARG;
+  if (!finite(d.i_bot)) return RTS_E_ARG;
+  for (int r = 0; r < d.nrays; ++r) {
+    const double* m = d.mu + 3 * r;
+    if (!finite(m[0]) || !finite(m[1]) || !finite(m[2]) || !finite(d.w[r])) return RTS_E_ARG;
+    const double n2 = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+    if (std::fabs(n2 - 1.0) > 1e-6) return RTS_E_ARG;
+    if (m[2] == 0.0) return RTS_E_ARG;
+  }
+  if (d.qweight)
+    for (int b = 0; b < d.nbands; ++b)
+      if (!finite(d.qweight[b])) return RTS_E_ARG;
+  if (d.nbands > 16 || d.nrays > 64) return RTS_E_UNSUPPORTED;
+  if (g.nx > kMaxCols || g.ny > kMaxCols) return RTS_E_UNSUPPORTED;
+  if ((int64_t)g.nx * g.ny * g.nz > ((int64_t)1 << 31)) return RTS_E_UNSUPPORTED;
+  return RTS_OK;
+}
+
+// Build every task of every box and the workspace layout for the current schedule.
+void build_layout(Plan& P) {
+  P.tasks.clear();
+  P.queue.clear();
+  const int H = P.sched.rows_per_strip;
+  const size_t esz = P.esz;
+  size_t off = align_up(sizeof(WsHeader));
+  // first pass: count tasks and strips
+  struct Pending { int box, band, g; };
+  std::vector<Pending> order;
+  for (size_t b = 0; b < P.boxes.size(); ++b)
+    for (int band = 0; band < P.boxes[b].d.nbands; ++band)
+      for (int g = 0; g < P.boxes[b].tasks_per_band; ++g) order.push_back({(int)b, band, g});
+  P.tasks.resize(order.size());
+  int max_cols = 1;
+  // data region offsets computed after headers
+  for (size_t t = 0; t < order.size(); ++t) {
+    const Box& B = P.boxes[order[t].box];
+    const rts_desc& d = B.d;
+    const int nx = d.g.nx, ny = d.g.ny, nz = d.g.nz;
+    const std::array<int, 4>& slots = B.groups[order[t].g];
+    int first_ray = -1;
+    for (int k = 0; k < 4; ++k)
+      if (slots[k] >= 0) { first_ray = slots[k]; break; }
+    RayGeo g0 = ray_geo(d.g, &B.mu[3 * first_ray]);
+    Task T;
+    std::memset(&T, 0, sizeof(T));
+    T.box = order[t].box;
+    T.band = order[t].band;
+    T.sa = g0.sa;
+    T.nrays = 0;
+    if (g0.axis == 2) {
+      T.n_planes = nz; T.n_rows = ny; T.n_cols = nx;
+      T.plane_stride = (int64_t)nx * ny; T.row_stride = nx;
+      T.z_planes = 1; T.row_periodic = 1; T.laps = 1; T.transposed = 0;
+      T.it_top = nz - 1; T.itp = 0; T.itr = nx; T.itc = 1;
+    } else if (g0.axis == 1) {
+      T.n_planes = ny; T.n_rows = nz; T.n_cols = nx;
+      T.plane_stride = nx; T.row_stride = (int64_t)nx * ny;
+      T.z_planes = 0; T.row_periodic = 0; T.laps = d.n_iter; T.transposed = 0;
+      T.it_top = nz - 1; T.itp = nx; T.itr = 0; T.itc = 1;
+    } else {
+      T.n_planes = nx; T.n_rows = nz; T.n_cols = ny;
+      T.plane_stride = (int64_t)nz * ny; T.row_stride = ny;
+      T.z_planes = 0; T.row_periodic = 0; T.laps = d.n_iter; T.transposed = 1;
+      T.it_top = nz - 1; T.itp = 1; T.itr = 0; T.itc = nx;
+    }
+    // boundary values D = I - S = a S + b of the bottom (thermal: 0; fixed:
+    // i_bot - S) and top (zero: -S; thermal: 0) layers
+    const double bot_a = d.bot == RTS_BOT_THERMAL ? 0.0 : -1.0;
+    const double bot_b = d.bot == RTS_BOT_THERMAL ? 0.0 : d.i_bot;
+    const double top_a = d.top == RTS_TOP_ZERO ? -1.0 : 0.0, top_b = 0.0;
+    if (T.z_planes) {
+      T.pl_a = T.sa > 0 ? bot_a : top_a;
+      T.pl_b = T.sa > 0 ? bot_b : top_b;
+    }
+    T.bu_a = bot_a; T.bu_b = bot_b; T.bd_a = top_a; T.bd_b = top_b;
+    const int col_axis = g0.axis == 0 ? 1 : 0;
+    const int row_axis = g0.axis == 2 ? 1 : 2;
+    const double dd[3] = {d.g.dx, d.g.dy, d.g.dz};
+    std::vector<int> up_index(d.nrays, -1);
+    for (int r = 0, u = 0; r < d.nrays; ++r)
+      if (B.mu[3 * r + 2] > 0) up_index[r] = u++;
+    bool uni = true;
+    for (int k = 0; k < 4; ++k) {
+      TaskRay& y = T.ray[k];
+      const int r = slots[k];
+      y.ray = r;
+      if (r < 0) {  // unused slot: contributes nothing
+        y.f1 = y.f2 = y.hds = y.w = 0.0;
+        y.itop = -1;
+        uni = false;
+        continue;
+      }
+      ++T.nrays;
+      RayGeo g = ray_geo(d.g, &B.mu[3 * r]);
+      y.f1 = g.ds * std::fabs(g.mu[col_axis]) / dd[col_axis];
+      y.f2 = g.ds * std::fabs(g.mu[row_axis]) / dd[row_axis];
+      y.hds = 0.5 * g.ds;
+      y.w = B.w[r];
+      y.itop = up_index[r];
+    }
+    for (int k = 1; k < 4 && uni; ++k)
+      uni = T.ray[k].f1 == T.ray[0].f1 && T.ray[k].f2 == T.ray[0].f2 &&
+            T.ray[k].hds == T.ray[0].hds && T.ray[k].w == T.ray[0].w;
+    T.uni = uni ? 1 : 0;
+    T.it_ray = (int64_t)nx * ny;
+    T.it_off = (int64_t)T.band * B.n_up * nx * ny;
+    T.rows_per_strip = std::min(H, T.n_rows);
+    T.strips = (T.n_rows + T.rows_per_strip - 1) / T.rows_per_strip;
+    max_cols = std::max(max_cols, T.n_cols);
+    P.tasks[t] = T;
+  }
+  // queue order: longest sweeps (most plane steps x cells) first, stable
+  std::vector<int> q(P.tasks.size());
+  for (size_t i = 0; i < q.size(); ++i) q[i] = (int)i;
+  if (P.sched.order == 0) {
+    std::stable_sort(q.begin(), q.end(), [&](int a, int b) {
+      const Task& A = P.tasks[a];
+      const Task& Bt = P.tasks[b];
+      const int64_t sa = (int64_t)A.laps * A.n_planes, sb = (int64_t)Bt.laps * Bt.n_planes;
+      if (sa != sb) return sa > sb;
+      return (int64_t)A.n_rows * A.n_cols > (int64_t)Bt.n_rows * Bt.n_cols;
+    });
+  }
+  int ticket = 0;
+  for (int i : q) {
+    P.tasks[i].ticket0 = ticket;
+    P.queue.push_back(ticket);
+    P.queue.push_back(i);
+    ticket += P.tasks[i].strips;
+  }
+  P.total_strips = ticket;
+  P.threads = ((max_cols + 63) / 64) * 64;
+  P.uni = true;
+  for (const Task& T : P.tasks) P.uni = P.uni && T.uni;
+
+  // layout
+  P.off_flags = off;
+  off = align_up(off + sizeof(int32_t) * (size_t)std::max(1, P.total_strips));
+  P.off_tasks = off;
+  off = align_up(off + sizeof(Task) * P.tasks.size());
+  P.off_queue = off;
+  off = align_up(off + sizeof(int32_t) * P.queue.size());
+  P.off_data = off;
+  for (Box& B : P.boxes) {
+    const size_t arr = (size_t)B.d.nbands * B.N * esz;
+    B.chi_off = (int64_t)(off / esz); off = align_up(off + arr);
+    B.chiT_off = (int64_t)(off / esz); off = align_up(off + arr);
+    B.sT_off = (int64_t)(off / esz); off = align_up(off + arr);
+  }
+  for (Task& T : P.tasks) {
+    const Box& B = P.boxes[T.box];
+    const int64_t bandN = (int64_t)T.band * B.N;
+    if (T.transposed) {
+      T.chi_off = B.chiT_off + bandN;
+      T.s_off = B.sT_off + bandN;
+    } else {
+      T.chi_off = B.chi_off + bandN;
+      T.s_off = bandN;  // into the caller's S
+    }
+    T.part_off = (int64_t)(off / esz);
+    off = align_up(off + (size_t)B.N * esz);
+  }
+  for (Task& T : P.tasks) {
+    T.xbuf_off = (int64_t)(off / esz);
+    off = align_up(off + (size_t)T.strips * 2 * 2 * kMaxRaysPerTask * T.n_cols * esz);
+  }
+  int fl = 0;
+  for (int i : q) {
+    P.tasks[i].flag_off = (int64_t)(P.off_flags / sizeof(int32_t)) + fl;
+    fl += P.tasks[i].strips;
+  }
+  P.total = off;
+  P.uploaded_ws = nullptr;
+  if (P.gexec) {
+    (void)hipGraphExecDestroy(P.gexec);
+    P.gexec = nullptr;
+  }
+}
+
+int dev_init(Plan& P) {
+  int dev = 0;
+  RTS_HIP(hipGetDevice(&dev));
+  if (P.dev_ready && dev == P.device) return RTS_OK;
+  hipDeviceProp_t prop;
+  RTS_HIP(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    g_last_hip = std::string("device is ") + prop.gcnArchName + ", library built for gfx950";
+    return RTS_E_NOT_BUILT;
+  }
+  P.device = dev;
+  P.cus = prop.multiProcessorCount;
+  int clk_khz = 0;
+  if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+      clk_khz <= 0)
+    clk_khz = 100000;
+  P.timeout_ticks = (int64_t)clk_khz * 1000 * 5;  // 5 s
+  P.dev_ready = true;
+  return RTS_OK;
+}
+
+template <class Real, int H>
+int occupancy_h(Plan& P) {
+  int nb = 0;
+  const void* fn = P.uni ? sweep_fn<Real, H, true>() : sweep_fn<Real, H, false>();
+  RTS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, P.threads,
+                                                       sweep_lds_bytes<Real, H>(P.threads)));
+  P.occupancy_blocks = nb;
+  return RTS_OK;
+}
+
+template <class Real>
+int occupancy(Plan& P) {
+  switch (P.sched.rows_per_strip) {
+    case 2: return occupancy_h<Real, 2>(P);
+    case 4: return occupancy_h<Real, 4>(P);
+    case 6: if (sizeof(Real) == 4) return occupancy_h<float, 6>(P); break;
+    case 8: if (sizeof(Real) == 4) return occupancy_h<float, 8>(P); break;
+  }
+  return RTS_E_UNSUPPORTED;
+}
+
+template <class Real, bool UNI>
+hipError_t launch_sweep_u(Plan& P, const SweepArgs& a, int grid, hipStream_t st) {
+  switch (P.sched.rows_per_strip) {
+    case 2: return launch_sweep_h<Real, 2, UNI>(a, grid, P.threads, st);
+    case 4: return launch_sweep_h<Real, 4, UNI>(a, grid, P.threads, st);
+    case 6: if (sizeof(Real) == 4) return launch_sweep_h<float, 6, UNI>(a, grid, P.threads, st); break;
+    case 8: if (sizeof(Real) == 4) return launch_sweep_h<float, 8, UNI>(a, grid, P.threads, st); break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class Real>
+hipError_t launch_sweep(Plan& P, const SweepArgs& a, int grid, hipStream_t st) {
+  return P.uni ? launch_sweep_u<Real, true>(P, a, grid, st) : launch_sweep_u<Real, false>(P, a, grid, st);
+}
+
+int ensure_pinned(Plan& P) {
+  const size_t bytes = (P.off_data - P.off_tasks);
+  if (P.pinned && P.pinned_bytes >= bytes) return RTS_OK;
+  if (P.pinned) P.old_pinned.push_back(P.pinned);
+  P.pinned = nullptr;
+  RTS_HIP(hipHostMalloc(&P.pinned, bytes, hipHostMallocDefault));
+  P.pinned_bytes = bytes;
+  std::memset(P.pinned, 0, bytes);
+  std::memcpy(P.pinned, P.tasks.data(), sizeof(Task) * P.tasks.size());
+  std::memcpy((char*)P.pinned + (P.off_queue - P.off_tasks), P.queue.data(),
+              sizeof(int32_t) * P.queue.size());
+  return RTS_OK;
+}
+
+// Enqueue one forward solve of all boxes of the plan.
+template <class Real>
+int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char* ws,
+                    hipStream_t st, bool timed) {
+  // header + flags to zero
+  RTS_HIP(launch_zero(reinterpret_cast<int*>(ws),
+                      (int64_t)((P.off_tasks) / sizeof(int32_t)), st));
+  if (P.uploaded_ws != ws) {
+    RTS_HIP(hipMemcpyAsync(ws + P.off_tasks, P.pinned, P.off_data - P.off_tasks,
+                           hipMemcpyHostToDevice, st));
+    P.uploaded_ws = ws;
+  }
+  for (size_t b = 0; b < P.boxes.size(); ++b) {
+    const Box& B = P.boxes[b];
+    RTS_HIP(launch_prep<Real>(in[b].kappa, in[b].rho, in[b].S, ws, B.chi_off, B.chiT_off,
+                              B.sT_off, B.d.g.nx, B.d.g.ny, B.d.g.nz, B.d.nbands, st));
+  }
+  SweepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.ws = ws;
+  a.tasks = reinterpret_cast<const Task*>(ws + P.off_tasks);
+  a.queue = reinterpret_cast<const int32_t*>(ws + P.off_queue);
+  a.ntasks = (int)P.tasks.size();
+  a.total_strips = P.total_strips;
+  a.timeout_ticks = P.timeout_ticks;
+  for (size_t b = 0; b < P.boxes.size(); ++b)
+    a.box[b] = BoxPtrs{in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top};
+  int grid = P.occupancy_blocks * P.cus;
+  if (P.sched.max_workgroups > 0) grid = std::min(grid, (int)P.sched.max_workgroups);
+  grid = std::max(1, std::min(grid, P.total_strips));
+  if (timed) RTS_HIP(hipEventRecord(P.ev[1], st));
+  RTS_HIP(launch_sweep<Real>(P, a, grid, st));
+  if (timed) RTS_HIP(hipEventRecord(P.ev[2], st));
+  for (size_t b = 0; b < P.boxes.size(); ++b) {
+    const Box& B = P.boxes[b];
+    BoxGeo G;
+    std::memset(&G, 0, sizeof(G));
+    G.nx = B.d.g.nx; G.ny = B.d.g.ny; G.nz = B.d.g.nz; G.nbands = B.d.nbands;
+    G.n_up = B.n_up;
+    G.tasks_per_band = B.tasks_per_band;
+    int first = 0;
+    for (size_t t = 0; t < P.tasks.size(); ++t)
+      if (P.tasks[t].box == (int)b) { first = (int)t; break; }
+    G.task0 = first;
+    for (int k = 0; k < B.d.nbands; ++k) G.qweight[k] = B.qw[k];
+    RTS_HIP(launch_reduce<Real>(ws, reinterpret_cast<const Task*>(ws + P.off_tasks), G,
+                                a.box[b], st));
+  }
+  return RTS_OK;
+}
+
+int check_call(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, void* ws,
+               size_t ws_bytes) {
+  if (!P || !in || !out) return RTS_E_ARG;
+  if (nbox != (int)P->boxes.size()) return RTS_E_ARG;
+  for (int b = 0; b < nbox; ++b) {
+    if (!in[b].kappa || !in[b].rho || !in[b].S || !out[b].Q) return RTS_E_ARG;
+  }
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 || ws_bytes < P->total)
+    return RTS_E_WORKSPACE;
+  return RTS_OK;
+}
+
+int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, void* ws,
+               size_t ws_bytes, void* stream, bool allow_graph) {
+  int rc = check_call(P, nbox, in, out, ws, ws_bytes);
+  if (rc) return rc;
+  if ((rc = dev_init(*P))) return rc;
+  if (P->occupancy_blocks == 0) {
+    rc = P->prec == RTS_FP32 ? occupancy<float>(*P) : occupancy<double>(*P);
+    if (rc) return rc;
+    if (P->occupancy_blocks < 1) {
+      g_last_hip = "sweep kernel cannot be resident (occupancy 0)";
+      return RTS_E_UNSUPPORTED;
+    }
+  }
+  if ((rc = ensure_pinned(*P))) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const bool graph = allow_graph && P->sched.use_graph;
+  const bool timed = P->timing && !graph;
+  if (timed) {
+    for (int i = 0; i < 4; ++i)
+      if (!P->ev[i]) RTS_HIP(hipEventCreate(&P->ev[i]));
+    RTS_HIP(hipEventRecord(P->ev[0], st));
+  }
+  if (!graph) {
+    rc = P->prec == RTS_FP32 ? enqueue_forward<float>(*P, in, out, (char*)ws, st, timed)
+                             : enqueue_forward<double>(*P, in, out, (char*)ws, st, timed);
+    if (rc) return rc;
+    if (timed) {
+      RTS_HIP(hipEventRecord(P->ev[3], st));
+      P->ev_valid = true;
+    }
+    return RTS_OK;
+  }
+  // graph path: key on every pointer the captured work uses
+  std::vector<const void*> key{ws};
+  for (int b = 0; b < nbox; ++b) {
+    key.insert(key.end(), {in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top});
+  }
+  if (!P->gexec || key != P->gkey) {
+    if (P->gexec) {
+      (void)hipGraphExecDestroy(P->gexec);
+      P->gexec = nullptr;
+    }
+    if (!P->cap_stream) RTS_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    // make sure the task table is resident before capture (the capture re-uploads it)
+    P->uploaded_ws = nullptr;
+    RTS_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = P->prec == RTS_FP32 ? enqueue_forward<float>(*P, in, out, (char*)ws, P->cap_stream, false)
+                             : enqueue_forward<double>(*P, in, out, (char*)ws, P->cap_stream, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    P->gkey = key;
+  }
+  RTS_HIP(hipGraphLaunch(P->gexec, st));
+  return RTS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rts_plan_create(const rts_desc* descs, int32_t nbox, void** out) {
+  if (!out) return RTS_E_ARG;
+  *out = nullptr;
+  if (!descs || nbox < 1) return RTS_E_ARG;
+  if (nbox > kMaxBoxes) return RTS_E_UNSUPPORTED;
+  try {
+    for (int b = 0; b < nbox; ++b) {
+      int rc = validate_desc(descs[b]);
+      if (rc) return rc;
+      if (descs[b].prec != descs[0].prec) return RTS_E_ARG;
+    }
+    Plan* P = new Plan();
+    P->prec = descs[0].prec;
+    P->esz = P->prec == RTS_FP32 ? 4 : 8;
+    P->sched.rows_per_strip = P->prec == RTS_FP32 ? 4 : 2;
+    for (int b = 0; b < nbox; ++b) {
+      Box B;
+      B.d = descs[b];
+      B.mu.assign(descs[b].mu, descs[b].mu + 3 * descs[b].nrays);
+      B.w.assign(descs[b].w, descs[b].w + descs[b].nrays);
+      B.qw.assign(descs[b].nbands, 1.0);
+      if (descs[b].qweight) B.qw.assign(descs[b].qweight, descs[b].qweight + descs[b].nbands);
+      B.d.mu = nullptr; B.d.w = nullptr; B.d.qweight = nullptr;
+      B.N = (int64_t)B.d.g.nx * B.d.g.ny * B.d.g.nz;
+      for (int r = 0; r < B.d.nrays; ++r) B.n_up += B.mu[3 * r + 2] > 0;
+      // group rays by (dominant axis, direction) in ray order; inside a group a
+      // ray takes the slot of its in-plane signs (slot = 2 [col sign < 0] +
+      // [row sign < 0]), opening a new task when that slot is taken
+      std::map<std::pair<int, int>, std::vector<std::array<int, 4>>> grp;
+      std::vector<std::pair<int, int>> keys;
+      for (int r = 0; r < B.d.nrays; ++r) {
+        RayGeo g = ray_geo(B.d.g, &B.mu[3 * r]);
+        auto k = std::make_pair(g.axis, g.sa);
+        if (!grp.count(k)) keys.push_back(k);
+        const int col_axis = g.axis == 0 ? 1 : 0;
+        const int row_axis = g.axis == 2 ? 1 : 2;
+        const int slot = (g.mu[col_axis] < 0 ? 2 : 0) + (g.mu[row_axis] < 0 ? 1 : 0);
+        auto& tl = grp[k];
+        bool placed = false;
+        for (auto& a : tl)
+          if (a[slot] < 0) { a[slot] = r; placed = true; break; }
+        if (!placed) {
+          std::array<int, 4> a{-1, -1, -1, -1};
+          a[slot] = r;
+          tl.push_back(a);
+        }
+      }
+      for (auto& k : keys)
+        for (auto& a : grp[k]) B.groups.push_back(a);
+      B.tasks_per_band = (int)B.groups.size();
+      P->boxes.push_back(std::move(B));
+    }
+    build_layout(*P);
+    *out = P;
+    return RTS_OK;
+  } catch (...) {
+    return RTS_E_ARG;
+  }
+}
+
+int rts_workspace_bytes(void* plan, int32_t op, size_t* bytes) {
+  if (!plan || !bytes) return RTS_E_ARG;
+  Plan* P = static_cast<Plan*>(plan);
+  if (op == RTS_OP_SOLVE) {
+    *bytes = P->total;
+    return RTS_OK;
+  }
+  if (op == RTS_OP_ADJOINT) return RTS_E_UNSUPPORTED;
+  return RTS_E_ARG;
+}
+
+int rts_solve(void* plan, const rts_inputs* in, const rts_outputs* out, void* ws, size_t ws_bytes,
+              void* hip_stream) {
+  if (!plan) return RTS_E_ARG;
+  Plan* P = static_cast<Plan*>(plan);
+  if (P->boxes.size() != 1) return RTS_E_ARG;
+  try {
+    return solve_impl(P, 1, in, out, ws, ws_bytes, hip_stream, false);
+  } catch (...) {
+    return RTS_E_HIP;
+  }
+}
+
+int rts_solve_batched(void* plan, int32_t nbox, const rts_inputs* in, const rts_outputs* out,
+                      void* ws, size_t ws_bytes, void* hip_stream) {
+  if (!plan) return RTS_E_ARG;
+  try {
+    return solve_impl(static_cast<Plan*>(plan), nbox, in, out, ws, ws_bytes, hip_stream, true);
+  } catch (...) {
+    return RTS_E_HIP;
+  }
+}
+
+int rts_adjoint(void* plan, int32_t nbox, const rts_inputs* in, const rts_seeds* g,
+                const rts_grads* d, void* ws, size_t ws_bytes, void* hip_stream) {
+  (void)nbox; (void)in; (void)g; (void)d; (void)ws; (void)ws_bytes; (void)hip_stream;
+  if (!plan) return RTS_E_ARG;
+  return RTS_E_UNSUPPORTED;
+}
+
+int rts_check_status(void* plan, const void* ws, void* hip_stream) {
+  if (!plan || !ws) return RTS_E_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  RTS_HIP(hipStreamSynchronize(st));
+  int32_t s = 0;
+  RTS_HIP(hipMemcpy(&s, ws, sizeof(s), hipMemcpyDeviceToHost));
+  return s ? RTS_E_DEADLOCK : RTS_OK;
+}
+
+int rts_plan_get_schedule(void* plan, rts_schedule* s) {
+  if (!plan || !s) return RTS_E_ARG;
+  *s = static_cast<Plan*>(plan)->sched;
+  return RTS_OK;
+}
+
+int rts_plan_set_schedule(void* plan, const rts_schedule* s) {
+  if (!plan || !s) return RTS_E_ARG;
+  Plan* P = static_cast<Plan*>(plan);
+  const int h = s->rows_per_strip;
+  const bool ok = P->prec == RTS_FP32 ? (h == 2 || h == 4 || h == 6 || h == 8) : (h == 2 || h == 4);
+  if (!ok || s->max_workgroups < 0 || (s->order != 0 && s->order != 1)) return RTS_E_ARG;
+  try {
+    P->sched = *s;
+    P->occupancy_blocks = 0;
+    if (P->pinned) {
+      P->old_pinned.push_back(P->pinned);
+      P->pinned = nullptr;
+      P->pinned_bytes = 0;
+    }
+    build_layout(*P);
+  } catch (...) {
+    return RTS_E_ARG;
+  }
+  return RTS_OK;
+}
+
+int rts_plan_enable_timing(void* plan, int32_t on) {
+  if (!plan) return RTS_E_ARG;
+  static_cast<Plan*>(plan)->timing = on != 0;
+  return RTS_OK;
+}
+
+int rts_plan_last_timing(void* plan, double* sweep_ms, double* total_ms) {
+  if (!plan || !sweep_ms || !total_ms) return RTS_E_ARG;
+  Plan* P = static_cast<Plan*>(plan);
+  *sweep_ms = -1;
+  *total_ms = -1;
+  if (!P->ev_valid) return RTS_OK;
+  float a = 0, b = 0;
+  RTS_HIP(hipEventSynchronize(P->ev[3]));
+  RTS_HIP(hipEventElapsedTime(&a, P->ev[1], P->ev[2]));
+  RTS_HIP(hipEventElapsedTime(&b, P->ev[0], P->ev[3]));
+  *sweep_ms = a;
+  *total_ms = b;
+  return RTS_OK;
+}
+
+void rts_plan_destroy(void* plan) {
+  if (!plan) return;
+  Plan* P = static_cast<Plan*>(plan);
+  if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+  if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+  for (auto& e : P->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (P->pinned) (void)hipHostFree(P->pinned);
+  for (void* p : P->old_pinned) (void)hipHostFree(p);
+  delete P;
+}
+
+const char* rts_status_string(int status) {
+  switch (status) {
+    case RTS_OK: return "RTS_OK";
+    case RTS_E_ARG: return "RTS_E_ARG: invalid argument";
+    case RTS_E_UNSUPPORTED: return "RTS_E_UNSUPPORTED: not supported by this build";
+    case RTS_E_WORKSPACE: return "RTS_E_WORKSPACE: workspace null, misaligned or too small";
+    case RTS_E_HIP: {
+      static thread_local std::string s;
+      s = "RTS_E_HIP: " + g_last_hip;
+      return s.c_str();
+    }
+    case RTS_E_DEADLOCK: return "RTS_E_DEADLOCK: a sweep neighbour wait timed out";
+    case RTS_E_NOT_BUILT: {
+      static thread_local std::string s;
+      s = "RTS_E_NOT_BUILT: " + g_last_hip;
+      return s.c_str();
+    }
+  }
+  return "unknown status";
+}
+
+const char* rts_version(void) { return "librts 0.1 (gfx950)"; }
+
+// In-bounds lane-layout check of the DPP whole-wave shifts used by the sweep:
+// in and out are device arrays of 64 and 128 floats.
+int rts_selftest_dpp(const float* in, float* out, void* hip_stream) {
+  if (!in || !out) return RTS_E_ARG;
+  RTS_HIP(launch_dpp_selftest(in, out, reinterpret_cast<hipStream_t>(hip_stream)));
+  return RTS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Internal structures shared by the host planner (rts_host.cpp) and the gfx950
+// kernels (rts_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+
+namespace rts {
+
+constexpr int kMaxRaysPerTask = 4;
+constexpr int kMaxBoxes = 16;
+constexpr int kMaxCols = 1024;  // one thread per column of the sweep plane
+
+// One ray slot inside a sweep task.  "cols" is the contiguous in-plane axis
+// (always periodic), "rows" the other in-plane axis.  Slot k's upwind column
+// is c-1 for k < 2 (else c+1) and its upwind row i-1 for even k (else i+1);
+// an unused slot has w = 0, f1 = f2 = 0, ds = 0, itop = -1.
+struct TaskRay {
+  double f1, f2;   // upwind fractions along cols and rows
+  double hds;      // ds / 2
+  double w;        // quadrature weight
+  int32_t itop;    // index among rays with mu_z > 0, or -1
+  int32_t ray;     // input ray index, or -1 for an unused slot
+};
+
+// One sweep task: up to four rays of one band of one box that share the
+// dominant axis and its direction.  The task is split into strips of rows;
+// each strip is processed by one workgroup that marches through the planes.
+struct Task {
+  int32_t box, band;
+  int32_t n_planes, n_rows, n_cols;
+  int32_t sa;              // +1 / -1 along the plane axis
+  int32_t laps;            // sweeps over the plane axis (1 when planes are z)
+  int32_t z_planes;        // planes are z: the first plane is the boundary layer
+  int32_t row_periodic;    // rows wrap (planes are z) or end at boundaries (rows are z)
+  int32_t nrays;
+  int32_t rows_per_strip, strips;
+  int32_t ticket0;         // first queue ticket of this task
+  int32_t transposed;      // chi/S read from the [x][z][y] copies
+  int32_t it_top;          // plane (z_planes) or row (otherwise) of the top layer
+  int32_t uni;             // all four slots share f1, f2, ds and w
+  int64_t plane_stride, row_stride;  // element strides of the view (col stride 1)
+  int64_t chi_off;         // element offset of this band's chi view in the workspace
+  int64_t s_off;           // element offset of S: into the box's S (natural) or workspace
+  int64_t part_off;        // element offset of the partial sum array in the workspace
+  int64_t xbuf_off;        // element offset of the neighbour exchange buffer
+  int64_t flag_off;        // int offset of the strip flags
+  int64_t it_off;          // element offset of this band's I_top block in the box I_top
+  int64_t itp, itr, itc;   // I_top strides for (plane, row, col)
+  int64_t it_ray;          // I_top stride between up rays (ny * nx)
+  double pl_a, pl_b;       // boundary-plane value D = pl_a * S + pl_b (z_planes)
+  double bu_a, bu_b;       // boundary row 0 of even slots (rows are z, mu_z > 0)
+  double bd_a, bd_b;       // boundary row n_rows-1 of odd slots (rows are z, mu_z < 0)
+  TaskRay ray[kMaxRaysPerTask];
+};
+
+struct BoxPtrs {
+  const void* kappa;
+  const void* rho;
+  const void* S;
+  double* Q;
+  void* J;
+  void* I_top;
+};
+
+// Per-box geometry for the prep and reduce kernels.
+struct BoxGeo {
+  int32_t nx, ny, nz, nbands;
+  int32_t task0;           // first task of this box (tasks of a box are contiguous, band-major)
+  int32_t tasks_per_band;
+  int32_t n_up;
+  int32_t pad;
+  int64_t chi_off;         // workspace element offset of chi [nbands][N]
+  int64_t chiT_off;        // chi^T [nbands][nx][nz][ny]
+  int64_t sT_off;          // S^T   [nbands][nx][nz][ny]
+  double qweight[16];
+};
+
+// Workspace header (first 256 bytes).
+struct WsHeader {
+  int32_t status;          // 0, or 1 after a neighbour-wait timeout
+  int32_t ticket;          // work-queue counter
+  int32_t pad[62];
+};
+
+struct SweepArgs {
+  char* ws;                // workspace base
+  const Task* tasks;       // in the workspace
+  const int32_t* queue;    // [ntasks][2]: (first ticket, task index), ascending tickets
+  int32_t ntasks;
+  int32_t total_strips;
+  int64_t timeout_ticks;   // s_memrealtime ticks before a wait gives up
+  BoxPtrs box[kMaxBoxes];
+};
+
+}  // namespace rts

@@ -1,0 +1,265 @@
+"""ctypes binding of librts (include/rts.h): argument marshalling only.
+
+Every step of the solve runs in the gfx950 kernels of `librts.so`; this
+module converts problem descriptions into the C structs, passes device
+pointers of torch tensors and the current HIP stream, and turns non-zero
+status codes into exceptions.  There is no fallback: if the library is not
+built, importing works but every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librts.so")
+
+RTS_OK = 0
+RTS_E_ARG = -1
+RTS_E_UNSUPPORTED = -2
+RTS_E_WORKSPACE = -3
+RTS_E_HIP = -4
+RTS_E_DEADLOCK = -5
+RTS_E_NOT_BUILT = -6
+RTS_FP64 = 0
+RTS_FP32 = 1
+RTS_OP_SOLVE = 0
+RTS_OP_ADJOINT = 1
+
+# every symbol declared in include/rts.h
+SYMBOLS = ("rts_plan_create", "rts_workspace_bytes", "rts_solve", "rts_solve_batched",
+           "rts_adjoint", "rts_check_status", "rts_plan_get_schedule", "rts_plan_set_schedule",
+           "rts_plan_enable_timing", "rts_plan_last_timing", "rts_selftest_dpp",
+           "rts_plan_destroy", "rts_status_string", "rts_version")
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("g", Grid), ("nbands", ctypes.c_int32), ("nrays", ctypes.c_int32),
+                ("mu", ctypes.POINTER(ctypes.c_double)), ("w", ctypes.POINTER(ctypes.c_double)),
+                ("qweight", ctypes.POINTER(ctypes.c_double)), ("bot", ctypes.c_int32),
+                ("top", ctypes.c_int32), ("i_bot", ctypes.c_double), ("n_iter", ctypes.c_int32),
+                ("prec", ctypes.c_int32)]
+
+
+class Inputs(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("S", ctypes.c_void_p)]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("Q", ctypes.c_void_p), ("J", ctypes.c_void_p), ("I_top", ctypes.c_void_p)]
+
+
+class Seeds(ctypes.Structure):
+    _fields_ = [("gQ", ctypes.c_void_p), ("gJ", ctypes.c_void_p), ("gItop", ctypes.c_void_p)]
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [("dS", ctypes.c_void_p), ("dchi", ctypes.c_void_p)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("rows_per_strip", ctypes.c_int32), ("max_workgroups", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class RTSError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)}")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded librts (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"librts.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        L.rts_plan_create.argtypes = [ctypes.POINTER(Desc), i32, ctypes.POINTER(vp)]
+        L.rts_workspace_bytes.argtypes = [vp, i32, ctypes.POINTER(sz)]
+        L.rts_solve.argtypes = [vp, ctypes.POINTER(Inputs), ctypes.POINTER(Outputs), vp, sz, vp]
+        L.rts_solve_batched.argtypes = [vp, i32, ctypes.POINTER(Inputs), ctypes.POINTER(Outputs),
+                                        vp, sz, vp]
+        L.rts_adjoint.argtypes = [vp, i32, ctypes.POINTER(Inputs), ctypes.POINTER(Seeds),
+                                  ctypes.POINTER(Grads), vp, sz, vp]
+        L.rts_check_status.argtypes = [vp, vp, vp]
+        L.rts_plan_get_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
+        L.rts_plan_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
+        L.rts_plan_enable_timing.argtypes = [vp, i32]
+        L.rts_plan_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]
+        L.rts_selftest_dpp.argtypes = [vp, vp, vp]
+        L.rts_plan_destroy.argtypes = [vp]
+        L.rts_plan_destroy.restype = None
+        L.rts_status_string.argtypes = [ctypes.c_int]
+        L.rts_status_string.restype = ctypes.c_char_p
+        L.rts_version.argtypes = []
+        L.rts_version.restype = ctypes.c_char_p
+        for f in ("rts_plan_create", "rts_workspace_bytes", "rts_solve", "rts_solve_batched",
+                  "rts_adjoint", "rts_check_status", "rts_plan_get_schedule",
+                  "rts_plan_set_schedule", "rts_plan_enable_timing", "rts_plan_last_timing",
+                  "rts_selftest_dpp"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().rts_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str):
+    if status != RTS_OK:
+        raise RTSError(status, where)
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A librts plan for one or more boxes (paper_2107_08145_amd.inputs.Problem)."""
+
+    def __init__(self, problems, prec: int = RTS_FP64):
+        if not isinstance(problems, (list, tuple)):
+            problems = [problems]
+        self.problems = list(problems)
+        self.prec = prec
+        self._keep = []
+        descs = (Desc * len(problems))()
+        for i, p in enumerate(problems):
+            mu = np.ascontiguousarray(p.mu, dtype=np.float64)
+            w = np.ascontiguousarray(p.w, dtype=np.float64)
+            qw = np.ascontiguousarray(p.qweight, dtype=np.float64)
+            self._keep += [mu, w, qw]
+            d = descs[i]
+            d.g = Grid(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz)
+            d.nbands, d.nrays = p.nbands, p.nrays
+            d.mu = mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            d.w = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            d.qweight = qw.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            d.bot, d.top, d.i_bot, d.n_iter, d.prec = p.bot, p.top, p.i_bot, p.n_iter, prec
+        h = ctypes.c_void_p()
+        _check(lib().rts_plan_create(descs, len(problems), ctypes.byref(h)), "rts_plan_create")
+        self.handle = h
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rts_plan_destroy(h)
+            self.handle = None
+
+    def workspace_bytes(self, op: int = RTS_OP_SOLVE) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().rts_workspace_bytes(self.handle, op, ctypes.byref(n)), "rts_workspace_bytes")
+        return n.value
+
+    def schedule(self) -> dict:
+        s = Schedule()
+        _check(lib().rts_plan_get_schedule(self.handle, ctypes.byref(s)), "rts_plan_get_schedule")
+        return {k: getattr(s, k) for k, _ in Schedule._fields_}
+
+    def set_schedule(self, **kw):
+        cur = self.schedule()
+        cur.update(kw)
+        s = Schedule(**cur)
+        _check(lib().rts_plan_set_schedule(self.handle, ctypes.byref(s)), "rts_plan_set_schedule")
+        self._ws = None
+
+    def enable_timing(self, on: bool = True):
+        _check(lib().rts_plan_enable_timing(self.handle, 1 if on else 0), "rts_plan_enable_timing")
+
+    def last_timing(self):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib().rts_plan_last_timing(self.handle, ctypes.byref(a), ctypes.byref(b)),
+               "rts_plan_last_timing")
+        return a.value, b.value
+
+    def workspace(self, op: int = RTS_OP_SOLVE):
+        import torch
+        need = self.workspace_bytes(op)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        return base + off, self._ws.numel() - off
+
+    # -- device arrays -------------------------------------------------------
+    @property
+    def dtype(self):
+        import torch
+        return torch.float32 if self.prec == RTS_FP32 else torch.float64
+
+    def device_inputs(self, p):
+        import torch
+        dt = self.dtype
+        return (torch.as_tensor(np.ascontiguousarray(p.kappa)).to("cuda", dt).contiguous(),
+                torch.as_tensor(np.ascontiguousarray(p.rho)).to("cuda", dt).contiguous(),
+                torch.as_tensor(np.ascontiguousarray(p.S)).to("cuda", dt).contiguous())
+
+    def new_outputs(self, p, want_j=True, want_itop=True):
+        import torch
+        Q = torch.empty((p.nz, p.ny, p.nx), dtype=torch.float64, device="cuda")
+        J = torch.empty((p.nbands, p.nz, p.ny, p.nx), dtype=self.dtype, device="cuda") if want_j else None
+        It = (torch.empty((p.nbands, p.n_up, p.ny, p.nx), dtype=self.dtype, device="cuda")
+              if want_itop else None)
+        return Q, J, It
+
+    def solve_into(self, ins, outs, stream=None, batched=False):
+        """Enqueue a forward solve.  ins: [(kappa, rho, S)] per box; outs: [(Q, J, I_top)]."""
+        n = len(ins)
+        ci = (Inputs * n)()
+        co = (Outputs * n)()
+        for i, ((k, r, s), (q, j, it)) in enumerate(zip(ins, outs)):
+            ci[i] = Inputs(k.data_ptr(), r.data_ptr(), s.data_ptr())
+            co[i] = Outputs(q.data_ptr(), j.data_ptr() if j is not None else None,
+                            it.data_ptr() if it is not None else None)
+        ws, nbytes = self.workspace()
+        st = _stream_ptr(stream)
+        if batched:
+            rc = lib().rts_solve_batched(self.handle, n, ci, co, ctypes.c_void_p(ws), nbytes, st)
+        else:
+            rc = lib().rts_solve(self.handle, ci, co, ctypes.c_void_p(ws), nbytes, st)
+        _check(rc, "rts_solve_batched" if batched else "rts_solve")
+
+    def check_status(self, stream=None):
+        ws, _ = self.workspace()
+        _check(lib().rts_check_status(self.handle, ctypes.c_void_p(ws), _stream_ptr(stream)),
+               "rts_check_status")
+
+
+def solve(p, prec: int = RTS_FP64, plan: Plan | None = None):
+    """Forward solve of one problem on the current GPU; returns numpy (Q, J, I_top)."""
+    import torch
+    plan = plan or Plan(p, prec)
+    ins = plan.device_inputs(p)
+    outs = plan.new_outputs(p)
+    plan.solve_into([ins], [outs])
+    plan.check_status()
+    torch.cuda.synchronize()
+    return tuple(o.double().cpu().numpy() for o in outs)
+
+
+def selftest_dpp():
+    """Lane layout of the DPP whole-wave shifts (see rts.h)."""
+    import torch
+    x = torch.arange(64, dtype=torch.float32, device="cuda")
+    out = torch.empty(128, dtype=torch.float32, device="cuda")
+    _check(lib().rts_selftest_dpp(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  _stream_ptr()), "rts_selftest_dpp")
+    torch.cuda.synchronize()
+    return out.cpu().numpy()

@@ -1,0 +1,122 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/rts.h, and rejects invalid problems before any launch."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2107_08145_amd import inputs, rts
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "rts.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rts_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = rts.lib()
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(rts.SYMBOLS)
+
+
+def test_version_and_status_strings():
+    L = rts.lib()
+    assert b"gfx950" in L.rts_version()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert rts.status_string(code)
+    assert rts.status_string(-3).startswith("RTS_E_WORKSPACE")
+
+
+def _desc_problem(**kw):
+    p = inputs.workload("grey32", size=8)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 1), ("ny", 0), ("nz", 1), ("dx", 0.0), ("dz", -1.0), ("dy", float("nan")),
+    ("n_iter", 0), ("bot", 2), ("top", -1), ("i_bot", float("inf")),
+])
+def test_plan_rejects_bad_fields(field, value):
+    p = _desc_problem(**{field: value})
+    with pytest.raises(rts.RTSError) as e:
+        rts.Plan(p)
+    assert e.value.status == rts.RTS_E_ARG
+
+
+def test_plan_rejects_bad_directions():
+    p = _desc_problem()
+    mu = p.mu.copy()
+    mu[3] = [1.0, 0.0, 0.0]                 # mu_z == 0: no vertical boundary
+    with pytest.raises(rts.RTSError):
+        rts.Plan(_desc_problem(mu=mu))
+    mu = p.mu.copy()
+    mu[0] *= 1.01                           # not a unit vector
+    with pytest.raises(rts.RTSError):
+        rts.Plan(_desc_problem(mu=mu))
+
+
+def test_plan_unsupported_sizes_and_precision():
+    with pytest.raises(rts.RTSError) as e:
+        rts.Plan(_desc_problem(nx=1025))
+    assert e.value.status == rts.RTS_E_UNSUPPORTED
+    with pytest.raises(rts.RTSError) as e:
+        rts.Plan(_desc_problem(), prec=7)
+    assert e.value.status == rts.RTS_E_ARG
+
+
+def test_null_arguments():
+    L = rts.lib()
+    h = ctypes.c_void_p()
+    assert L.rts_plan_create(None, 1, ctypes.byref(h)) == rts.RTS_E_ARG
+    assert L.rts_workspace_bytes(None, 0, None) == rts.RTS_E_ARG
+    assert L.rts_solve(None, None, None, None, 0, None) == rts.RTS_E_ARG
+    pl = rts.Plan(_desc_problem())
+    n = ctypes.c_size_t()
+    assert L.rts_workspace_bytes(pl.handle, 9, ctypes.byref(n)) == rts.RTS_E_ARG
+    # calls with missing inputs or workspace are rejected before any HIP call
+    ci, co = rts.Inputs(), rts.Outputs()
+    assert L.rts_solve(pl.handle, ctypes.byref(ci), ctypes.byref(co), None, 0, None) == rts.RTS_E_ARG
+    ci = rts.Inputs(16, 16, 16)
+    co = rts.Outputs(16, None, None)
+    assert L.rts_solve(pl.handle, ctypes.byref(ci), ctypes.byref(co), None, 0, None) == rts.RTS_E_WORKSPACE
+    assert L.rts_solve(pl.handle, ctypes.byref(ci), ctypes.byref(co), ctypes.c_void_p(256 * 3 + 8),
+                       1 << 40, None) == rts.RTS_E_WORKSPACE          # misaligned
+    assert L.rts_solve(pl.handle, ctypes.byref(ci), ctypes.byref(co), ctypes.c_void_p(256 * 4),
+                       16, None) == rts.RTS_E_WORKSPACE               # too small
+    assert L.rts_solve_batched(pl.handle, 2, ctypes.byref(ci), ctypes.byref(co),
+                               ctypes.c_void_p(256), 1 << 40, None) == rts.RTS_E_ARG
+
+
+def test_workspace_and_schedule():
+    p = inputs.workload("grey32", size=16)
+    pl = rts.Plan(p, rts.RTS_FP32)
+    n0 = pl.workspace_bytes()
+    N = p.ncells
+    assert n0 >= 4 * N * (3 + 6)            # chi, chi^T, S^T and six partial sums
+    s = pl.schedule()
+    assert s["rows_per_strip"] in (2, 4, 6, 8)
+    pl.set_schedule(rows_per_strip=8)
+    assert pl.schedule()["rows_per_strip"] == 8
+    with pytest.raises(rts.RTSError):
+        pl.set_schedule(rows_per_strip=3)
+    p64 = rts.Plan(p, rts.RTS_FP64)
+    with pytest.raises(rts.RTSError):
+        p64.set_schedule(rows_per_strip=8)  # fp64 strips hold at most 4 rows
+    assert p64.workspace_bytes() > n0
+
+
+def test_adjoint_workspace_query():
+    pl = rts.Plan(_desc_problem())
+    n = ctypes.c_size_t()
+    rc = rts.lib().rts_workspace_bytes(pl.handle, rts.RTS_OP_ADJOINT, ctypes.byref(n))
+    assert rc in (rts.RTS_OK, rts.RTS_E_UNSUPPORTED)

@@ -1,0 +1,188 @@
+"""GPU parity: librts (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (derived from the arithmetic):
+* FP64 path vs oracle.  The library sweeps D = I - S, the oracle I; both
+  round at ~1e-16 per operation.  J and I_top agree to a few 1e-15 relative.
+  Q = 4 pi chi (J - S): the oracle forms J - S by subtraction, which loses
+  up to 1e-16 * S absolutely, so the per-cell bound is
+  |dQ| <= 1e-9 |Q| + 4 pi chi S * 1e-13.
+* FP32 path vs oracle on the same (FP32-rounded) inputs: D is carried in
+  FP32 (6e-8 per operation, transcendental ops ~1 ulp), accumulated with a
+  compensated sum and reduced in FP64; we require max|dQ|/max|Q| <= 2e-5 and
+  J, I_top within 2e-6 relative of max.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2107_08145_amd import inputs, rts
+
+pytestmark = pytest.mark.gpu
+
+
+def _cfg(name, **kw):
+    return kw
+
+
+def _rand_problem(nx, ny, nz, seed, bands=1, lo=1e-2, hi=1e2, h_rho=8.0, **kw):
+    r = np.random.default_rng(seed)
+    kap = 10 ** r.uniform(math.log10(lo), math.log10(hi), (bands, nz, ny, nx))
+    z = np.arange(nz, dtype=np.float64)
+    rho = np.broadcast_to(np.exp(-z / h_rho)[:, None, None], (nz, ny, nx)).copy()
+    S = (1 + 2 * np.exp(-z / 10))[None, :, None, None] ** 4 * np.exp(0.1 * r.standard_normal((bands, nz, ny, nx)))
+    mu, w = inputs.s4_quadrature()
+    p = inputs.Problem(nx, ny, nz, 1.0, 1.0, 1.0, mu, w, kap, rho, S, np.ones(bands))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _check64(p, got, ref):
+    Qg, Jg, Ig = got
+    Qo, Jo, Io = ref
+    chi = oracle.chi_of(p)
+    floor = 4 * math.pi * (np.abs(chi) * np.abs(p.S)).max(axis=0) * 1e-13
+    assert np.all(np.abs(Qg - Qo) <= 1e-9 * np.abs(Qo) + floor), np.abs(Qg - Qo).max()
+    assert np.abs(Jg - Jo).max() <= 1e-13 * np.abs(Jo).max()
+    assert np.abs(Ig - Io).max() <= 1e-13 * max(np.abs(Io).max(), 1e-300)
+
+
+def _check32(p32, got, ref, q_tol=2e-5, j_tol=2e-6):
+    Qg, Jg, Ig = got
+    Qo, Jo, Io = ref
+    eq = np.abs(Qg - Qo).max() / np.abs(Qo).max()
+    ej = np.abs(Jg - Jo).max() / np.abs(Jo).max()
+    ei = np.abs(Ig - Io).max() / max(np.abs(Io).max(), 1e-300)
+    assert eq <= q_tol and ej <= j_tol and ei <= j_tol, (eq, ej, ei)
+    return eq, ej, ei
+
+
+def test_dpp_lane_layout():
+    out = rts.selftest_dpp()
+    assert out[0] == -1.0
+    assert np.array_equal(out[1:64], np.arange(0, 63, dtype=np.float32))
+    assert np.array_equal(out[64:127], np.arange(1, 64, dtype=np.float32))
+    assert out[127] == -2.0
+
+
+def test_grey32_fp64_matches_oracle():
+    p = inputs.workload("grey32")
+    print("case grey32 fp64", flush=True)
+    got = rts.solve(p, rts.RTS_FP64)
+    _check64(p, got, oracle.solve(p, threads=8))
+
+
+def test_grey32_fp32_matches_oracle():
+    p = inputs.workload("grey32").astype(np.float32)
+    print("case grey32 fp32", flush=True)
+    got = rts.solve(p, rts.RTS_FP32)
+    eq, ej, ei = _check32(p, got, oracle.solve(p.astype(np.float64), threads=8))
+    print(f"grey32 fp32: Q {eq:.2e} J {ej:.2e} I_top {ei:.2e}")
+
+
+@pytest.mark.parametrize("shape", [(20, 13, 11), (130, 70, 9), (64, 7, 33), (2, 3, 2), (65, 64, 17)])
+def test_ragged_shapes_fp64(shape):
+    nx, ny, nz = shape
+    p = _rand_problem(nx, ny, nz, seed=nx * 7 + ny)
+    print("case ragged", shape, flush=True)
+    _check64(p, rts.solve(p, rts.RTS_FP64), oracle.solve(p, threads=8))
+
+
+@pytest.mark.parametrize("shape", [(20, 13, 11), (130, 70, 9), (97, 33, 40)])
+def test_ragged_shapes_fp32(shape):
+    nx, ny, nz = shape
+    p = _rand_problem(nx, ny, nz, seed=nx * 11 + nz).astype(np.float32)
+    print("case ragged fp32", shape, flush=True)
+    _check32(p, rts.solve(p, rts.RTS_FP32), oracle.solve(p.astype(np.float64), threads=8))
+
+
+@pytest.mark.parametrize("bc", [(1, 1, 1.7, 3), (0, 1, 0.0, 1), (1, 0, 0.3, 4)])
+def test_boundary_variants_and_iterations(bc):
+    bot, top, ib, nit = bc
+    p = _rand_problem(24, 20, 14, seed=5, bot=bot, top=top, i_bot=ib, n_iter=nit)
+    print("case bc", bc, flush=True)
+    _check64(p, rts.solve(p, rts.RTS_FP64), oracle.solve(p, threads=8))
+
+
+def test_general_directions_nonuniform_path():
+    # dx = dy = 3 dz: every S4 ray is z-dominant with its own fractions, so
+    # tasks are not uniform; plus two random directions leave slots unused
+    p = _rand_problem(18, 16, 12, seed=9)
+    p.dx = p.dy = 3.0
+    r = np.random.default_rng(3)
+    extra = r.standard_normal((2, 3))
+    extra /= np.linalg.norm(extra, axis=1, keepdims=True)
+    p.mu = np.vstack([p.mu, extra])
+    p.w = np.concatenate([p.w * 0.9, [0.05, 0.05]])
+    print("case general directions", flush=True)
+    _check64(p, rts.solve(p, rts.RTS_FP64), oracle.solve(p, threads=8))
+    p32 = p.astype(np.float32)
+    _check32(p32, rts.solve(p32, rts.RTS_FP32), oracle.solve(p32.astype(np.float64), threads=8))
+
+
+def test_multiband_qweight():
+    p = _rand_problem(26, 22, 15, seed=21, bands=3)
+    p.qweight = np.array([1.0, 0.25, 0.0])
+    print("case multiband", flush=True)
+    _check64(p, rts.solve(p, rts.RTS_FP64), oracle.solve(p, threads=8))
+
+
+def test_isothermal_exact_on_gpu():
+    p = _rand_problem(40, 36, 30, seed=2, lo=1e-3, hi=1e3)
+    p.S = np.full_like(p.S, 2.5)
+    p.top = inputs.TOP_THERMAL
+    Q, J, I = rts.solve(p, rts.RTS_FP64)
+    assert np.abs(J - 2.5).max() < 1e-13 and np.abs(I - 2.5).max() < 1e-13
+    Q, J, I = rts.solve(p.astype(np.float32), rts.RTS_FP32)
+    assert np.abs(J - 2.5).max() < 1e-5
+
+
+def test_schedules_are_bitwise_identical():
+    p = _rand_problem(70, 40, 37, seed=4).astype(np.float32)
+    ref = None
+    for h in (2, 4, 6, 8):
+        pl = rts.Plan(p, rts.RTS_FP32)
+        pl.set_schedule(rows_per_strip=h)
+        got = rts.solve(p, rts.RTS_FP32, plan=pl)
+        if ref is None:
+            ref = got
+        else:
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), h
+    pl = rts.Plan(p, rts.RTS_FP32)
+    pl.set_schedule(max_workgroups=7, order=1)
+    got = rts.solve(p, rts.RTS_FP32, plan=pl)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+
+def test_fp64_schedules_bitwise_and_repeatable():
+    p = _rand_problem(33, 30, 19, seed=8)
+    pl = rts.Plan(p, rts.RTS_FP64)
+    a = rts.solve(p, rts.RTS_FP64, plan=pl)
+    b = rts.solve(p, rts.RTS_FP64, plan=pl)
+    pl.set_schedule(rows_per_strip=4)
+    c = rts.solve(p, rts.RTS_FP64, plan=pl)
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+def test_batched_equals_single():
+    import torch
+    ps = [_rand_problem(40, 24, 18, seed=31, bands=2), _rand_problem(17, 33, 21, seed=32, bands=2)]
+    ps = [p.astype(np.float32) for p in ps]
+    pl = rts.Plan(ps, rts.RTS_FP32)
+    ins = [pl.device_inputs(p) for p in ps]
+    outs = [pl.new_outputs(p) for p in ps]
+    for use_graph in (0, 1):
+        pl.set_schedule(use_graph=use_graph)
+        for rep in range(3):
+            pl.solve_into(ins, outs, batched=True)
+            pl.check_status()
+            torch.cuda.synchronize()
+            for p, o in zip(ps, outs):
+                single = rts.solve(p, rts.RTS_FP32)
+                for a, b in zip(o, single):
+                    assert np.array_equal(a.double().cpu().numpy(), b), (use_graph, rep)
