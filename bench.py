@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark of the short-characteristics RTS on one MI355X.
+
+Workload (default): 288^3 grid, four opacity bins plus the grey band (5
+band sweeps), 24 rays (S4, three per octant), periodic x/y with 3 boundary
+iterations, FP32 sweep with compensated partial sums and FP64 final
+reduction; seeded synthetic stratified atmosphere.  A step is one complete
+rts_solve: chi preparation, every sweep of every band and ray, and the final
+reduction, with inputs already resident in HBM.
+
+Prints one JSON line.  `value` is nominal cell-ray-band updates per second
+(N * rays * bands per step).  `roofline` describes the sweep kernel, timed
+with HIP events on its own stream inside the timed region.  `cpu_baseline`
+times the FP64 oracle on the grey band of the same workload (full grid, all
+rays) on this host's cores.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (published)
+PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector (published)
+FLOPS_PER_UPDATE = 32          # algorithmic FP operations of one D-form update
+
+
+def sweep_model(p, plan_sched_tasks, esz):
+    """Executed updates and algorithmic bytes of one sweep launch."""
+    N = p.ncells
+    executed = 0
+    nbytes = 0
+    for laps, nrays in plan_sched_tasks:
+        executed += N * nrays * laps
+        nbytes += laps * N * 2 * esz + N * esz   # chi and S per lap, one partial write
+    return executed, nbytes
+
+
+def task_list(p):
+    """(laps, rays) of every sweep task of problem p: rays grouped by dominant
+    axis and direction, four per task (equal spacing: 6 tasks per band)."""
+    tasks = []
+    d = (p.dx, p.dy, p.dz)
+    groups = {}
+    for m in p.mu:
+        s = [d[a] / abs(m[a]) if m[a] != 0 else math.inf for a in range(3)]
+        ax = max(a for a in range(3) if s[a] == min(s))
+        groups.setdefault((ax, m[ax] > 0), []).append(m)
+    for (ax, _), rays in groups.items():
+        for i in range(0, len(rays), 4):
+            tasks.append((1 if ax == 2 else p.n_iter, len(rays[i:i + 4])))
+    return tasks * p.nbands
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("rts_kernels.hip", "rts_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2107_08145_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    f = os.path.join(ROOT, "profiles", f"rts_sweep_{workload}_pmc.json")
+    if not os.path.exists(f):
+        return None
+    try:
+        d = json.load(open(f))
+    except ValueError:
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(p_full, seconds_hint=True):
+    import oracle
+    from paper_2107_08145_amd import inputs
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = max(1, min(16, cores))
+    b = p_full.nbands - 1  # the grey band
+    q = inputs.Problem(p_full.nx, p_full.ny, p_full.nz, p_full.dx, p_full.dy, p_full.dz,
+                       p_full.mu, p_full.w, p_full.kappa[b:b + 1].astype(np.float64),
+                       p_full.rho.astype(np.float64), p_full.S[b:b + 1].astype(np.float64),
+                       np.ones(1), p_full.bot, p_full.top, p_full.i_bot, p_full.n_iter)
+    oracle._load()
+    t0 = time.perf_counter()
+    oracle.solve(q, threads=threads)
+    dt = time.perf_counter() - t0
+    nominal = q.ncells * q.nrays
+    return {"value": nominal / dt, "unit": "cell-ray-band updates/s", "cores": threads,
+            "kind": "oracle", "seconds": round(dt, 2),
+            "sample": f"FP64 oracle, grey band of the workload: {q.nx}x{q.ny}x{q.nz}, "
+                      f"{q.nrays} rays, n_iter {q.n_iter}, one band (of {p_full.nbands})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="bands288", choices=["bands288", "grey288"])
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--size", type=int, default=None, help="cube edge override (debug)")
+    ap.add_argument("--rows", type=int, default=0, help="rows per strip (0: plan default)")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2107_08145_amd import inputs, rts
+
+    t_gen = time.perf_counter()
+    p = inputs.workload(args.workload, size=args.size)
+    prec = rts.RTS_FP32 if args.prec == "fp32" else rts.RTS_FP64
+    dt_np = np.float32 if prec == rts.RTS_FP32 else np.float64
+    pd = p.astype(dt_np)
+    print(f"# inputs generated in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    plan = rts.Plan(pd, prec)
+    if args.rows:
+        plan.set_schedule(rows_per_strip=args.rows)
+    ins = plan.device_inputs(pd)
+    outs = plan.new_outputs(pd)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        plan.solve_into([ins], [outs])
+    plan.check_status()
+    torch.cuda.synchronize()
+    print("# warmup done", file=sys.stderr, flush=True)
+
+    plan.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.solve_into([ins], [outs])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sweep_ms, call_ms = plan.last_timing()
+    plan.enable_timing(False)
+    plan.check_status()
+    ms = (t1 - t0) * 1e3 / args.steps
+
+    N = p.ncells
+    nominal = N * p.nrays * p.nbands
+    esz = 4 if prec == rts.RTS_FP32 else 8
+    executed, alg_bytes = sweep_model(p, task_list(p), esz)
+    sw_s = sweep_ms * 1e-3
+    gbs = alg_bytes / sw_s / 1e9
+    tflops = executed * FLOPS_PER_UPDATE / sw_s / 1e12
+    peak_alu = PEAK_FP32_TFLOPS if prec == rts.RTS_FP32 else PEAK_FP64_TFLOPS
+    traffic = traffic_from_profile(args.workload) if args.size is None else None
+    if tflops / peak_alu >= gbs / PEAK_HBM_GBS:
+        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": peak_alu, "unit": "TFLOP/s",
+                "frac": round(tflops / peak_alu, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    roof["traffic"] = traffic
+    roof["kernel"] = "rts_sweep"
+    roof["kernel_ms"] = round(sweep_ms, 4)
+    roof["alg_bytes_per_launch"] = alg_bytes
+    roof["alg_GBs"] = round(gbs, 1)
+    roof["alg_TFLOPs"] = round(tflops, 3)
+    roof["executed_updates_per_launch"] = executed
+
+    cfg = {"workload": f"{args.workload}: {p.nx}x{p.ny}x{p.nz}, {p.nbands} bands "
+                       f"({'4 opacity bins + grey' if p.nbands == 5 else 'grey'}), "
+                       f"{p.nrays} rays S4, n_iter {p.n_iter}, seeded stratified atmosphere",
+           "grid": [p.nx, p.ny, p.nz], "bands": p.nbands, "rays": p.nrays, "n_iter": p.n_iter,
+           "schedule": plan.schedule(), "sweep_ms": round(sweep_ms, 4),
+           "call_ms": round(call_ms, 4), "executed_updates_per_s": executed / (ms * 1e-3)}
+    out = {"metric": "cell-ray-band updates/sec (288^3 4-band+grey 24-ray RTS)",
+           "value": nominal / (ms * 1e-3), "unit": "cell-ray-band updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if prec == rts.RTS_FP32 else "f64", "data": "synthetic",
+           "config": cfg, "roofline": roof}
+    if not args.no_cpu and args.size is None:
+        print("# cpu baseline (oracle)...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

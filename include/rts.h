@@ -117,7 +117,8 @@ typedef struct {
 /* Schedule knobs (chosen by the plan; settable for tuning). */
 typedef struct {
   int32_t rows_per_strip; /* rows of the sweep plane per workgroup: 2, 4, 6 or 8 */
-  int32_t max_workgroups; /* 0 = as many as are co-resident */
+  int32_t max_workgroups; /* 0 = as many as are co-resident; never fewer than the strips of
+                             the largest task (they must all be resident together) */
   int32_t order;          /* 0: longest sweeps first, 1: input order */
   int32_t use_graph;      /* 1: rts_solve_batched replays a captured hipGraph */
 } rts_schedule;
@@ -153,8 +154,12 @@ int rts_check_status(void* plan, const void* ws, void* hip_stream);
 int rts_plan_get_schedule(void* plan, rts_schedule* s);
 int rts_plan_set_schedule(void* plan, const rts_schedule* s);
 
-/* Device-side timing of the last call's sweep kernel (ms), recorded with HIP
- * events on the call's stream when timing is enabled; -1 if unavailable. */
+/* Device-side timing.  While enabled, each rts_solve / rts_solve_batched call
+ * (not graph replays) records HIP events on its stream around the sweep kernel
+ * and around the whole call (up to 512 calls).  rts_plan_last_timing waits for
+ * the last recorded call and returns the mean sweep-kernel and whole-call
+ * durations in ms over the calls recorded since timing was (re)enabled, or -1
+ * if none.  Enabling resets the record. */
 int rts_plan_enable_timing(void* plan, int32_t on);
 int rts_plan_last_timing(void* plan, double* sweep_ms, double* total_ms);
 

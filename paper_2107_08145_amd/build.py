@@ -10,6 +10,8 @@ OUT = os.path.join(HERE, "librts.so")
 SOURCES = ["rts_kernels.hip", "rts_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+         # every fused multiply-add is explicit in the source
+         "-ffp-contract=off",
          # no packed FP32 instructions in any device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]

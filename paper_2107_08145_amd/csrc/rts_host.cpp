@@ -56,6 +56,7 @@ int hip_fail(hipError_t e, const char* where) {
   } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxTimed = 512;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct RayGeo {
@@ -101,6 +102,7 @@ struct Plan {
   std::vector<Task> tasks;
   std::vector<int32_t> queue;
   int total_strips = 0;
+  int max_strips = 1;  // strips of the largest task
   int threads = 64;
   bool uni = true;  // every task's four slots share f1, f2, ds and w
   // device-dependent state, filled on first use
@@ -115,10 +117,10 @@ struct Plan {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<const void*> gkey;
-  // timing
+  // timing: events of up to kMaxTimed calls (call start, sweep start, sweep end, call end)
   bool timing = false;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  bool ev_valid = false;
+  std::vector<std::array<hipEvent_t, 4>> ev;
+  int ev_used = 0;
 };
 
 bool finite(double v) { return std::isfinite(v); }
@@ -264,6 +266,8 @@ void build_layout(Plan& P) {
     ticket += P.tasks[i].strips;
   }
   P.total_strips = ticket;
+  P.max_strips = 1;
+  for (const Task& T : P.tasks) P.max_strips = std::max(P.max_strips, (int)T.strips);
   P.threads = ((max_cols + 63) / 64) * 64;
   P.uni = true;
   for (const Task& T : P.tasks) P.uni = P.uni && T.uni;
@@ -387,7 +391,7 @@ int ensure_pinned(Plan& P) {
 // Enqueue one forward solve of all boxes of the plan.
 template <class Real>
 int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char* ws,
-                    hipStream_t st, bool timed) {
+                    hipStream_t st, hipEvent_t* ev) {
   // header + flags to zero
   RTS_HIP(launch_zero(reinterpret_cast<int*>(ws),
                       (int64_t)((P.off_tasks) / sizeof(int32_t)), st));
@@ -411,12 +415,16 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
   a.timeout_ticks = P.timeout_ticks;
   for (size_t b = 0; b < P.boxes.size(); ++b)
     a.box[b] = BoxPtrs{in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top};
+  // Every strip of a task must be resident together (neighbouring strips wait
+  // on each other), so the grid never drops below the largest task's strip
+  // count; tickets are claimed in order, hence with that many resident
+  // workgroups the tasks being worked on always make progress.
   int grid = P.occupancy_blocks * P.cus;
-  if (P.sched.max_workgroups > 0) grid = std::min(grid, (int)P.sched.max_workgroups);
+  if (P.sched.max_workgroups > 0) grid = std::min(grid, std::max((int)P.sched.max_workgroups, P.max_strips));
   grid = std::max(1, std::min(grid, P.total_strips));
-  if (timed) RTS_HIP(hipEventRecord(P.ev[1], st));
+  if (ev) RTS_HIP(hipEventRecord(ev[1], st));
   RTS_HIP(launch_sweep<Real>(P, a, grid, st));
-  if (timed) RTS_HIP(hipEventRecord(P.ev[2], st));
+  if (ev) RTS_HIP(hipEventRecord(ev[2], st));
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     const Box& B = P.boxes[b];
     BoxGeo G;
@@ -455,27 +463,31 @@ int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
   if (P->occupancy_blocks == 0) {
     rc = P->prec == RTS_FP32 ? occupancy<float>(*P) : occupancy<double>(*P);
     if (rc) return rc;
-    if (P->occupancy_blocks < 1) {
-      g_last_hip = "sweep kernel cannot be resident (occupancy 0)";
+    if (P->occupancy_blocks < 1 || P->occupancy_blocks * P->cus < P->max_strips) {
+      g_last_hip = "the strips of one sweep task cannot all be resident; use more rows per strip";
       return RTS_E_UNSUPPORTED;
     }
   }
   if ((rc = ensure_pinned(*P))) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool graph = allow_graph && P->sched.use_graph;
-  const bool timed = P->timing && !graph;
-  if (timed) {
-    for (int i = 0; i < 4; ++i)
-      if (!P->ev[i]) RTS_HIP(hipEventCreate(&P->ev[i]));
-    RTS_HIP(hipEventRecord(P->ev[0], st));
+  hipEvent_t* ev = nullptr;
+  if (P->timing && !graph && P->ev_used < kMaxTimed) {
+    if ((int)P->ev.size() <= P->ev_used) {
+      std::array<hipEvent_t, 4> e{};
+      for (int i = 0; i < 4; ++i) RTS_HIP(hipEventCreate(&e[i]));
+      P->ev.push_back(e);
+    }
+    ev = P->ev[P->ev_used].data();
+    RTS_HIP(hipEventRecord(ev[0], st));
   }
   if (!graph) {
-    rc = P->prec == RTS_FP32 ? enqueue_forward<float>(*P, in, out, (char*)ws, st, timed)
-                             : enqueue_forward<double>(*P, in, out, (char*)ws, st, timed);
+    rc = P->prec == RTS_FP32 ? enqueue_forward<float>(*P, in, out, (char*)ws, st, ev)
+                             : enqueue_forward<double>(*P, in, out, (char*)ws, st, ev);
     if (rc) return rc;
-    if (timed) {
-      RTS_HIP(hipEventRecord(P->ev[3], st));
-      P->ev_valid = true;
+    if (ev) {
+      RTS_HIP(hipEventRecord(ev[3], st));
+      ++P->ev_used;
     }
     return RTS_OK;
   }
@@ -493,8 +505,8 @@ int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
     // make sure the task table is resident before capture (the capture re-uploads it)
     P->uploaded_ws = nullptr;
     RTS_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
-    rc = P->prec == RTS_FP32 ? enqueue_forward<float>(*P, in, out, (char*)ws, P->cap_stream, false)
-                             : enqueue_forward<double>(*P, in, out, (char*)ws, P->cap_stream, false);
+    rc = P->prec == RTS_FP32 ? enqueue_forward<float>(*P, in, out, (char*)ws, P->cap_stream, nullptr)
+                             : enqueue_forward<double>(*P, in, out, (char*)ws, P->cap_stream, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
     if (rc) {
@@ -653,7 +665,9 @@ int rts_plan_set_schedule(void* plan, const rts_schedule* s) {
 
 int rts_plan_enable_timing(void* plan, int32_t on) {
   if (!plan) return RTS_E_ARG;
-  static_cast<Plan*>(plan)->timing = on != 0;
+  Plan* P = static_cast<Plan*>(plan);
+  P->timing = on != 0;
+  P->ev_used = 0;
   return RTS_OK;
 }
 
@@ -662,13 +676,18 @@ int rts_plan_last_timing(void* plan, double* sweep_ms, double* total_ms) {
   Plan* P = static_cast<Plan*>(plan);
   *sweep_ms = -1;
   *total_ms = -1;
-  if (!P->ev_valid) return RTS_OK;
-  float a = 0, b = 0;
-  RTS_HIP(hipEventSynchronize(P->ev[3]));
-  RTS_HIP(hipEventElapsedTime(&a, P->ev[1], P->ev[2]));
-  RTS_HIP(hipEventElapsedTime(&b, P->ev[0], P->ev[3]));
-  *sweep_ms = a;
-  *total_ms = b;
+  if (P->ev_used == 0) return RTS_OK;
+  double sa = 0, sb = 0;
+  RTS_HIP(hipEventSynchronize(P->ev[P->ev_used - 1][3]));
+  for (int i = 0; i < P->ev_used; ++i) {
+    float a = 0, b = 0;
+    RTS_HIP(hipEventElapsedTime(&a, P->ev[i][1], P->ev[i][2]));
+    RTS_HIP(hipEventElapsedTime(&b, P->ev[i][0], P->ev[i][3]));
+    sa += a;
+    sb += b;
+  }
+  *sweep_ms = sa / P->ev_used;
+  *total_ms = sb / P->ev_used;
   return RTS_OK;
 }
 
@@ -677,8 +696,9 @@ void rts_plan_destroy(void* plan) {
   Plan* P = static_cast<Plan*>(plan);
   if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
-  for (auto& e : P->ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto& a : P->ev)
+    for (auto& e : a)
+      if (e) (void)hipEventDestroy(e);
   if (P->pinned) (void)hipHostFree(P->pinned);
   for (void* p : P->old_pinned) (void)hipHostFree(p);
   delete P;

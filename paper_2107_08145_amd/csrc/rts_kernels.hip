@@ -77,6 +77,14 @@ __device__ inline double dpp_shl(double old, double v) {
   return *reinterpret_cast<double*>(&r);
 }
 
+// a + f (b - a) as one explicit fused multiply-add (the library is built with
+// -ffp-contract=off, so every fusion is written out and the arithmetic of a
+// cell does not depend on how the compiler schedules a template instance).
+__device__ inline float lerp(float a, float b, float f) { return fmaf(f, b - a, a); }
+__device__ inline double lerp(double a, double b, double f) { return fma(f, b - a, a); }
+__device__ inline float fmad(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline double fmad(double a, double b, double c) { return fma(a, b, c); }
+
 // Error-free sum s + t = u + err (Knuth).
 template <class R>
 __device__ inline void two_sum(R s, R t, R& u, R& err) {
@@ -85,9 +93,25 @@ __device__ inline void two_sum(R s, R t, R& u, R& err) {
   err = (s - (u - bp)) + (t - bp);
 }
 
-__device__ inline int ld_flag(const int* p) {
+// Cross-workgroup traffic of the sweep (edge rows and progress flags) uses
+// only device-coherent accesses: relaxed agent-scope atomic loads and stores,
+// which gfx950 issues with the sc1 bit, so they neither read nor leave stale
+// lines in the non-coherent per-XCD L2.  Ordering is explicit: a producer's
+// edge-row stores complete (s_waitcnt vmcnt(0)) before the workgroup barrier
+// that precedes its flag store; a consumer issues its edge-row loads only
+// after its flag load returned the awaited value.  No cache-wide writeback or
+// invalidate is needed, which an agent-scope fence would cost at every plane.
+template <class R>
+__device__ inline R ld_dev(const R* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+template <class R>
+__device__ inline void st_dev(R* p, R v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void vmem_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__device__ inline int ld_flag(const int* p) { return ld_dev(p); }
 
 // Wait until the given flags reach `need` (null flags are skipped).  Bounded:
 // after `limit` ticks of the constant real-time clock the device status is set
@@ -102,12 +126,12 @@ __device__ inline void wait_flags(const int* fa, const int* fb, int need, int* s
     if (ok) break;
     if (__builtin_amdgcn_readfirstlane(ld_flag(status)) != 0) break;
     if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > limit) {
-      __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      st_dev(status, 1);
       break;
     }
     __builtin_amdgcn_s_sleep(1);
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  asm volatile("" ::: "memory");
 }
 
 // ---------------------------------------------------------------------------
@@ -277,8 +301,8 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, const Task& T, con
         for (int r = 0; r < R; ++r) {
           const bool up = (r & 1) == 0;
           const int br = up ? bc_up : bc_dn;
-          D[i][r] = zp ? pla * sx[i + 1] + plb
-                       : ((r0 + i == br) ? (up ? bua : bda) * sx[i + 1] + (up ? bub : bdb) : Real(0));
+          D[i][r] = zp ? fmad(pla, sx[i + 1], plb)
+                       : ((r0 + i == br) ? fmad(up ? bua : bda, sx[i + 1], up ? bub : bdb) : Real(0));
         }
     } else {
       const int pold = (phase - 1) & 1;  // table of the previous plane
@@ -297,8 +321,8 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, const Task& T, con
 #pragma unroll
         for (int v = 0; v < NC; ++v) {
           const bool lft = UNI ? (v == 0) : (v < 2);
-          lc[v] = cx[idx] + f1[v] * ((lft ? cl : cr) - cx[idx]);
-          ls[v] = sx[idx] + f1[v] * ((lft ? sl : sr) - sx[idx]);
+          lc[v] = lerp(cx[idx], lft ? cl : cr, f1[v]);
+          ls[v] = lerp(sx[idx], lft ? sl : sr, f1[v]);
         }
       };
       auto ldd = [&](int i, Real* ld) {
@@ -306,7 +330,7 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, const Task& T, con
         for (int r = 0; r < R; ++r) {
           const int k = 2 * (H + 2) + i * R + r;
           const Real n = r < 2 ? left(k, D[i][r]) : right(k, D[i][r]);
-          ld[r] = D[i][r] + f1[r] * (n - D[i][r]);
+          ld[r] = lerp(D[i][r], n, f1[r]);
         }
       };
       // halo rows: column-interpolated chi and S, and D
@@ -322,8 +346,8 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, const Task& T, con
           const bool up = (r & 1) == 0;
           const int br = up ? bc_up : bc_dn;
           const Real a = up ? bua : bda, b = up ? bub : bdb;
-          hld[r] = zp ? pla * hls[v] + plb : (row_lo == br ? a * hls[v] + b : Real(0));
-          hud[r] = zp ? pla * hus[v] + plb : (row_hi == br ? a * hus[v] + b : Real(0));
+          hld[r] = zp ? fmad(pla, hls[v], plb) : (row_lo == br ? fmad(a, hls[v], b) : Real(0));
+          hud[r] = zp ? fmad(pla, hus[v], plb) : (row_hi == br ? fmad(a, hus[v], b) : Real(0));
         }
       } else {
         wait_flags(flag_lo, flag_hi, t, status, A.timeout_ticks);
@@ -335,12 +359,14 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, const Task& T, con
           const int cn = r < 2 ? cm : cp1;
           // only the slots whose upwind row is the halo need it
           if ((r & 1) == 0) {
-            const Real a = has_lo ? xl[r * W + cc] : Real(0), b = has_lo ? xl[r * W + cn] : Real(0);
-            hld[r] = a + f1[r] * (b - a);
+            const Real a = has_lo ? ld_dev(xl + r * W + cc) : Real(0);
+            const Real b = has_lo ? ld_dev(xl + r * W + cn) : Real(0);
+            hld[r] = lerp(a, b, f1[r]);
             hud[r] = Real(0);
           } else {
-            const Real a = has_hi ? xh[r * W + cc] : Real(0), b = has_hi ? xh[r * W + cn] : Real(0);
-            hud[r] = a + f1[r] * (b - a);
+            const Real a = has_hi ? ld_dev(xh + r * W + cc) : Real(0);
+            const Real b = has_hi ? ld_dev(xh + r * W + cn) : Real(0);
+            hud[r] = lerp(a, b, f1[r]);
             hld[r] = Real(0);
           }
         }
@@ -376,15 +402,15 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, const Task& T, con
           const Real uc = up ? pc[v] : nc[v];
           const Real us = up ? pS[v] : nS[v];
           const Real ud = up ? pd[r] : nd[r];
-          const Real bc = kc[v] + f2[r] * (uc - kc[v]);
-          const Real bs = kS[v] + f2[r] * (us - kS[v]);
-          const Real bd = kd[r] + f2[r] * (ud - kd[r]);
+          const Real bc = lerp(kc[v], uc, f2[r]);
+          const Real bs = lerp(kS[v], us, f2[r]);
+          const Real bd = lerp(kd[r], ud, f2[r]);
           const Real x = hds[r] * (cpv + bc);
           const Real e = rts_exp_neg(x);
           const Real cw = rts_cw(x, e);
-          const Real dn = e * bd + cw * (bs - spv);
+          const Real dn = fmad(e, bd, cw * (bs - spv));
           const int br = up ? bc_up : bc_dn;
-          D[i][r] = (gr == br) ? (up ? bua : bda) * spv + (up ? bub : bdb) : dn;
+          D[i][r] = (gr == br) ? fmad(up ? bua : bda, spv, up ? bub : bdb) : dn;
         }
 #pragma unroll
         for (int v = 0; v < NC; ++v) { pc[v] = kc[v]; pS[v] = kS[v]; kc[v] = nc[v]; kS[v] = nS[v]; }
@@ -402,11 +428,11 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, const Task& T, con
 #pragma unroll
           for (int i = 1; i < H; ++i)
             if (i == hr - 1) top = D[i][r];
-          if ((r & 1) == 1) xe[r * W + c] = D[0][r];        // lower neighbour: its odd slots
-          if ((r & 1) == 0) xe[xstride + r * W + c] = top;  // upper neighbour: its even slots
+          if ((r & 1) == 1) st_dev(xe + r * W + c, D[0][r]);        // lower neighbour: its odd slots
+          if ((r & 1) == 0) st_dev(xe + xstride + r * W + c, top);  // upper neighbour: its even slots
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      vmem_drain();
     }
     // ---- outputs of plane q: partial sum of w_r D_r (compensated) and I_top
     if (act && (t < 0 ? zp : t >= out_from)) {
@@ -456,8 +482,7 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, const Task& T, con
       }
     }
     __syncthreads();
-    if (t >= 0 && threadIdx.x == 0)
-      __hip_atomic_store(flags + strip, t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (t >= 0 && threadIdx.x == 0) st_dev(flags + strip, t + 1);
     ++phase;
   }
 }
