@@ -82,6 +82,75 @@ def traffic_from_profile(workload):
     return d.get("hbm_bytes_per_launch")
 
 
+COPY_BYTES = 1 << 30
+
+
+def calibrate_copy():
+    """A plain device copy of COPY_BYTES bytes: reads and writes exactly that many."""
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES}))
+
+
+def _db_files(d):
+    import glob
+    return sorted(glob.glob(os.path.join(d, "**", "*.db"), recursive=True))
+
+
+def _pmc_rows(d, counter):
+    """(kernel name, value) of every dispatch in the rocprofv3 databases under d."""
+    import sqlite3
+    rows = []
+    for f in _db_files(d):
+        c = sqlite3.connect(f)
+        q = ("select k.name, p.counter_value from pmc_events p join kernels k "
+             "on p.dispatch_id = k.dispatch_id where p.counter_name = ?")
+        rows += [(n, float(v)) for n, v in c.execute(q, (counter,)).fetchall()]
+    return rows
+
+
+def trace_summary(d):
+    """Per-kernel calls and mean duration from a rocprofv3 --kernel-trace database."""
+    import sqlite3
+    out = []
+    for f in _db_files(d):
+        c = sqlite3.connect(f)
+        q = ("select name, count(*), avg(duration), sum(duration) from kernels "
+             "group by name order by sum(duration) desc")
+        out += [(n, k, a / 1e3, s / 1e6) for n, k, a, s in c.execute(q).fetchall()]
+    return out
+
+
+def pmc_summary(workload, fetch_dir, write_dir, cfetch_dir, cwrite_dir):
+    """HBM bytes per sweep launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
+    scaled by the same counters' reading for the plain copy kernel."""
+    def per_kernel(d, counter, key):
+        v = [x for n, x in _pmc_rows(d, counter) if key in n]
+        return sum(v) / len(v) if v else None
+    f_sweep = per_kernel(fetch_dir, "FETCH_SIZE", "rts_sweep")
+    w_sweep = per_kernel(write_dir, "WRITE_SIZE", "rts_sweep")
+    rows_cf = [x for n, x in _pmc_rows(cfetch_dir, "FETCH_SIZE") if "copyBuffer" in n]
+    rows_cw = [x for n, x in _pmc_rows(cwrite_dir, "WRITE_SIZE") if "copyBuffer" in n]
+    cf = max(rows_cf) if rows_cf else None
+    cw = max(rows_cw) if rows_cw else None
+    kf = COPY_BYTES / (cf * 1024) if cf else None
+    kw = COPY_BYTES / (cw * 1024) if cw else None
+    out = {"workload": workload, "kernel": "rts_sweep", "kernel_hash": kernel_hash(),
+           "fetch_kib_per_dispatch": f_sweep, "write_kib_per_dispatch": w_sweep,
+           "copy_fetch_kib": cf, "copy_write_kib": cw, "copy_bytes": COPY_BYTES,
+           "fetch_scale": kf, "write_scale": kw}
+    if f_sweep and w_sweep and kf and kw:
+        out["hbm_bytes_per_launch"] = f_sweep * 1024 * kf + w_sweep * 1024 * kw
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    path = os.path.join(ROOT, "profiles", f"rts_sweep_{workload}_pmc.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(json.dumps(out))
+
+
 def cpu_baseline(p_full, seconds_hint=True):
     import oracle
     from paper_2107_08145_amd import inputs
@@ -113,7 +182,23 @@ def main():
     ap.add_argument("--size", type=int, default=None, help="cube edge override (debug)")
     ap.add_argument("--rows", type=int, default=0, help="rows per strip (0: plan default)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (scales rocprofv3 byte counters)")
+    ap.add_argument("--trace-summary", metavar="TRACE_DIR",
+                    help="print per-kernel mean durations of a rocprofv3 --kernel-trace run")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs into profiles/")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.pmc_summary:
+        pmc_summary(args.workload, *args.pmc_summary)
+        return
+    if args.trace_summary:
+        for n, k, avg_us, tot_ms in trace_summary(args.trace_summary):
+            print(f"{avg_us:12.1f} us  x{k:4d}  {tot_ms:10.3f} ms  {n[:110]}")
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
