@@ -172,12 +172,99 @@ def cpu_baseline(p_full, seconds_hint=True):
                       f"{q.nrays} rays, n_iter {q.n_iter}, one band (of {p_full.nbands})"}
 
 
+def _time_calls(fn, steps, warmup):
+    """Mean wall time (ms) of `steps` enqueued calls, synchronised on both sides."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def bench_adjoint(args):
+    """Adjoint vs forward on the adjoint workload (128^3 grey unless --workload/--size).
+
+    Loss: L = sum over the top layer and upward rays of (I_top - I_target)^2 +
+    sum(g Q), I_target from the same solver on a 5 % perturbed S.  One adjoint
+    call re-runs the forward sweep (storing D of every plane) and the reverse
+    sweep; the forward reference is one rts_solve."""
+    import torch
+    from paper_2107_08145_amd import inputs, rts
+    name = args.workload if args.workload != "bands288" else "adjoint128"
+    p = inputs.workload(name, size=args.size)
+    prec = rts.RTS_FP32 if args.prec == "fp32" else rts.RTS_FP64
+    pd = p.astype(np.float32 if prec == rts.RTS_FP32 else np.float64)
+    s_target, g = inputs.adjoint_seeds(p, 4000)
+    torch.cuda.set_device(0)
+    plan = rts.Plan(pd, prec)
+    ins = plan.device_inputs(pd)
+    outs = plan.new_outputs(pd)
+    tgt = pd.astype(pd.S.dtype)
+    tgt.S = s_target.astype(pd.S.dtype)
+    _, _, it_target = rts.solve(tgt, prec)
+    plan.solve_into([ins], [outs])
+    torch.cuda.synchronize()
+    gI = (2 * (outs[2] - torch.as_tensor(it_target, device="cuda").to(outs[2].dtype))).contiguous()
+    gQ = torch.as_tensor(g, device="cuda", dtype=torch.float64)
+    dS = torch.empty_like(ins[2])
+    dchi = torch.empty_like(ins[2])
+    fwd_ms = _time_calls(lambda: plan.solve_into([ins], [outs]), args.steps, args.warmup)
+    adj_ms = _time_calls(lambda: plan.adjoint_into([ins], [(gQ, None, gI)], [(dS, dchi)]),
+                         args.steps, args.warmup)
+    plan.check_status()
+    nominal = p.ncells * p.nrays * p.nbands
+    out = {"metric": "adjoint time / forward time (RTS, reverse-mode dL/dS and dL/dchi)",
+           "value": adj_ms / fwd_ms, "unit": "ratio", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(adj_ms, 4), "forward_ms": round(fwd_ms, 4),
+           "higher_is_better": False, "dtype": "f32" if prec == rts.RTS_FP32 else "f64",
+           "data": "synthetic",
+           "adjoint_updates_per_s": nominal / (adj_ms * 1e-3),
+           "workspace_bytes": plan.workspace_bytes(rts.RTS_OP_ADJOINT),
+           "config": {"workload": f"{name}: {p.nx}x{p.ny}x{p.nz}, {p.nbands} band(s), {p.nrays} rays, "
+                                  f"n_iter {p.n_iter}; L = sum (I_top - I_target)^2 + sum g Q"}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """All boxes of the six-box workload in one rts_solve_batched call (graph replay)."""
+    import torch
+    from paper_2107_08145_amd import inputs, rts
+    ps = inputs.workload("boxes6", size=args.size)
+    prec = rts.RTS_FP32 if args.prec == "fp32" else rts.RTS_FP64
+    pds = [p.astype(np.float32 if prec == rts.RTS_FP32 else np.float64) for p in ps]
+    torch.cuda.set_device(0)
+    plan = rts.Plan(pds, prec)
+    if args.rows:
+        plan.set_schedule(rows_per_strip=args.rows)
+    plan.set_schedule(use_graph=1)
+    ins = [plan.device_inputs(p) for p in pds]
+    outs = [plan.new_outputs(p) for p in pds]
+    ms = _time_calls(lambda: plan.solve_into(ins, outs, batched=True), args.steps, args.warmup)
+    plan.check_status()
+    nominal = sum(p.ncells * p.nrays * p.nbands for p in ps)
+    out = {"metric": "cell-ray-band updates/sec (six uneven boxes, 4-band+grey, 24 rays, batched)",
+           "value": nominal / (ms * 1e-3), "unit": "cell-ray-band updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if prec == rts.RTS_FP32 else "f64", "data": "synthetic",
+           "config": {"workload": "boxes6: " + ", ".join(f"{p.nx}x{p.ny}x{p.nz}" for p in ps),
+                      "schedule": plan.schedule()}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="bands288", choices=["bands288", "grey288"])
+    ap.add_argument("--workload", default="bands288",
+                    choices=["bands288", "grey288", "adjoint128", "boxes6"])
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time rts_adjoint against rts_solve (default workload adjoint128)")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--size", type=int, default=None, help="cube edge override (debug)")
     ap.add_argument("--rows", type=int, default=0, help="rows per strip (0: plan default)")
@@ -207,6 +294,12 @@ def main():
     import torch
     from paper_2107_08145_amd import inputs, rts
 
+    if args.adjoint:
+        bench_adjoint(args)
+        return
+    if args.workload == "boxes6":
+        bench_batched(args)
+        return
     t_gen = time.perf_counter()
     p = inputs.workload(args.workload, size=args.size)
     prec = rts.RTS_FP32 if args.prec == "fp32" else rts.RTS_FP64

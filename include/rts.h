@@ -63,7 +63,7 @@ typedef enum { RTS_FP64 = 0, RTS_FP32 = 1 } rts_precision;
 typedef enum { RTS_BOT_THERMAL = 0 /* I = S */, RTS_BOT_FIXED = 1 /* I = i_bot */ } rts_bot_bc;
 typedef enum { RTS_TOP_ZERO = 0 /* I = 0 */, RTS_TOP_THERMAL = 1 /* I = S */ } rts_top_bc;
 /* Operations for rts_workspace_bytes. */
-typedef enum { RTS_OP_SOLVE = 0, RTS_OP_ADJOINT = 1 } rts_op;
+typedef enum { RTS_OP_SOLVE = 0, RTS_OP_ADJOINT = 1, RTS_OP_AUTOTUNE = 2 } rts_op;
 
 typedef struct {
   int32_t nx, ny, nz; /* >= 2 each; nx, ny <= 1024 */
@@ -143,9 +143,34 @@ int rts_solve_batched(void* plan, int32_t nbox, const rts_inputs* in, const rts_
                       void* ws, size_t ws_bytes, void* hip_stream);
 
 /* Reverse-mode gradients of L (rts_seeds) w.r.t. S and chi for every box of
- * the plan; `in`, `g`, `d` point to arrays of nbox entries. */
+ * the plan; `in`, `g`, `d` point to arrays of nbox entries; the workspace
+ * must hold rts_workspace_bytes(RTS_OP_ADJOINT) bytes.
+ *
+ * This is the adjoint of the discrete forward solve (the recursion of the
+ * "Summary of the Radiation Transport Solver" section as implemented by
+ * rts_solve): the call re-runs the forward sweep, storing D of every plane
+ * and lap in the workspace, then sweeps the transposed recursion downwind to
+ * upwind, one launch per plane, recomputing the exp and interpolation weights
+ * from the stored upwind D.  Seeds may be NULL (zero).  dS and dchi are
+ * overwritten; chi = kappa * rho, so dL/dkappa_b = rho dL/dchi_b and
+ * dL/drho = sum_b kappa_b dL/dchi_b.  Per-task partials are summed in a
+ * fixed order in FP64: results are bitwise reproducible for a fixed plan. */
 int rts_adjoint(void* plan, int32_t nbox, const rts_inputs* in, const rts_seeds* g,
                 const rts_grads* d, void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Autotuner: runs the forward solve of all boxes (as rts_solve_batched, not
+ * replayed from a graph) under every candidate schedule -- rows per strip
+ * 2/4/6/8 (FP32) or 2/4 (FP64), queue order 0/1 -- `reps` timed calls each
+ * after one warm-up call, timed with HIP events on `hip_stream`, and keeps
+ * the fastest in the plan (written to *chosen if not NULL).  Candidates whose
+ * workspace exceeds ws_bytes, or whose strips cannot all be resident, are
+ * skipped; rts_workspace_bytes(RTS_OP_AUTOTUNE) covers every candidate.
+ * Synchronous.  The choice is cached per process by problem shape and
+ * device: a later call on an equal problem applies it without timing.
+ * Outputs hold the result of the last timed call. */
+int rts_plan_autotune(void* plan, int32_t nbox, const rts_inputs* in, const rts_outputs* out,
+                      void* ws, size_t ws_bytes, void* hip_stream, int32_t reps,
+                      rts_schedule* chosen);
 
 /* Synchronise `hip_stream` and read the device status word left in `ws` by
  * the last call: RTS_OK, or RTS_E_DEADLOCK if a neighbour wait timed out. */

@@ -11,6 +11,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <new>
@@ -35,6 +36,14 @@ template <class Real, int H, bool UNI>
 hipError_t launch_sweep_h(const SweepArgs&, int, int, hipStream_t);
 template <class Real>
 hipError_t launch_reduce(const char*, const Task*, const BoxGeo&, const BoxPtrs&, hipStream_t);
+template <class Real>
+hipError_t launch_adj_plane(const AdjArgs&, int, hipStream_t);
+template <class Real>
+hipError_t launch_adj_seed(const void*, const void*, const double*, const void*, void*, void*,
+                           double, int, int, int, hipStream_t);
+template <class Real>
+hipError_t launch_adj_reduce(const char*, const Task*, const AdjTask*, const BoxGeo&,
+                             const double*, const void*, const void*, void*, void*, hipStream_t);
 hipError_t launch_dpp_selftest(const float*, float*, hipStream_t);
 }  // namespace rts
 
@@ -90,6 +99,7 @@ struct Box {
   int tasks_per_band = 0;
   std::vector<std::array<int, 4>> groups;  // ray index per slot (-1 unused), same for every band
   int64_t chi_off = 0, chiT_off = 0, sT_off = 0;  // Real-element offsets
+  int64_t seed_off = 0, seedT_off = 0;            // adjoint seeds [nbands][N], both layouts
 };
 
 struct Plan {
@@ -98,7 +108,12 @@ struct Plan {
   size_t esz = 8;
   rts_schedule sched{4, 0, 0, 0};
   // layout (bytes)
-  size_t off_flags = 0, off_tasks = 0, off_queue = 0, off_data = 0, total = 0;
+  size_t off_flags = 0, off_tasks = 0, off_queue = 0, off_atasks = 0, off_data = 0, total = 0;
+  // adjoint: the solve layout, then stored D planes, reverse state, gradient
+  // partials [off_grads, off_grads_end) and seeds
+  size_t off_grads = 0, off_grads_end = 0, total_adj = 0;
+  int adj_launches = 0, adj_blocks = 0;
+  std::vector<AdjTask> atasks;
   std::vector<Task> tasks;
   std::vector<int32_t> queue;
   int total_strips = 0;
@@ -150,6 +165,7 @@ int validate_desc(const rts_desc& d) {
   if (d.nbands > 16 || d.nrays > 64) return RTS_E_UNSUPPORTED;
   if (g.nx > kMaxCols || g.ny > kMaxCols) return RTS_E_UNSUPPORTED;
   if ((int64_t)g.nx * g.ny * g.nz > ((int64_t)1 << 31)) return RTS_E_UNSUPPORTED;
+  if ((int64_t)g.nz * d.nbands > 65535) return RTS_E_UNSUPPORTED;  // grid z of prep and reduce
   return RTS_OK;
 }
 
@@ -243,6 +259,7 @@ void build_layout(Plan& P) {
     T.it_off = (int64_t)T.band * B.n_up * nx * ny;
     T.rows_per_strip = std::min(H, T.n_rows);
     T.strips = (T.n_rows + T.rows_per_strip - 1) / T.rows_per_strip;
+    T.n_unrolled = T.z_planes ? T.n_planes : T.laps * T.n_planes;
     max_cols = std::max(max_cols, T.n_cols);
     P.tasks[t] = T;
   }
@@ -272,13 +289,22 @@ void build_layout(Plan& P) {
   P.uni = true;
   for (const Task& T : P.tasks) P.uni = P.uni && T.uni;
 
-  // layout
+  // layout: header, then the neighbour exchange buffers (both zeroed by every
+  // call: exchanged words carry step tags that must not survive a call), the
+  // task table and queue, the per-box arrays and the per-task partial sums
+  const size_t words = P.prec == RTS_FP32 ? 1 : 2;  // 64-bit words per exchanged value
   P.off_flags = off;
-  off = align_up(off + sizeof(int32_t) * (size_t)std::max(1, P.total_strips));
+  for (Task& T : P.tasks) {
+    T.xbuf_off = (int64_t)(off / sizeof(uint64_t));
+    off = align_up(off + (size_t)T.strips * 2 * 2 * kMaxRaysPerTask * T.n_cols * words * sizeof(uint64_t));
+    T.flag_off = 0;
+  }
   P.off_tasks = off;
   off = align_up(off + sizeof(Task) * P.tasks.size());
   P.off_queue = off;
   off = align_up(off + sizeof(int32_t) * P.queue.size());
+  P.off_atasks = off;
+  off = align_up(off + sizeof(AdjTask) * P.tasks.size());
   P.off_data = off;
   for (Box& B : P.boxes) {
     const size_t arr = (size_t)B.d.nbands * B.N * esz;
@@ -299,16 +325,47 @@ void build_layout(Plan& P) {
     T.part_off = (int64_t)(off / esz);
     off = align_up(off + (size_t)B.N * esz);
   }
-  for (Task& T : P.tasks) {
-    T.xbuf_off = (int64_t)(off / esz);
-    off = align_up(off + (size_t)T.strips * 2 * 2 * kMaxRaysPerTask * T.n_cols * esz);
-  }
-  int fl = 0;
-  for (int i : q) {
-    P.tasks[i].flag_off = (int64_t)(P.off_flags / sizeof(int32_t)) + fl;
-    fl += P.tasks[i].strips;
-  }
   P.total = off;
+
+  // adjoint region
+  P.atasks.assign(P.tasks.size(), AdjTask{});
+  for (size_t t = 0; t < P.tasks.size(); ++t) {
+    Task& T = P.tasks[t];
+    const size_t pc = (size_t)T.n_rows * T.n_cols;
+    T.dstore_off = (int64_t)(off / esz);
+    off = align_up(off + (size_t)T.n_unrolled * kMaxRaysPerTask * pc * esz);
+    P.atasks[t].state_off = (int64_t)(off / esz);
+    off = align_up(off + 2 * kMaxRaysPerTask * 3 * pc * esz);
+  }
+  P.off_grads = off;
+  for (size_t t = 0; t < P.tasks.size(); ++t) {
+    const Box& B = P.boxes[P.tasks[t].box];
+    P.atasks[t].gs_off = (int64_t)(off / esz);
+    off = align_up(off + (size_t)B.N * esz);
+    P.atasks[t].gc_off = (int64_t)(off / esz);
+    off = align_up(off + (size_t)B.N * esz);
+  }
+  P.off_grads_end = off;
+  for (Box& B : P.boxes) {
+    const size_t arr = (size_t)B.d.nbands * B.N * esz;
+    B.seed_off = (int64_t)(off / esz); off = align_up(off + arr);
+    B.seedT_off = (int64_t)(off / esz); off = align_up(off + arr);
+  }
+  P.total_adj = off;
+  P.adj_launches = 0;
+  P.adj_blocks = 0;
+  for (size_t t = 0; t < P.tasks.size(); ++t) {
+    const Task& T = P.tasks[t];
+    const Box& B = P.boxes[T.box];
+    AdjTask& AT = P.atasks[t];
+    AT.task = (int32_t)t;
+    AT.ncell = T.n_rows * T.n_cols;
+    AT.cell0 = P.adj_blocks * 256;
+    P.adj_blocks += (AT.ncell + 255) / 256;
+    AT.u_init = T.z_planes ? 0 : -1;
+    AT.seed_off = (T.transposed ? B.seedT_off : B.seed_off) + (int64_t)T.band * B.N;
+    P.adj_launches = std::max(P.adj_launches, T.n_unrolled - AT.u_init);
+  }
   P.uploaded_ws = nullptr;
   if (P.gexec) {
     (void)hipGraphExecDestroy(P.gexec);
@@ -385,14 +442,31 @@ int ensure_pinned(Plan& P) {
   std::memcpy(P.pinned, P.tasks.data(), sizeof(Task) * P.tasks.size());
   std::memcpy((char*)P.pinned + (P.off_queue - P.off_tasks), P.queue.data(),
               sizeof(int32_t) * P.queue.size());
+  std::memcpy((char*)P.pinned + (P.off_atasks - P.off_tasks), P.atasks.data(),
+              sizeof(AdjTask) * P.atasks.size());
   return RTS_OK;
 }
 
 // Enqueue one forward solve of all boxes of the plan.
+BoxGeo box_geo(const Plan& P, size_t b) {
+  const Box& B = P.boxes[b];
+  BoxGeo G;
+  std::memset(&G, 0, sizeof(G));
+  G.nx = B.d.g.nx; G.ny = B.d.g.ny; G.nz = B.d.g.nz; G.nbands = B.d.nbands;
+  G.n_up = B.n_up;
+  G.tasks_per_band = B.tasks_per_band;
+  for (size_t t = 0; t < P.tasks.size(); ++t)
+    if (P.tasks[t].box == (int)b) { G.task0 = (int)t; break; }
+  for (int k = 0; k < B.d.nbands; ++k) G.qweight[k] = B.qw[k];
+  return G;
+}
+
+// With out == nullptr (the forward pass of the adjoint) the sweep also stores
+// D of every plane, writes no I_top and the reduce is skipped.
 template <class Real>
 int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char* ws,
                     hipStream_t st, hipEvent_t* ev) {
-  // header + flags to zero
+  // header and exchange buffers to zero
   RTS_HIP(launch_zero(reinterpret_cast<int*>(ws),
                       (int64_t)((P.off_tasks) / sizeof(int32_t)), st));
   if (P.uploaded_ws != ws) {
@@ -414,7 +488,9 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
   a.total_strips = P.total_strips;
   a.timeout_ticks = P.timeout_ticks;
   for (size_t b = 0; b < P.boxes.size(); ++b)
-    a.box[b] = BoxPtrs{in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top};
+    a.box[b] = out ? BoxPtrs{in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top}
+                   : BoxPtrs{in[b].kappa, in[b].rho, in[b].S, nullptr, nullptr, nullptr};
+  a.store_d = out ? 0 : 1;
   // Every strip of a task must be resident together (neighbouring strips wait
   // on each other), so the grid never drops below the largest task's strip
   // count; tickets are claimed in order, hence with that many resident
@@ -425,20 +501,54 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
   if (ev) RTS_HIP(hipEventRecord(ev[1], st));
   RTS_HIP(launch_sweep<Real>(P, a, grid, st));
   if (ev) RTS_HIP(hipEventRecord(ev[2], st));
+  if (!out) return RTS_OK;
   for (size_t b = 0; b < P.boxes.size(); ++b) {
-    const Box& B = P.boxes[b];
-    BoxGeo G;
-    std::memset(&G, 0, sizeof(G));
-    G.nx = B.d.g.nx; G.ny = B.d.g.ny; G.nz = B.d.g.nz; G.nbands = B.d.nbands;
-    G.n_up = B.n_up;
-    G.tasks_per_band = B.tasks_per_band;
-    int first = 0;
-    for (size_t t = 0; t < P.tasks.size(); ++t)
-      if (P.tasks[t].box == (int)b) { first = (int)t; break; }
-    G.task0 = first;
-    for (int k = 0; k < B.d.nbands; ++k) G.qweight[k] = B.qw[k];
+    const BoxGeo G = box_geo(P, b);
     RTS_HIP(launch_reduce<Real>(ws, reinterpret_cast<const Task*>(ws + P.off_tasks), G,
                                 a.box[b], st));
+  }
+  return RTS_OK;
+}
+
+// Enqueue one adjoint: the forward sweep storing D, the seeds, one reverse
+// launch per unrolled plane (every task of every box), the gradient reduce.
+template <class Real>
+int enqueue_adjoint(Plan& P, const rts_inputs* in, const rts_seeds* g, const rts_grads* d,
+                    char* ws, hipStream_t st) {
+  int rc = enqueue_forward<Real>(P, in, nullptr, ws, st, nullptr);
+  if (rc) return rc;
+  RTS_HIP(launch_zero(reinterpret_cast<int*>(ws + P.off_grads),
+                      (int64_t)((P.off_grads_end - P.off_grads) / sizeof(int32_t)), st));
+  for (size_t b = 0; b < P.boxes.size(); ++b) {
+    const Box& B = P.boxes[b];
+    Real* base = reinterpret_cast<Real*>(ws);
+    for (int k = 0; k < B.d.nbands; ++k) {
+      const int64_t o = (int64_t)k * B.N;
+      const double qf = 4.0 * 3.14159265358979323846 * B.qw[k];
+      const Real* kap = reinterpret_cast<const Real*>(in[b].kappa) + o;
+      const Real* gJ = g[b].gJ ? reinterpret_cast<const Real*>(g[b].gJ) + o : nullptr;
+      RTS_HIP(launch_adj_seed<Real>(kap, in[b].rho, g[b].gQ, gJ, base + B.seed_off + o,
+                                    base + B.seedT_off + o, qf, B.d.g.nx, B.d.g.ny, B.d.g.nz, st));
+    }
+  }
+  AdjArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.ws = ws;
+  a.tasks = reinterpret_cast<const Task*>(ws + P.off_tasks);
+  a.atasks = reinterpret_cast<const AdjTask*>(ws + P.off_atasks);
+  a.natasks = (int)P.atasks.size();
+  for (size_t b = 0; b < P.boxes.size(); ++b) {
+    a.gItop[b] = g[b].gItop;
+    a.S[b] = in[b].S;
+  }
+  for (int k = 0; k < P.adj_launches; ++k) {
+    a.k = k;
+    RTS_HIP(launch_adj_plane<Real>(a, P.adj_blocks, st));
+  }
+  for (size_t b = 0; b < P.boxes.size(); ++b) {
+    const BoxGeo G = box_geo(P, b);
+    RTS_HIP(launch_adj_reduce<Real>(ws, a.tasks, a.atasks, G, g[b].gQ, g[b].gJ, g[b].gItop,
+                                    d[b].dS, d[b].dchi, st));
   }
   return RTS_OK;
 }
@@ -455,11 +565,10 @@ int check_call(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
   return RTS_OK;
 }
 
-int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, void* ws,
-               size_t ws_bytes, void* stream, bool allow_graph) {
-  int rc = check_call(P, nbox, in, out, ws, ws_bytes);
+// Device state a call needs: the device check, occupancy and the pinned task table.
+int prepare(Plan* P) {
+  int rc = dev_init(*P);
   if (rc) return rc;
-  if ((rc = dev_init(*P))) return rc;
   if (P->occupancy_blocks == 0) {
     rc = P->prec == RTS_FP32 ? occupancy<float>(*P) : occupancy<double>(*P);
     if (rc) return rc;
@@ -468,7 +577,14 @@ int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
       return RTS_E_UNSUPPORTED;
     }
   }
-  if ((rc = ensure_pinned(*P))) return rc;
+  return ensure_pinned(*P);
+}
+
+int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, void* ws,
+               size_t ws_bytes, void* stream, bool allow_graph) {
+  int rc = check_call(P, nbox, in, out, ws, ws_bytes);
+  if (rc) return rc;
+  if ((rc = prepare(P))) return rc;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool graph = allow_graph && P->sched.use_graph;
   hipEvent_t* ev = nullptr;
@@ -521,6 +637,106 @@ int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
   }
   RTS_HIP(hipGraphLaunch(P->gexec, st));
   return RTS_OK;
+}
+
+// Schedules the autotuner tries: every strip height of the precision, both
+// queue orders.
+std::vector<rts_schedule> tune_candidates(const Plan& P) {
+  std::vector<rts_schedule> c;
+  const int hs32[] = {2, 4, 6, 8}, hs64[] = {2, 4};
+  const int* hs = P.prec == RTS_FP32 ? hs32 : hs64;
+  const int nh = P.prec == RTS_FP32 ? 4 : 2;
+  for (int i = 0; i < nh; ++i)
+    for (int order = 0; order < 2; ++order) c.push_back(rts_schedule{hs[i], 0, order, P.sched.use_graph});
+  return c;
+}
+
+std::string tune_key(const Plan& P, int device) {
+  std::string k = std::to_string(device) + "/" + std::to_string(P.prec);
+  for (const Box& B : P.boxes) {
+    k += "|" + std::to_string(B.d.g.nx) + "x" + std::to_string(B.d.g.ny) + "x" +
+         std::to_string(B.d.g.nz) + "b" + std::to_string(B.d.nbands) + "t" +
+         std::to_string(B.tasks_per_band) + "i" + std::to_string(B.d.n_iter);
+    for (const auto& g : B.groups)
+      for (int r : g) k += "," + std::to_string(r);
+  }
+  return k;
+}
+
+std::map<std::string, rts_schedule>& tune_cache() {
+  static std::map<std::string, rts_schedule> m;
+  return m;
+}
+
+void set_sched(Plan* P, const rts_schedule& s) {
+  P->sched = s;
+  P->occupancy_blocks = 0;
+  if (P->pinned) {
+    P->old_pinned.push_back(P->pinned);
+    P->pinned = nullptr;
+    P->pinned_bytes = 0;
+  }
+  build_layout(*P);
+}
+
+// Time every candidate schedule on the caller's data (HIP events, `reps`
+// timed calls after one warm-up call each) and keep the fastest.  Results
+// are cached per process by problem shape and device.
+int autotune_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, void* ws,
+                  size_t ws_bytes, hipStream_t st, int reps, int* tried) {
+  int rc = check_call(P, nbox, in, out, ws, SIZE_MAX);  // the size is checked per candidate
+  if (rc) return rc;
+  if ((rc = dev_init(*P))) return rc;
+  const std::string key = tune_key(*P, P->device);
+  *tried = 0;
+  auto hit = tune_cache().find(key);
+  if (hit != tune_cache().end()) {
+    set_sched(P, hit->second);
+    return RTS_OK;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  RTS_HIP(hipEventCreate(&e0));
+  RTS_HIP(hipEventCreate(&e1));
+  const rts_schedule orig = P->sched;
+  rts_schedule best = orig;
+  float best_ms = INFINITY;
+  int status = RTS_OK;
+  for (const rts_schedule& c : tune_candidates(*P)) {
+    set_sched(P, c);
+    if (P->total > ws_bytes) continue;
+    rc = prepare(P);
+    if (rc == RTS_E_UNSUPPORTED) continue;
+    if (rc) { status = rc; break; }
+    auto run = [&]() {
+      return P->prec == RTS_FP32 ? enqueue_forward<float>(*P, in, out, (char*)ws, st, nullptr)
+                                 : enqueue_forward<double>(*P, in, out, (char*)ws, st, nullptr);
+    };
+    if ((rc = run())) { status = rc; break; }
+    if (hipEventRecord(e0, st) != hipSuccess) { status = RTS_E_HIP; break; }
+    for (int i = 0; i < reps && !rc; ++i) rc = run();
+    if (rc) { status = rc; break; }
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      status = RTS_E_HIP;
+      break;
+    }
+    int32_t dev_status = 0;
+    if (hipMemcpy(&dev_status, ws, sizeof(dev_status), hipMemcpyDeviceToHost) != hipSuccess) {
+      status = RTS_E_HIP;
+      break;
+    }
+    if (dev_status) { status = RTS_E_DEADLOCK; break; }
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { status = RTS_E_HIP; break; }
+    ms /= reps;
+    ++*tried;
+    if (ms < best_ms) { best_ms = ms; best = c; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status == RTS_OK && *tried == 0) status = RTS_E_WORKSPACE;
+  set_sched(P, status == RTS_OK ? best : orig);
+  if (status == RTS_OK) tune_cache()[key] = best;
+  return status;
 }
 
 }  // namespace
@@ -594,7 +810,28 @@ int rts_workspace_bytes(void* plan, int32_t op, size_t* bytes) {
     *bytes = P->total;
     return RTS_OK;
   }
-  if (op == RTS_OP_ADJOINT) return RTS_E_UNSUPPORTED;
+  if (op == RTS_OP_ADJOINT) {
+    *bytes = P->total_adj;
+    return RTS_OK;
+  }
+  if (op == RTS_OP_AUTOTUNE) {
+    size_t m = 0;
+    try {
+      for (const rts_schedule& c : tune_candidates(*P)) {
+        Plan tmp;
+        tmp.boxes = P->boxes;
+        tmp.prec = P->prec;
+        tmp.esz = P->esz;
+        tmp.sched = c;
+        build_layout(tmp);
+        m = std::max(m, tmp.total);
+      }
+    } catch (...) {
+      return RTS_E_ARG;
+    }
+    *bytes = m;
+    return RTS_OK;
+  }
   return RTS_E_ARG;
 }
 
@@ -622,9 +859,38 @@ int rts_solve_batched(void* plan, int32_t nbox, const rts_inputs* in, const rts_
 
 int rts_adjoint(void* plan, int32_t nbox, const rts_inputs* in, const rts_seeds* g,
                 const rts_grads* d, void* ws, size_t ws_bytes, void* hip_stream) {
-  (void)nbox; (void)in; (void)g; (void)d; (void)ws; (void)ws_bytes; (void)hip_stream;
-  if (!plan) return RTS_E_ARG;
-  return RTS_E_UNSUPPORTED;
+  if (!plan || !in || !g || !d) return RTS_E_ARG;
+  Plan* P = static_cast<Plan*>(plan);
+  if (nbox != (int)P->boxes.size()) return RTS_E_ARG;
+  for (int b = 0; b < nbox; ++b)
+    if (!in[b].kappa || !in[b].rho || !in[b].S || !d[b].dS || !d[b].dchi) return RTS_E_ARG;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 || ws_bytes < P->total_adj)
+    return RTS_E_WORKSPACE;
+  try {
+    int rc = prepare(P);
+    if (rc) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    return P->prec == RTS_FP32 ? enqueue_adjoint<float>(*P, in, g, d, (char*)ws, st)
+                               : enqueue_adjoint<double>(*P, in, g, d, (char*)ws, st);
+  } catch (...) {
+    return RTS_E_HIP;
+  }
+}
+
+int rts_plan_autotune(void* plan, int32_t nbox, const rts_inputs* in, const rts_outputs* out,
+                      void* ws, size_t ws_bytes, void* hip_stream, int32_t reps,
+                      rts_schedule* chosen) {
+  if (!plan || reps < 1) return RTS_E_ARG;
+  Plan* P = static_cast<Plan*>(plan);
+  try {
+    int tried = 0;
+    const int rc = autotune_impl(P, nbox, in, out, ws, ws_bytes,
+                                 reinterpret_cast<hipStream_t>(hip_stream), reps, &tried);
+    if (rc == RTS_OK && chosen) *chosen = P->sched;
+    return rc;
+  } catch (...) {
+    return RTS_E_HIP;
+  }
 }
 
 int rts_check_status(void* plan, const void* ws, void* hip_stream) {
@@ -649,14 +915,7 @@ int rts_plan_set_schedule(void* plan, const rts_schedule* s) {
   const bool ok = P->prec == RTS_FP32 ? (h == 2 || h == 4 || h == 6 || h == 8) : (h == 2 || h == 4);
   if (!ok || s->max_workgroups < 0 || (s->order != 0 && s->order != 1)) return RTS_E_ARG;
   try {
-    P->sched = *s;
-    P->occupancy_blocks = 0;
-    if (P->pinned) {
-      P->old_pinned.push_back(P->pinned);
-      P->pinned = nullptr;
-      P->pinned_bytes = 0;
-    }
-    build_layout(*P);
+    set_sched(P, *s);
   } catch (...) {
     return RTS_E_ARG;
   }

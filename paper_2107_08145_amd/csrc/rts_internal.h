@@ -41,15 +41,41 @@ struct Task {
   int64_t chi_off;         // element offset of this band's chi view in the workspace
   int64_t s_off;           // element offset of S: into the box's S (natural) or workspace
   int64_t part_off;        // element offset of the partial sum array in the workspace
-  int64_t xbuf_off;        // element offset of the neighbour exchange buffer
-  int64_t flag_off;        // int offset of the strip flags
+  int64_t xbuf_off;        // 64-bit-word offset of the neighbour exchange buffer
+  int64_t flag_off;        // unused
   int64_t it_off;          // element offset of this band's I_top block in the box I_top
   int64_t itp, itr, itc;   // I_top strides for (plane, row, col)
   int64_t it_ray;          // I_top stride between up rays (ny * nx)
+  int64_t dstore_off;      // element offset of the stored D of every plane [u][slot][row][col]
+  int32_t n_unrolled;      // planes u of the unrolled sweep (u = 0 first plane after the ghost,
+                           // or the boundary plane when planes are z)
+  int32_t pad1;
   double pl_a, pl_b;       // boundary-plane value D = pl_a * S + pl_b (z_planes)
   double bu_a, bu_b;       // boundary row 0 of even slots (rows are z, mu_z > 0)
   double bd_a, bd_b;       // boundary row n_rows-1 of odd slots (rows are z, mu_z < 0)
   TaskRay ray[kMaxRaysPerTask];
+};
+
+// Reverse sweep of one task, for the adjoint (one launch per unrolled plane).
+struct AdjTask {
+  int32_t task;       // index into the Task table (AdjTask i belongs to Task i)
+  int32_t cell0;      // first thread of this task in a launch (a multiple of the block size)
+  int32_t ncell;      // n_rows * n_cols
+  int32_t u_init;     // first unrolled plane: -1 (ghost plane of a periodic sweep) or 0
+  int64_t state_off;  // Real offset of [2][slot][a, b, g][row][col]
+  int64_t gs_off;     // Real offset of this task's dL/dS partial (task array layout)
+  int64_t gc_off;     // Real offset of this task's dL/dchi partial (task array layout)
+  int64_t seed_off;   // Real offset of the band's seed in the task array layout
+};
+
+struct AdjArgs {
+  char* ws;
+  const Task* tasks;
+  const AdjTask* atasks;
+  int32_t natasks;
+  int32_t k;  // launch index: each task handles unrolled plane n_unrolled - 1 - k
+  const void* gItop[kMaxBoxes];  // per box, [nbands][n_up][ny][nx] or null
+  const void* S[kMaxBoxes];      // per box, [nbands][N]
 };
 
 struct BoxPtrs {
@@ -88,6 +114,8 @@ struct SweepArgs {
   int32_t ntasks;
   int32_t total_strips;
   int64_t timeout_ticks;   // s_memrealtime ticks before a wait gives up
+  int32_t store_d;         // also store D of every plane (forward pass of the adjoint)
+  int32_t pad;
   BoxPtrs box[kMaxBoxes];
 };
 

@@ -26,6 +26,14 @@
 
 namespace rts {
 
+// The task table and queue are written by the host before the sweep and only
+// read by it.  Reading them through the constant address space lets the
+// compiler use scalar loads (and reload instead of spilling): a plain global
+// pointer into the workspace, which the sweep also writes, forces vector loads.
+#define RTS_CONST __attribute__((address_space(4)))
+typedef const Task RTS_CONST CTask;
+typedef const int32_t RTS_CONST CInt;
+
 // ---------------------------------------------------------------------------
 // small helpers
 
@@ -111,28 +119,46 @@ __device__ inline void st_dev(R* p, R v) {
 }
 __device__ inline void vmem_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-__device__ inline int ld_flag(const int* p) { return ld_dev(p); }
-
-// Wait until the given flags reach `need` (null flags are skipped).  Bounded:
-// after `limit` ticks of the constant real-time clock the device status is set
-// and every later wait returns at once, so every wave always finishes.
-__device__ inline void wait_flags(const int* fa, const int* fb, int need, int* status,
-                                  int64_t limit) {
-  uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-  for (;;) {
-    int ok = 1;
-    if (fa) ok &= __builtin_amdgcn_readfirstlane(ld_flag(fa)) >= need;
-    if (fb) ok &= __builtin_amdgcn_readfirstlane(ld_flag(fb)) >= need;
-    if (ok) break;
-    if (__builtin_amdgcn_readfirstlane(ld_flag(status)) != 0) break;
-    if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > limit) {
-      st_dev(status, 1);
-      break;
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS accesses,
+// not for its outstanding global stores (the sweep's global stores are read by
+// other workgroups through tags, never by this one).
+__device__ inline void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
   asm volatile("" ::: "memory");
 }
+
+// Edge rows are exchanged as self-validating words: every published value
+// carries the number of the plane step that produced it (plus one) in the
+// same single-copy-atomic 64-bit word.  FP32: (value, tag); FP64: two words
+// (low half, tag) and (high half, tag).  A consumer issues its loads early,
+// overlaps them with other work, and re-polls only if a tag is stale.
+template <class Real>
+struct Tagged;
+template <>
+struct Tagged<float> {
+  static constexpr int WORDS = 1;
+  __device__ static void put(uint64_t* p, float v, uint32_t tag) {
+    st_dev<uint64_t>(p, ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(v));
+  }
+  __device__ static bool fresh(const uint64_t* w, uint32_t tag) { return (uint32_t)(w[0] >> 32) == tag; }
+  __device__ static float value(const uint64_t* w) { return __uint_as_float((uint32_t)w[0]); }
+};
+template <>
+struct Tagged<double> {
+  static constexpr int WORDS = 2;
+  __device__ static void put(uint64_t* p, double v, uint32_t tag) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    st_dev<uint64_t>(p, ((uint64_t)tag << 32) | (b & (uint64_t)0xffffffffu));
+    st_dev<uint64_t>(p + 1, ((uint64_t)tag << 32) | (b >> 32));
+  }
+  __device__ static bool fresh(const uint64_t* w, uint32_t tag) {
+    return (uint32_t)(w[0] >> 32) == tag && (uint32_t)(w[1] >> 32) == tag;
+  }
+  __device__ static double value(const uint64_t* w) {
+    return __longlong_as_double((long long)((w[0] & 0xffffffffull) | (w[1] << 32)));
+  }
+};
 
 // ---------------------------------------------------------------------------
 // prep: chi = kappa * rho, chi^T and S^T in [x][z][y]
@@ -183,8 +209,40 @@ __global__ void rts_zero_ints(int* p, int64_t n) {
 
 template <class Real, int H>
 struct Strip {
-  // LDS table entry of one lane: chi and S of rows -1..H, then D of rows 0..H-1 per ray
-  static constexpr int NS = 2 * (H + 2) + kMaxRaysPerTask * H;
+  // LDS plane state, one column per thread: chi and S of rows -1..H (index
+  // 0..H+1), then D of rows 0..H-1 for the four slots.  Stored [column][NQP]
+  // with an odd NQP, so that a thread's quantities sit at immediate offsets
+  // from its column base and consecutive columns hit distinct banks.
+  static constexpr int NQ = 2 * (H + 2) + kMaxRaysPerTask * H;
+  static constexpr int NQP = NQ | 1;
+  __device__ static constexpr int qc(int j) { return j; }
+  __device__ static constexpr int qs(int j) { return H + 2 + j; }
+  __device__ static constexpr int qd(int i, int r) { return 2 * (H + 2) + kMaxRaysPerTask * i + r; }
+};
+
+// e = exp(-x) and c = (1 - e)/x of the linear-source step.  FP32 takes
+// xs = x log2(e) (the factor is folded into ds/2 by the caller) so that e is
+// one v_exp_f32; c uses its 5-term series below x = 0.1.  FP64 takes xs = x.
+__device__ inline void step_weights(float xs, float& e, float& c) {
+  constexpr float ln2 = 0.69314718055994531f, log2e = 1.4426950408889634f;
+  e = __builtin_amdgcn_exp2f(-xs);
+  // sum_{n=0}^{4} (-x)^n / (n+1)!  with x = xs ln2
+  constexpr float a1 = -ln2 / 2.f, a2 = ln2 * ln2 / 6.f, a3 = -ln2 * ln2 * ln2 / 24.f,
+                  a4 = ln2 * ln2 * ln2 * ln2 / 120.f;
+  const float s = fmaf(fmaf(fmaf(fmaf(xs, a4, a3), xs, a2), xs, a1), xs, 1.f);
+  const float l = (1.f - e) * (__builtin_amdgcn_rcpf(xs) * log2e);
+  c = xs < 0.1f * log2e ? s : l;
+}
+__device__ inline void step_weights(double x, double& e, double& c) {
+  e = exp(-x);
+  c = rts_cw(x, e);
+}
+
+// Column-interpolated values of one old row: chi and S (NC variants) and D of
+// every slot, at the upwind column of each slot.
+template <class Real, int NC>
+struct LRow {
+  Real c[NC], s[NC], d[kMaxRaysPerTask];
 };
 
 // One strip of one task: H rows x all columns of the task's sweep plane,
@@ -193,45 +251,44 @@ struct Strip {
 // Ray slots are fixed: slot k has its upwind column at c-1 for k < 2 (else
 // c+1) and its upwind row at i-1 for even k (else i+1).  With UNI the four
 // slots share f1, f2, ds and w, so the column interpolation of chi and S is
-// shared by the two slots with the same column direction.
+// shared by the two slots with the same column direction.  FULL strips have
+// exactly H rows (known at compile time); the last strip of a task may not.
 //
-// State carried from plane to plane is raw: chi and S of the strip's rows and
-// of the two halo rows, and D of every row and slot.  The interpolation to the
-// upwind point of the next plane is done at step time, row by row: along the
-// columns with DPP lane shifts (wave-edge lanes patched from the LDS table),
-// along the rows from registers (halo rows: chi and S loaded, D from the
-// neighbouring strips' published edge rows).
-template <class Real, int H, bool UNI>
-__device__ __forceinline__ void run_strip(const SweepArgs& A, const Task& T, const int strip,
-                                          Real* tab, int& phase) {
+// The old plane (chi, S of the strip's rows and the two halo rows, D of every
+// row and slot) lives in LDS, one column per thread, so that column
+// neighbours are plain LDS reads and registers hold only a sliding window of
+// interpolated rows.  A step has a read phase (the two edge rows first, which
+// need the neighbouring strips' D and are published at once as tagged words,
+// then the interior rows) and, after a barrier, a write phase that stores the
+// new plane; a second barrier ends the step.  Addresses of global data are a
+// uniform row pointer plus the thread's column.
+template <class Real, int H, bool UNI, bool FULL>
+__device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const int strip,
+                                          Real* lds) {
+  using ST = Strip<Real, H>;
   constexpr int R = kMaxRaysPerTask;
-  constexpr int NS = Strip<Real, H>::NS;
   constexpr int NC = UNI ? 2 : R;  // distinct column-interpolated chi/S per row
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  using LR = LRow<Real, NC>;
+  using TG = Tagged<Real>;
+  constexpr int NW = TG::WORDS;
   const int W = T.n_cols;
   const int c = threadIdx.x;
   const bool act = c < W;
   const int cc = act ? c : W - 1;
-  const int nwt = (W + 63) >> 6;  // waves that hold columns of this task
-  const int last_lane = (wv == nwt - 1) ? (W - 1 - 64 * (nwt - 1)) : 63;
+  const int cm = cc > 0 ? cc - 1 : W - 1, cp1 = cc + 1 < W ? cc + 1 : 0;
   const int r0 = strip * T.rows_per_strip;
-  const int hr = min(T.rows_per_strip, T.n_rows - r0);
-  const int64_t ps = T.plane_stride, rs = T.row_stride;
+  const int hr = FULL ? H : min(T.rows_per_strip, T.n_rows - r0);
+  const int ps = (int)T.plane_stride, rs = (int)T.row_stride;
   int* status = reinterpret_cast<int*>(A.ws);
 
+  // per-slot constants; FP32 folds log2(e) into ds/2 (see step_weights)
+  const Real kx = sizeof(Real) == 4 ? Real(1.4426950408889634) : Real(1);
   Real f1[R], f2[R], hds[R], wgt[R];
-  int itop[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const TaskRay& y = T.ray[UNI ? 0 : r];
-    f1[r] = (Real)y.f1; f2[r] = (Real)y.f2; hds[r] = (Real)y.hds; wgt[r] = (Real)y.w;
-    itop[r] = T.ray[r].itop;
+    const TaskRay RTS_CONST& y = T.ray[UNI ? 0 : r];
+    f1[r] = (Real)y.f1; f2[r] = (Real)y.f2; hds[r] = (Real)y.hds * kx; wgt[r] = (Real)y.w;
   }
-  // boundary values D = a S + b: boundary plane (planes are z), or the boundary
-  // row of the up (even slots, row 0) and down (odd slots, last row) rays
-  const Real pla = (Real)T.pl_a, plb = (Real)T.pl_b;
-  const Real bua = (Real)T.bu_a, bub = (Real)T.bu_b;
-  const Real bda = (Real)T.bd_a, bdb = (Real)T.bd_b;
   const bool zp = T.z_planes != 0;
   const int bc_up = zp ? -1 : 0, bc_dn = zp ? -1 : T.n_rows - 1;
 
@@ -239,9 +296,8 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, const Task& T, con
   const Real* Sv = T.transposed ? reinterpret_cast<const Real*>(A.ws) + T.s_off
                                 : reinterpret_cast<const Real*>(A.box[T.box].S) + T.s_off;
   Real* P = reinterpret_cast<Real*>(A.ws) + T.part_off;
-  Real* X = reinterpret_cast<Real*>(A.ws) + T.xbuf_off;
-  int* flags = reinterpret_cast<int*>(A.ws) + T.flag_off;
-  Real* Itop = reinterpret_cast<Real*>(A.box[T.box].I_top);
+  // exchange buffer of 64-bit words: [strip][parity][edge][slot][column][NW]
+  uint64_t* X = reinterpret_cast<uint64_t*>(A.ws) + T.xbuf_off;
 
   const int ns = T.strips;
   const bool per = T.row_periodic != 0;
@@ -251,259 +307,337 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, const Task& T, con
   const int row_hi = r0 + hr < T.n_rows ? r0 + hr : 0;
   const int st_lo = strip > 0 ? strip - 1 : ns - 1;
   const int st_hi = strip + 1 < ns ? strip + 1 : 0;
-  const int* flag_lo = has_lo ? flags + st_lo : nullptr;
-  const int* flag_hi = has_hi ? flags + st_hi : nullptr;
-  const int64_t xstride = (int64_t)R * W;  // one published edge row, all slots
+  const int xstride = R * W * NW;  // one published edge row, all slots
+  const int lrow = has_lo ? row_lo : r0, hrow = has_hi ? row_hi : r0;
 
   const int na = T.n_planes;
   const int q0 = T.sa > 0 ? 0 : na - 1;
   const int q_last = T.sa > 0 ? na - 1 : 0;
   const int nsteps = zp ? na - 1 : T.laps * na;
   const int out_from = zp ? 0 : (T.laps - 1) * na;
-  const int wl = wv > 0 ? wv - 1 : nwt - 1, wr = wv + 1 < nwt ? wv + 1 : 0;
-  const int cm = cc > 0 ? cc - 1 : W - 1, cp1 = cc + 1 < W ? cc + 1 : 0;
+  auto plane_of = [&](int t) {
+    return t < 0 ? (zp ? q0 : q_last) : (zp ? q0 + T.sa * (t + 1) : q0 + T.sa * (t % na));
+  };
+  Real* lc = lds + c * ST::NQP;                         // this column
+  const Real* lcc = lds + cc * ST::NQP;                 // this column (clamped)
+  const Real* lcm = lds + cm * ST::NQP;                 // column c-1
+  const Real* lcp = lds + cp1 * ST::NQP;                // column c+1
+  const unsigned ucc = (unsigned)cc, uc = (unsigned)c;
+  // uniform row pointer (a readfirstlane'd offset, so the compiler keeps one
+  // 32-bit lane offset instead of a 64-bit pointer per row)
+  auto urow = [&](auto* base, int off) __attribute__((always_inline)) {
+    return base + __builtin_amdgcn_readfirstlane(off);
+  };
 
-  // raw state of the last computed plane (index 0: lower halo, 1..H: rows, H+1: upper halo)
-  Real cx[H + 2], sx[H + 2], D[H][R];
+  // chi and S of a plane, rows -1..H (index 0..H+1)
+  Real ncx[H + 2], nsx[H + 2];
+  auto load_plane = [&](int q) __attribute__((always_inline)) {
+    const int qo = q * ps;
 #pragma unroll
-  for (int i = 0; i < H + 2; ++i) cx[i] = sx[i] = Real(0);
+    for (int i = 0; i < H; ++i) {
+      const int o = qo + (r0 + (FULL || i < hr ? i : 0)) * rs;
+      ncx[i + 1] = urow(chi, o)[ucc];
+      nsx[i + 1] = urow(Sv, o)[ucc];
+    }
+    ncx[0] = urow(chi, qo + lrow * rs)[ucc];
+    nsx[0] = urow(Sv, qo + lrow * rs)[ucc];
+    ncx[H + 1] = urow(chi, qo + hrow * rs)[ucc];
+    nsx[H + 1] = urow(Sv, qo + hrow * rs)[ucc];
+  };
+  // outputs of plane q from the new D and S: the compensated partial sum of
+  // w_r D_r and I_top
+  auto write_out = [&](int q, const Real (&Dn)[H][R]) __attribute__((always_inline)) {
+    if (!act) return;
+    const int qo = q * ps;
 #pragma unroll
-  for (int i = 0; i < H; ++i)
+    for (int i = 0; i < H; ++i) {
+      if (!FULL && i >= hr) break;
+      Real sum = wgt[0] * Dn[i][0], comp = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) D[i][r] = Real(0);
-
-  for (int t = -1; t < nsteps; ++t) {
-    const int q = t < 0 ? (zp ? q0 : q_last) : (zp ? q0 + T.sa * (t + 1) : q0 + T.sa * (t % na));
-    // ---- chi and S of plane q
-    Real ncx[H + 2], nsx[H + 2];
-    {
-      const int64_t base = (int64_t)q * ps + cc;
+      for (int r = 1; r < R; ++r) {
+        Real u, e;
+        two_sum(sum, wgt[r] * Dn[i][r], u, e);
+        sum = u;
+        comp += e;
+      }
+      urow(P, qo + (r0 + i) * rs)[uc] = sum + comp;
+    }
+    Real* Itop = reinterpret_cast<Real*>(A.box[T.box].I_top);
+    const int it_row = T.it_top - r0;
+    if (Itop && (zp ? (q == T.it_top) : (it_row >= 0 && it_row < hr))) {
 #pragma unroll
       for (int i = 0; i < H; ++i) {
-        const int64_t o = base + (int64_t)(r0 + (i < hr ? i : 0)) * rs;
-        ncx[i + 1] = chi[o];
-        nsx[i + 1] = Sv[o];
+        if (zp ? (!FULL && i >= hr) : (i != it_row)) continue;
+        const int gr = r0 + i;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int it = T.ray[r].itop;
+          if (it >= 0)
+            Itop[T.it_off + it * T.it_ray + (int64_t)q * T.itp + (int64_t)gr * T.itr +
+                 (int64_t)c * T.itc] = nsx[i + 1] + Dn[i][r];
+        }
       }
-      const int64_t ol = base + (int64_t)(has_lo ? row_lo : r0) * rs;
-      const int64_t oh = base + (int64_t)(has_hi ? row_hi : r0) * rs;
-      ncx[0] = chi[ol];
-      nsx[0] = Sv[ol];
-      ncx[H + 1] = chi[oh];
-      nsx[H + 1] = Sv[oh];
     }
-    if (t < 0) {
-      // first upwind plane: the boundary layer (planes are z) or the ghost plane
+  };
+  // D of unrolled plane u, kept for the adjoint's reverse sweep
+  auto store_d = [&](int u, const Real (&Dn)[H][R]) __attribute__((always_inline)) {
+    if (!A.store_d || !act) return;
+    Real* ds = reinterpret_cast<Real*>(A.ws) + T.dstore_off + (int64_t)u * R * T.n_rows * W;
 #pragma unroll
-      for (int i = 0; i < H + 2; ++i) { cx[i] = ncx[i]; sx[i] = nsx[i]; }
+    for (int i = 0; i < H; ++i) {
+      if (!FULL && i >= hr) break;
 #pragma unroll
-      for (int i = 0; i < H; ++i)
+      for (int r = 0; r < R; ++r) urow(ds, (r * T.n_rows + r0 + i) * W)[uc] = Dn[i][r];
+    }
+  };
+  // store the plane (ncx, nsx, Dn) as the next step's old plane
+  auto store_plane = [&](const Real (&Dn)[H][R]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < H + 2; ++j) {
+      lc[ST::qc(j)] = ncx[j];
+      lc[ST::qs(j)] = nsx[j];
+    }
+#pragma unroll
+    for (int i = 0; i < H; ++i)
+#pragma unroll
+      for (int r = 0; r < R; ++r) lc[ST::qd(i, r)] = Dn[i][r];
+  };
+
+  // ---- first upwind plane: the boundary layer (planes are z) or the ghost plane
+  {
+    load_plane(plane_of(-1));
+    const Real pa = (Real)T.pl_a, pb = (Real)T.pl_b;
+    const Real ua = (Real)T.bu_a, ub = (Real)T.bu_b, da = (Real)T.bd_a, db = (Real)T.bd_b;
+    Real D0[H][R];
+#pragma unroll
+    for (int i = 0; i < H; ++i)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool up = (r & 1) == 0;
+        const int br = up ? bc_up : bc_dn;
+        D0[i][r] = zp ? fmad(pa, nsx[i + 1], pb)
+                      : ((r0 + i == br) ? fmad(up ? ua : da, nsx[i + 1], up ? ub : db) : Real(0));
+      }
+    lds_barrier();  // the previous strip of this workgroup has finished with the LDS
+    store_plane(D0);
+    if (zp) write_out(q0, D0);
+    if (zp) store_d(0, D0);
+    if (nsteps > 0) load_plane(plane_of(0));
+    lds_barrier();
+  }
+
+  // neighbours' tagged edge-row words for the next step: issued at the end of
+  // a step (the neighbours publish early in theirs), checked in the next
+  uint64_t hw[R][2][NW];
+  auto halo_issue = [&](int t) __attribute__((always_inline)) {
+    const int par = (t - 1) & 1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool lower = (r & 1) == 0;  // even slots look at the lower halo, odd at the upper
+      const bool has = lower ? has_lo : has_hi;
+      const int xoff = (((lower ? st_lo : st_hi) * 2 + par) * 2 + (lower ? 1 : 0)) * xstride;
+      const uint64_t* rowp = urow(X, xoff + r * W * NW);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const unsigned col = (unsigned)(k == 0 ? cc : (r < 2 ? cm : cp1)) * NW;
+#pragma unroll
+        for (int x = 0; x < NW; ++x) hw[r][k][x] = has ? ld_dev(rowp + col + x) : 0ull;
+      }
+    }
+  };
+  // wait until every word of this step is fresh (re-polling, bounded by the watchdog)
+  auto halo_wait = [&](int t) __attribute__((always_inline)) {
+    const uint32_t tag = (uint32_t)t;
+    auto all_fresh = [&]() __attribute__((always_inline)) {
+      bool ok = true;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool has = (r & 1) == 0 ? has_lo : has_hi;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) ok = ok && (!has || TG::fresh(hw[r][k], tag));
+      }
+      return ok;
+    };
+    if (__ballot(!all_fresh()) == 0) return;
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+      __builtin_amdgcn_s_sleep(1);
+      halo_issue(t);
+      if (__ballot(!all_fresh()) == 0) break;
+      if (__builtin_amdgcn_readfirstlane(ld_dev(status)) != 0) break;
+      if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > A.timeout_ticks) {
+        st_dev(status, 1);
+        break;
+      }
+    }
+  };
+
+  // ---- the march
+  for (int t = 0; t < nsteps; ++t) {
+    const int q = plane_of(t);
+    if (t > 0) halo_wait(t);
+
+    // column interpolation of old LDS row j (own rows, 1..H, carry D of row j-1)
+    auto interp = [&](int j, bool own, LR& o) __attribute__((always_inline)) {
+      const Real ca = lcc[ST::qc(j)], cl = lcm[ST::qc(j)], cr = lcp[ST::qc(j)];
+      const Real sa = lcc[ST::qs(j)], sl = lcm[ST::qs(j)], sr = lcp[ST::qs(j)];
+#pragma unroll
+      for (int v = 0; v < NC; ++v) {
+        const bool lft = UNI ? (v == 0) : (v < 2);
+        o.c[v] = lerp(ca, lft ? cl : cr, f1[UNI ? 2 * v : v]);
+        o.s[v] = lerp(sa, lft ? sl : sr, f1[UNI ? 2 * v : v]);
+      }
+      if (own) {
+        const int i = j - 1 >= 0 ? (j - 1 < H ? j - 1 : H - 1) : 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const bool up = (r & 1) == 0;
-          const int br = up ? bc_up : bc_dn;
-          D[i][r] = zp ? fmad(pla, sx[i + 1], plb)
-                       : ((r0 + i == br) ? fmad(up ? bua : bda, sx[i + 1], up ? bub : bdb) : Real(0));
-        }
-    } else {
-      const int pold = (phase - 1) & 1;  // table of the previous plane
-      const Real* tl = tab + ((pold * 2 * 16 + wl * 2 + 1) * NS);   // left wave, last lane
-      const Real* trt = tab + ((pold * 2 * 16 + wr * 2 + 0) * NS);  // right wave, first lane
-      const Real* t0 = tab + ((pold * 2 * 16 + 0 * 2 + 0) * NS);    // column 0
-      auto left = [&](int k, Real v) { return dpp_shr(tl[k], v); };
-      auto right = [&](int k, Real v) {
-        const Real r = dpp_shl(trt[k], v);
-        return c == W - 1 ? t0[k] : r;
-      };
-      // column-interpolated chi and S of old row index idx (NC variants)
-      auto lcs = [&](int idx, Real* lc, Real* ls) {
-        const Real cl = left(idx, cx[idx]), cr = right(idx, cx[idx]);
-        const Real sl = left(H + 2 + idx, sx[idx]), sr = right(H + 2 + idx, sx[idx]);
-#pragma unroll
-        for (int v = 0; v < NC; ++v) {
-          const bool lft = UNI ? (v == 0) : (v < 2);
-          lc[v] = lerp(cx[idx], lft ? cl : cr, f1[v]);
-          ls[v] = lerp(sx[idx], lft ? sl : sr, f1[v]);
-        }
-      };
-      auto ldd = [&](int i, Real* ld) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int k = 2 * (H + 2) + i * R + r;
-          const Real n = r < 2 ? left(k, D[i][r]) : right(k, D[i][r]);
-          ld[r] = lerp(D[i][r], n, f1[r]);
-        }
-      };
-      // halo rows: column-interpolated chi and S, and D
-      Real hlc[NC], hls[NC], huc[NC], hus[NC], hld[R], hud[R];
-      lcs(0, hlc, hls);
-      lcs(H + 1, huc, hus);
-      if (t == 0) {
-        // first plane: the halo D is known locally, an affine function of S
-        // (the column interpolation commutes with it: its weights sum to 1)
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int v = UNI ? (r < 2 ? 0 : 1) : r;
-          const bool up = (r & 1) == 0;
-          const int br = up ? bc_up : bc_dn;
-          const Real a = up ? bua : bda, b = up ? bub : bdb;
-          hld[r] = zp ? fmad(pla, hls[v], plb) : (row_lo == br ? fmad(a, hls[v], b) : Real(0));
-          hud[r] = zp ? fmad(pla, hus[v], plb) : (row_hi == br ? fmad(a, hus[v], b) : Real(0));
+          const Real a = lcc[ST::qd(i, r)], n = (r < 2 ? lcm : lcp)[ST::qd(i, r)];
+          o.d[r] = lerp(a, n, f1[r]);
         }
       } else {
-        wait_flags(flag_lo, flag_hi, t, status, A.timeout_ticks);
-        const int par = (t - 1) & 1;
-        const Real* xl = X + ((int64_t)(st_lo * 2 + par) * 2 + 1) * xstride;
-        const Real* xh = X + ((int64_t)(st_hi * 2 + par) * 2 + 0) * xstride;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int cn = r < 2 ? cm : cp1;
-          // only the slots whose upwind row is the halo need it
-          if ((r & 1) == 0) {
-            const Real a = has_lo ? ld_dev(xl + r * W + cc) : Real(0);
-            const Real b = has_lo ? ld_dev(xl + r * W + cn) : Real(0);
-            hld[r] = lerp(a, b, f1[r]);
-            hud[r] = Real(0);
-          } else {
-            const Real a = has_hi ? ld_dev(xh + r * W + cc) : Real(0);
-            const Real b = has_hi ? ld_dev(xh + r * W + cn) : Real(0);
-            hud[r] = lerp(a, b, f1[r]);
-            hld[r] = Real(0);
-          }
-        }
+        for (int r = 0; r < R; ++r) o.d[r] = Real(0);
       }
-      // ---- formal solution, row by row, with a sliding window of the
-      // interpolated old rows i-1 (p*), i (k*) and i+1 (n*)
-      Real pc[NC], pS[NC], pd[R], kc[NC], kS[NC], kd[R], nc[NC], nS[NC], nd[R];
+    };
+    // the formal solution of row i from the interpolated old rows i-1, i, i+1
+    auto solve_row = [&](int i, const LR& lp, const LR& lk, const LR& ln, Real* out)
+        __attribute__((always_inline)) {
+      const Real cpv = ncx[i + 1], spv = nsx[i + 1];
 #pragma unroll
-      for (int v = 0; v < NC; ++v) { pc[v] = hlc[v]; pS[v] = hls[v]; }
-#pragma unroll
-      for (int r = 0; r < R; ++r) pd[r] = hld[r];
-      lcs(1, kc, kS);
-      ldd(0, kd);
-#pragma unroll
-      for (int i = 0; i < H; ++i) {
-        if (i >= hr) break;
-        const bool last = (i == hr - 1);
-        if (last || i + 1 >= H) {
-#pragma unroll
-          for (int v = 0; v < NC; ++v) { nc[v] = huc[v]; nS[v] = hus[v]; }
-#pragma unroll
-          for (int r = 0; r < R; ++r) nd[r] = hud[r];
-        } else {
-          lcs(i + 2 < H + 2 ? i + 2 : H + 1, nc, nS);
-          ldd(i + 1 < H ? i + 1 : H - 1, nd);
-        }
-        const int gr = r0 + i;
-        const Real cpv = ncx[i + 1], spv = nsx[i + 1];
+      for (int r = 0; r < R; ++r) {
+        const int v = UNI ? (r < 2 ? 0 : 1) : r;
+        const bool up = (r & 1) == 0;
+        const Real bc = lerp(lk.c[v], up ? lp.c[v] : ln.c[v], f2[r]);
+        const Real bs = lerp(lk.s[v], up ? lp.s[v] : ln.s[v], f2[r]);
+        const Real bd = lerp(lk.d[r], up ? lp.d[r] : ln.d[r], f2[r]);
+        Real e, cw;
+        step_weights(hds[r] * (cpv + bc), e, cw);
+        out[r] = fmad(e, bd, cw * (bs - spv));
+      }
+      const int gr = r0 + i;  // boundary rows (rows are z): set, not integrated
+      if (gr == bc_up) {
+        const Real v = fmad((Real)T.bu_a, spv, (Real)T.bu_b);
+        out[0] = v; out[2] = v;
+      }
+      if (gr == bc_dn) {
+        const Real v = fmad((Real)T.bd_a, spv, (Real)T.bd_b);
+        out[1] = v; out[3] = v;
+      }
+    };
+    // halo D of the slots that look at the halo row (even: lower, odd: upper).
+    // On the first plane it is local, an affine function of the halo's S (the
+    // column interpolation commutes with it); later it is the neighbour's
+    // edge row of the previous plane, a tagged word.
+    auto halo_d = [&](bool lower, LR& h) __attribute__((always_inline)) {
+      const bool has = lower ? has_lo : has_hi;
+      const int hrow_g = lower ? row_lo : row_hi;
+      if (t == 0) {
+        const Real pa = (Real)T.pl_a, pb = (Real)T.pl_b;
+        const Real ua = (Real)T.bu_a, ub = (Real)T.bu_b, da = (Real)T.bd_a, db = (Real)T.bd_b;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+          if (((r & 1) == 0) != lower) continue;
           const int v = UNI ? (r < 2 ? 0 : 1) : r;
           const bool up = (r & 1) == 0;
-          const Real uc = up ? pc[v] : nc[v];
-          const Real us = up ? pS[v] : nS[v];
-          const Real ud = up ? pd[r] : nd[r];
-          const Real bc = lerp(kc[v], uc, f2[r]);
-          const Real bs = lerp(kS[v], us, f2[r]);
-          const Real bd = lerp(kd[r], ud, f2[r]);
-          const Real x = hds[r] * (cpv + bc);
-          const Real e = rts_exp_neg(x);
-          const Real cw = rts_cw(x, e);
-          const Real dn = fmad(e, bd, cw * (bs - spv));
           const int br = up ? bc_up : bc_dn;
-          D[i][r] = (gr == br) ? fmad(up ? bua : bda, spv, up ? bub : bdb) : dn;
+          h.d[r] = !has ? Real(0)
+                        : zp ? fmad(pa, h.s[v], pb)
+                             : (hrow_g == br ? fmad(up ? ua : da, h.s[v], up ? ub : db) : Real(0));
         }
-#pragma unroll
-        for (int v = 0; v < NC; ++v) { pc[v] = kc[v]; pS[v] = kS[v]; kc[v] = nc[v]; kS[v] = nS[v]; }
-#pragma unroll
-        for (int r = 0; r < R; ++r) { pd[r] = kd[r]; kd[r] = nd[r]; }
+        return;
       }
+      if (!has) return;
 #pragma unroll
-      for (int i = 0; i < H + 2; ++i) { cx[i] = ncx[i]; sx[i] = nsx[i]; }
-      // ---- publish the edge rows for the neighbouring strips
-      if (act) {
-        Real* xe = X + ((int64_t)(strip * 2 + (t & 1)) * 2) * xstride;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          Real top = D[0][r];
-#pragma unroll
-          for (int i = 1; i < H; ++i)
-            if (i == hr - 1) top = D[i][r];
-          if ((r & 1) == 1) st_dev(xe + r * W + c, D[0][r]);        // lower neighbour: its odd slots
-          if ((r & 1) == 0) st_dev(xe + xstride + r * W + c, top);  // upper neighbour: its even slots
-        }
+      for (int r = 0; r < R; ++r) {
+        if (((r & 1) == 0) != lower) continue;
+        h.d[r] = lerp(TG::value(hw[r][0]), TG::value(hw[r][1]), f1[r]);
       }
-      vmem_drain();
-    }
-    // ---- outputs of plane q: partial sum of w_r D_r (compensated) and I_top
-    if (act && (t < 0 ? zp : t >= out_from)) {
-#pragma unroll
-      for (int i = 0; i < H; ++i) {
-        if (i >= hr) break;
-        Real s = wgt[0] * D[i][0], comp = 0;
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          Real u, e;
-          two_sum(s, wgt[r] * D[i][r], u, e);
-          s = u;
-          comp += e;
-        }
-        P[(int64_t)q * ps + (int64_t)(r0 + i) * rs + c] = s + comp;
-        if (Itop) {
-          const int gr = r0 + i;
-          if (zp ? (q == T.it_top) : (gr == T.it_top)) {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-              if (itop[r] >= 0)
-                Itop[T.it_off + itop[r] * T.it_ray + (int64_t)q * T.itp + (int64_t)gr * T.itr +
-                     (int64_t)c * T.itc] = sx[i + 1] + D[i][r];
-          }
-        }
-      }
-    }
-    // ---- LDS edge table of this plane, then the step barrier
+    };
+
+    Real Dn[H][R];
+    // ---- edge rows first, published for the neighbouring strips
     {
-      const int par = phase & 1;
-      if (lane == 0 || lane == last_lane) {
-        Real* te = tab + ((par * 2 * 16 + wv * 2 + (lane == 0 ? 0 : 1)) * NS);
+      LR lo, k0, n0;
+      interp(0, false, lo);
+      halo_d(true, lo);
+      interp(1, true, k0);
+      if (hr == 1) {
+        interp(H + 1, false, n0);
+        halo_d(false, n0);
+      } else {
+        interp(2, true, n0);
+      }
+      solve_row(0, lo, k0, n0, Dn[0]);
+    }
 #pragma unroll
-        for (int i = 0; i < H + 2; ++i) {
-          te[i] = cx[i];
-          te[H + 2 + i] = sx[i];
-        }
+    for (int i = 1; i < H; ++i) {
+      if (!(FULL ? (i == H - 1) : (i == hr - 1))) continue;
+      LR lp, lk, up_;
+      interp(i, true, lp);
+      interp(i + 1, true, lk);
+      interp(H + 1, false, up_);
+      halo_d(false, up_);
+      solve_row(i, lp, lk, up_, Dn[i]);
+    }
+    if (act) {
+      const int xe = ((strip * 2 + (t & 1)) * 2) * xstride;
+      const uint32_t tag = (uint32_t)(t + 1);
+      const unsigned col = uc * NW;
 #pragma unroll
-        for (int i = 0; i < H; ++i)
+      for (int r = 0; r < R; ++r) {
+        Real top = Dn[0][r];
 #pragma unroll
-          for (int r = 0; r < R; ++r) te[2 * (H + 2) + i * R + r] = D[i][r];
-        if (lane == 0 && last_lane == 0) {  // one-lane wave: both sides
-          Real* t1 = tab + ((par * 2 * 16 + wv * 2 + 1) * NS);
-#pragma unroll
-          for (int k = 0; k < NS; ++k) t1[k] = te[k];
-        }
+        for (int i = 1; i < H; ++i)
+          if (FULL ? (i == H - 1) : (i == hr - 1)) top = Dn[i][r];
+        if ((r & 1) == 1) TG::put(urow(X, xe + r * W * NW) + col, Dn[0][r], tag);          // lower: odd slots
+        if ((r & 1) == 0) TG::put(urow(X, xe + xstride + r * W * NW) + col, top, tag);  // upper: even slots
       }
     }
-    __syncthreads();
-    if (t >= 0 && threadIdx.x == 0) st_dev(flags + strip, t + 1);
-    ++phase;
+    // ---- interior rows, sliding window of interpolated old rows
+    if (FULL ? (H > 2) : (hr > 2)) {
+      LR a, b, d;
+      interp(1, true, a);
+      interp(2, true, b);
+#pragma unroll
+      for (int i = 1; i < H - 1; ++i) {
+        if (!FULL && i >= hr - 1) break;
+        interp(i + 2, true, d);
+        solve_row(i, a, b, d, Dn[i]);
+        a = b;
+        b = d;
+      }
+    }
+    lds_barrier();  // every thread has read the old plane
+    store_plane(Dn);
+    if (t >= out_from) write_out(q, Dn);
+    store_d(zp ? t + 1 : t, Dn);
+    if (t + 1 < nsteps) {
+      load_plane(plane_of(t + 1));
+      halo_issue(t + 1);
+    }
+    lds_barrier();  // the new plane is complete
   }
 }
 
 template <class Real, int H, bool UNI>
 __global__ __launch_bounds__(1024) void rts_sweep(SweepArgs A) {
   extern __shared__ char smem_raw[];
-  Real* tab = reinterpret_cast<Real*>(smem_raw);
+  Real* lds = reinterpret_cast<Real*>(smem_raw);
   __shared__ int sh_ticket;
   WsHeader* hdr = reinterpret_cast<WsHeader*>(A.ws);
-  int phase = 0;
   for (;;) {
     if (threadIdx.x == 0) sh_ticket = atomicAdd(&hdr->ticket, 1);
     __syncthreads();
     const int tk = __builtin_amdgcn_readfirstlane(sh_ticket);
     __syncthreads();
     if (tk >= A.total_strips) return;
+    CInt* queue = (CInt*)(uintptr_t)A.queue;
     int qi = 0;
-    while (qi + 1 < A.ntasks && A.queue[2 * (qi + 1)] <= tk) ++qi;
-    const Task& T = A.tasks[A.queue[2 * qi + 1]];
-    run_strip<Real, H, UNI>(A, T, tk - A.queue[2 * qi], tab, phase);
+    while (qi + 1 < A.ntasks && queue[2 * (qi + 1)] <= tk) ++qi;
+    CTask& T = ((CTask*)(uintptr_t)A.tasks)[queue[2 * qi + 1]];
+    const int strip = tk - queue[2 * qi];
+    if ((strip + 1) * T.rows_per_strip <= T.n_rows) run_strip<Real, H, UNI, true>(A, T, strip, lds);
+    else run_strip<Real, H, UNI, false>(A, T, strip, lds);
   }
 }
 
@@ -565,6 +699,280 @@ __global__ __launch_bounds__(256) void rts_reduce(const char* __restrict__ ws,
   }
 }
 
+// ---------------------------------------------------------------------------
+// adjoint: reverse sweep, one launch per unrolled plane (all tasks at once).
+//
+// Forward recursion of cell q of unrolled plane u, slot r: with B the
+// bilinear interpolation at the upwind point in plane u-1,
+//   x = ds/2 (chi_q + B chi),  e = exp(-x),  c = (1 - e)/x,
+//   D_q = e B(D) + c (B(S) - S_q).
+// With lambda_q = dL/dD_q, reverse mode gives for every integrated cell
+//   a_q = e lambda_q            (flows to the upwind D),
+//   b_q = c lambda_q            (flows to the upwind S; -b_q to S_q),
+//   g_q = ds/2 lambda_q dD/dx   (flows to chi_q and the upwind chi),
+//   dD/dx = -e B(D) + c' (B(S) - S_q),  c' = dc/dx = (e - c)/x,
+// and a cell of plane u collects from plane u+1 with the transposed
+// (mirrored) bilinear weights B^T:
+//   lambda_q = seed_q + B^T a,  dL/dS_q += B^T b - b_q,  dL/dchi_q += B^T g + g_q.
+// A boundary cell (D = a_bc S + b_bc) adds a_bc lambda_q to dL/dS_q and
+// passes nothing upwind; the ghost plane of a periodic sweep (u = -1) is such
+// a plane, with D = 0 off the boundary row.  The seed of a cell in the last
+// lap is w_r (4 pi qweight chi gQ + gJ) (+ gItop in the top layer).
+
+// c' = dc/dx, power series below x = 0.1 (sum_{n>=1} n (-x)^(n-1) / (n+1)!, with sign)
+__device__ inline float rts_dcw(float x, float e, float c) {
+  const float s =
+      fmaf(fmaf(fmaf(fmaf(x, -5.f / 720.f, 4.f / 120.f), x, -3.f / 24.f), x, 2.f / 6.f), x, -0.5f);
+  return x < 0.1f ? s : (e - c) * __builtin_amdgcn_rcpf(x);
+}
+__device__ inline double rts_dcw(double x, double e, double c) {
+  double s = -11.0 / 479001600.0;
+  s = fma(s, x, 10.0 / 39916800.0);
+  s = fma(s, x, -9.0 / 3628800.0);
+  s = fma(s, x, 8.0 / 362880.0);
+  s = fma(s, x, -7.0 / 40320.0);
+  s = fma(s, x, 6.0 / 5040.0);
+  s = fma(s, x, -5.0 / 720.0);
+  s = fma(s, x, 4.0 / 120.0);
+  s = fma(s, x, -3.0 / 24.0);
+  s = fma(s, x, 2.0 / 6.0);
+  s = fma(s, x, -0.5);
+  if (x < 0.1) return s;
+  return (e - c) / x;
+}
+
+typedef const AdjTask RTS_CONST CAdjTask;
+
+// One cell of one task per thread; every task's cells start at a multiple of
+// the block size, so a block belongs to one task.
+template <class Real>
+__global__ __launch_bounds__(256) void rts_adj_plane(AdjArgs A) {
+  CAdjTask* ats = (CAdjTask*)(uintptr_t)A.atasks;
+  const int blk0 = blockIdx.x * blockDim.x;
+  int ai = 0;
+  while (ai + 1 < A.natasks && ats[ai + 1].cell0 <= blk0) ++ai;
+  CAdjTask& AT = ats[ai];
+  CTask& T = ((CTask*)(uintptr_t)A.tasks)[AT.task];
+  constexpr int R = kMaxRaysPerTask;
+  const int U = T.n_unrolled;
+  const int u = U - 1 - A.k;
+  if (u < AT.u_init) return;
+  const int cell = blk0 + (int)threadIdx.x - AT.cell0;
+  if (cell >= AT.ncell) return;
+  const int nr = T.n_rows, W = T.n_cols;
+  const int i = cell / W, c = cell - i * W;
+  const int na = T.n_planes;
+  const bool zp = T.z_planes != 0;
+  const int q0 = T.sa > 0 ? 0 : na - 1, q_last = T.sa > 0 ? na - 1 : 0;
+  auto plane_of = [&](int uu) { return uu < 0 ? q_last : q0 + T.sa * (zp ? uu : uu % na); };
+  const int qp = plane_of(u);
+  const int ps = (int)T.plane_stride, rs = (int)T.row_stride;
+  Real* ws = reinterpret_cast<Real*>(A.ws);
+  const Real* chi = ws + T.chi_off;
+  const Real* Sv = T.transposed ? ws + T.s_off : reinterpret_cast<const Real*>(A.S[T.box]) + T.s_off;
+  Real* st = ws + AT.state_off;
+  const int64_t pc = (int64_t)nr * W;  // cells of one plane
+  // state of unrolled plane v: [v & 1][slot][quantity a, b, g][row][col]
+  auto stp = [&](int v, int r, int qty) { return st + ((int64_t)(((v & 1) * R + r) * 3 + qty)) * pc; };
+  auto wrapc = [&](int x) { return x < 0 ? x + W : (x >= W ? x - W : x); };
+  const bool rowper = T.row_periodic != 0;
+  const int phys = qp * ps + i * rs + c;  // this cell, in the task's array layout
+  const Real s_q = Sv[phys], chi_q = chi[phys];
+  const bool last_lap = u >= 0 && (zp || u >= (T.laps - 1) * na);
+  const Real seed = last_lap ? (ws + AT.seed_off)[phys] : Real(0);
+  const bool top_cell = last_lap && (zp ? qp == T.it_top : i == T.it_top);
+  const Real* gi = reinterpret_cast<const Real*>(A.gItop[T.box]);
+  Real gs = 0, gc = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const TaskRay RTS_CONST& y = T.ray[r];
+    const Real f1 = (Real)y.f1, f2 = (Real)y.f2, hds = (Real)y.hds;
+    const int sc = r < 2 ? -1 : 1, sr = (r & 1) == 0 ? -1 : 1;  // upwind column / row offsets
+    const bool up = (r & 1) == 0;
+    // B^T of plane u+1: downwind cells at rows i, i - sr and columns c, c - sc
+    Real ta = 0, tb = 0, tg = 0;
+    if (u + 1 < U) {
+      const int c1 = wrapc(c - sc);
+      int i1 = i - sr;
+      bool ok1 = true;
+      if (rowper) i1 = i1 < 0 ? i1 + nr : (i1 >= nr ? i1 - nr : i1);
+      else ok1 = i1 >= 0 && i1 < nr;
+      Real v[3];
+#pragma unroll
+      for (int qty = 0; qty < 3; ++qty) {
+        const Real* sp = stp(u + 1, r, qty);
+        const Real x00 = sp[i * W + c], x10 = sp[i * W + c1];
+        const Real x01 = ok1 ? sp[i1 * W + c] : Real(0), x11 = ok1 ? sp[i1 * W + c1] : Real(0);
+        v[qty] = lerp(lerp(x00, x10, f1), lerp(x01, x11, f1), f2);
+      }
+      ta = v[0]; tb = v[1]; tg = v[2];
+    }
+    Real lam = ta;
+    if (last_lap) {
+      lam = fmad((Real)y.w, seed, lam);
+      if (gi && top_cell && y.itop >= 0)
+        lam += gi[T.it_off + y.itop * T.it_ray + (int64_t)qp * T.itp + (int64_t)i * T.itr +
+                  (int64_t)c * T.itc];
+    }
+    const int br = zp ? -2 : (up ? 0 : nr - 1);  // this slot's boundary row
+    const Real bca = (Real)(up ? T.bu_a : T.bd_a), bcb = (Real)(up ? T.bu_b : T.bd_b);
+    Real a = 0, b = 0, g = 0;
+    if (u < 0) {
+      if (i == br) gs = fmad(bca, lam, gs);
+    } else if (zp ? u == 0 : i == br) {
+      gs = fmad(zp ? (Real)T.pl_a : bca, lam, gs);
+    } else {
+      // the forward step of this cell, recomputed from plane u-1
+      const int qu = plane_of(u - 1);
+      const int cu = wrapc(c + sc);
+      int iu = i + sr;
+      if (rowper) iu = iu < 0 ? iu + nr : (iu >= nr ? iu - nr : iu);
+      const int o0 = qu * ps + i * rs, o1 = qu * ps + iu * rs;
+      const Real cb = lerp(lerp(chi[o0 + c], chi[o0 + cu], f1), lerp(chi[o1 + c], chi[o1 + cu], f1), f2);
+      const Real sb = lerp(lerp(Sv[o0 + c], Sv[o0 + cu], f1), lerp(Sv[o1 + c], Sv[o1 + cu], f1), f2);
+      Real db;
+      if (u >= 1) {
+        const Real* Dp = ws + T.dstore_off + ((int64_t)(u - 1) * R + r) * pc;
+        db = lerp(lerp(Dp[i * W + c], Dp[i * W + cu], f1), lerp(Dp[iu * W + c], Dp[iu * W + cu], f1), f2);
+      } else {
+        // upwind is the ghost plane: D = a_bc S + b_bc on the boundary row, else 0
+        const Real d00 = i == br ? fmad(bca, Sv[o0 + c], bcb) : Real(0);
+        const Real d10 = i == br ? fmad(bca, Sv[o0 + cu], bcb) : Real(0);
+        const Real d01 = iu == br ? fmad(bca, Sv[o1 + c], bcb) : Real(0);
+        const Real d11 = iu == br ? fmad(bca, Sv[o1 + cu], bcb) : Real(0);
+        db = lerp(lerp(d00, d10, f1), lerp(d01, d11, f1), f2);
+      }
+      const Real x = hds * (chi_q + cb);
+      const Real e = rts_exp_neg(x);
+      const Real cw = rts_cw(x, e);
+      const Real dc = rts_dcw(x, e, cw);
+      a = e * lam;
+      b = cw * lam;
+      g = hds * lam * fmad(-e, db, dc * (sb - s_q));
+      gs -= b;
+      gc += g;
+    }
+    gs += tb;
+    gc += tg;
+    if (u >= 0) {
+      stp(u, r, 0)[cell] = a;
+      stp(u, r, 1)[cell] = b;
+      stp(u, r, 2)[cell] = g;
+    }
+  }
+  Real* GS = ws + AT.gs_off;
+  Real* GC = ws + AT.gc_off;
+  GS[phys] += gs;
+  GC[phys] += gc;
+}
+
+// Seeds of one band, w_r aside: 4 pi qweight chi gQ + gJ, in [z][y][x] and
+// in the [x][z][y] layout of the x-sweeps.
+template <class Real>
+__global__ __launch_bounds__(256) void rts_adj_seed(const Real* __restrict__ kappa,
+                                                   const Real* __restrict__ rho,
+                                                   const double* __restrict__ gQ,
+                                                   const Real* __restrict__ gJ,
+                                                   Real* __restrict__ seed, Real* __restrict__ seedT,
+                                                   double qf, int nx, int ny, int nz) {
+  __shared__ Real tl[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32, z = blockIdx.z;
+  for (int i = 0; i < 4; ++i) {
+    const int y = y0 + ty + 8 * i, x = x0 + tx;
+    if (x < nx && y < ny) {
+      const int64_t p = ((int64_t)z * ny + y) * nx + x;
+      double v = 0;
+      if (gQ) v = qf * (double)(kappa[p] * rho[p]) * gQ[p];
+      if (gJ) v += (double)gJ[p];
+      seed[p] = (Real)v;
+      tl[ty + 8 * i][tx] = (Real)v;
+    }
+  }
+  __syncthreads();
+  for (int i = 0; i < 4; ++i) {
+    const int x = x0 + ty + 8 * i, y = y0 + tx;
+    if (x < nx && y < ny) seedT[((int64_t)x * nz + z) * ny + y] = tl[tx][ty + 8 * i];
+  }
+}
+
+// Gradients of one box: the task partials summed in a fixed order (FP64),
+// plus the direct terms dL/dS_b += gJ_b (+ sum_r gItop_b,r in the top layer)
+// and dL/dchi_b += 4 pi qweight_b (J_b - S_b) gQ, where J_b - S_b is the sum
+// of the forward partials.
+template <class Real>
+__global__ __launch_bounds__(256) void rts_adj_reduce(const char* __restrict__ ws,
+                                                     const Task* __restrict__ tasks,
+                                                     const AdjTask* __restrict__ atasks, BoxGeo G,
+                                                     const double* __restrict__ gQ,
+                                                     const Real* __restrict__ gJ,
+                                                     const Real* __restrict__ gItop,
+                                                     Real* __restrict__ dS, Real* __restrict__ dchi) {
+  __shared__ Real t0[32][33], t1[32][33], t2[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32, z = blockIdx.z;
+  const int nx = G.nx, ny = G.ny, nz = G.nz;
+  const int64_t N = (int64_t)nx * ny * nz;
+  const Real* w = reinterpret_cast<const Real*>(ws);
+  for (int b = 0; b < G.nbands; ++b) {
+    double as[4] = {0, 0, 0, 0}, ac[4] = {0, 0, 0, 0}, aj[4] = {0, 0, 0, 0};
+    for (int k = 0; k < G.tasks_per_band; ++k) {
+      const int ti = G.task0 + b * G.tasks_per_band + k;
+      const Task& T = tasks[ti];
+      const AdjTask& AT = atasks[ti];
+      const Real* gs = w + AT.gs_off;
+      const Real* gc = w + AT.gc_off;
+      const Real* pj = w + T.part_off;
+      if (!T.transposed) {
+        for (int i = 0; i < 4; ++i) {
+          const int y = y0 + ty + 8 * i, x = x0 + tx;
+          if (x < nx && y < ny) {
+            const int64_t p = ((int64_t)z * ny + y) * nx + x;
+            as[i] += (double)gs[p];
+            ac[i] += (double)gc[p];
+            aj[i] += (double)pj[p];
+          }
+        }
+      } else {
+        __syncthreads();
+        for (int i = 0; i < 4; ++i) {
+          const int x = x0 + ty + 8 * i, y = y0 + tx;
+          if (x < nx && y < ny) {
+            const int64_t p = ((int64_t)x * nz + z) * ny + y;
+            t0[ty + 8 * i][tx] = gs[p];
+            t1[ty + 8 * i][tx] = gc[p];
+            t2[ty + 8 * i][tx] = pj[p];
+          }
+        }
+        __syncthreads();
+        for (int i = 0; i < 4; ++i) {
+          const int y = y0 + ty + 8 * i, x = x0 + tx;
+          if (x < nx && y < ny) {
+            as[i] += (double)t0[tx][ty + 8 * i];
+            ac[i] += (double)t1[tx][ty + 8 * i];
+            aj[i] += (double)t2[tx][ty + 8 * i];
+          }
+        }
+      }
+    }
+    const double qf = 4.0 * 3.14159265358979323846 * G.qweight[b];
+    for (int i = 0; i < 4; ++i) {
+      const int y = y0 + ty + 8 * i, x = x0 + tx;
+      if (x < nx && y < ny) {
+        const int64_t p = ((int64_t)z * ny + y) * nx + x;
+        double vs = as[i], vc = ac[i];
+        if (gJ) vs += (double)gJ[b * N + p];
+        if (gItop && z == nz - 1)
+          for (int r = 0; r < G.n_up; ++r)
+            vs += (double)gItop[(((int64_t)b * G.n_up + r) * ny + y) * nx + x];
+        if (gQ) vc += qf * aj[i] * gQ[p];
+        dS[b * N + p] = (Real)vs;
+        dchi[b * N + p] = (Real)vc;
+      }
+    }
+  }
+}
+
 // DPP lane-layout self test: out[i] = in[i-1] (shr, lane 0 keeps -1) and
 // out[64 + i] = in[i+1] (shl, lane 63 keeps -2) for one wave.
 __global__ void rts_dpp_selftest(const float* in, float* out) {
@@ -602,8 +1010,7 @@ hipError_t launch_zero(int* p, int64_t n, hipStream_t st) {
 
 template <class Real, int H>
 size_t sweep_lds_bytes(int threads) {
-  (void)threads;
-  return (size_t)2 * 16 * 2 * Strip<Real, H>::NS * sizeof(Real);
+  return (size_t)Strip<Real, H>::NQP * threads * sizeof(Real);
 }
 
 template <class Real, int H, bool UNI>
@@ -625,6 +1032,33 @@ hipError_t launch_reduce(const char* ws, const Task* tasks, const BoxGeo& g, con
   return hipGetLastError();
 }
 
+template <class Real>
+hipError_t launch_adj_plane(const AdjArgs& a, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(rts_adj_plane<Real>, dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <class Real>
+hipError_t launch_adj_seed(const void* kappa, const void* rho, const double* gQ, const void* gJ,
+                           void* seed, void* seedT, double qf, int nx, int ny, int nz,
+                           hipStream_t st) {
+  dim3 grid((nx + 31) / 32, (ny + 31) / 32, nz);
+  hipLaunchKernelGGL(rts_adj_seed<Real>, grid, dim3(256), 0, st, (const Real*)kappa,
+                     (const Real*)rho, gQ, (const Real*)gJ, (Real*)seed, (Real*)seedT, qf, nx, ny,
+                     nz);
+  return hipGetLastError();
+}
+
+template <class Real>
+hipError_t launch_adj_reduce(const char* ws, const Task* tasks, const AdjTask* atasks,
+                             const BoxGeo& g, const double* gQ, const void* gJ, const void* gItop,
+                             void* dS, void* dchi, hipStream_t st) {
+  dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, g.nz);
+  hipLaunchKernelGGL(rts_adj_reduce<Real>, grid, dim3(256), 0, st, ws, tasks, atasks, g, gQ,
+                     (const Real*)gJ, (const Real*)gItop, (Real*)dS, (Real*)dchi);
+  return hipGetLastError();
+}
+
 hipError_t launch_dpp_selftest(const float* in, float* out, hipStream_t st) {
   hipLaunchKernelGGL(rts_dpp_selftest, dim3(1), dim3(64), 0, st, in, out);
   return hipGetLastError();
@@ -639,6 +1073,16 @@ template hipError_t launch_reduce<float>(const char*, const Task*, const BoxGeo&
                                          hipStream_t);
 template hipError_t launch_reduce<double>(const char*, const Task*, const BoxGeo&, const BoxPtrs&,
                                           hipStream_t);
+#define RTS_ADJ_INST(Real)                                                                      \
+  template hipError_t launch_adj_plane<Real>(const AdjArgs&, int, hipStream_t);                 \
+  template hipError_t launch_adj_seed<Real>(const void*, const void*, const double*, const void*, \
+                                            void*, void*, double, int, int, int, hipStream_t);  \
+  template hipError_t launch_adj_reduce<Real>(const char*, const Task*, const AdjTask*,          \
+                                              const BoxGeo&, const double*, const void*,         \
+                                              const void*, void*, void*, hipStream_t);
+RTS_ADJ_INST(float)
+RTS_ADJ_INST(double)
+#undef RTS_ADJ_INST
 #define RTS_INST(Real, H)                                                                   \
   template hipError_t launch_sweep_h<Real, H, true>(const SweepArgs&, int, int, hipStream_t); \
   template hipError_t launch_sweep_h<Real, H, false>(const SweepArgs&, int, int, hipStream_t); \

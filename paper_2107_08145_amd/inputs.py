@@ -177,6 +177,24 @@ def workload(name: str, size: int | None = None) -> Problem | list[Problem]:
     raise KeyError(name)
 
 
+def random_problem(nx: int, ny: int, nz: int, seed: int, bands: int = 1, lo: float = 1e-2,
+                   hi: float = 1e2, h_rho: float = 8.0, **fields) -> Problem:
+    """Small test problem: log-uniform kappa in [lo, hi] per band, exponential
+    density, a stratified S with 10 % log-normal noise, S4 rays; `fields`
+    overrides Problem attributes (bot, top, i_bot, n_iter, qweight, ...)."""
+    r = np.random.default_rng(seed)
+    kap = 10 ** r.uniform(math.log10(lo), math.log10(hi), (bands, nz, ny, nx))
+    z = np.arange(nz, dtype=np.float64)
+    rho = np.broadcast_to(np.exp(-z / h_rho)[:, None, None], (nz, ny, nx)).copy()
+    S = ((1 + 2 * np.exp(-z / 10))[None, :, None, None] ** 4
+         * np.exp(0.1 * r.standard_normal((bands, nz, ny, nx))))
+    mu, w = s4_quadrature()
+    p = Problem(nx, ny, nz, 1.0, 1.0, 1.0, mu, w, kap, rho, S, np.ones(bands))
+    for k, v in fields.items():
+        setattr(p, k, v)
+    return p
+
+
 def adjoint_seeds(p: Problem, seed: int):
     """Loss definition for the adjoint workload.
 

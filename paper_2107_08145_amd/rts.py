@@ -27,10 +27,11 @@ RTS_FP64 = 0
 RTS_FP32 = 1
 RTS_OP_SOLVE = 0
 RTS_OP_ADJOINT = 1
+RTS_OP_AUTOTUNE = 2
 
 # every symbol declared in include/rts.h
 SYMBOLS = ("rts_plan_create", "rts_workspace_bytes", "rts_solve", "rts_solve_batched",
-           "rts_adjoint", "rts_check_status", "rts_plan_get_schedule", "rts_plan_set_schedule",
+           "rts_adjoint", "rts_plan_autotune", "rts_check_status", "rts_plan_get_schedule", "rts_plan_set_schedule",
            "rts_plan_enable_timing", "rts_plan_last_timing", "rts_selftest_dpp",
            "rts_plan_destroy", "rts_status_string", "rts_version")
 
@@ -93,6 +94,8 @@ def lib():
                                         vp, sz, vp]
         L.rts_adjoint.argtypes = [vp, i32, ctypes.POINTER(Inputs), ctypes.POINTER(Seeds),
                                   ctypes.POINTER(Grads), vp, sz, vp]
+        L.rts_plan_autotune.argtypes = [vp, i32, ctypes.POINTER(Inputs), ctypes.POINTER(Outputs),
+                                         vp, sz, vp, i32, ctypes.POINTER(Schedule)]
         L.rts_check_status.argtypes = [vp, vp, vp]
         L.rts_plan_get_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
         L.rts_plan_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
@@ -107,7 +110,7 @@ def lib():
         L.rts_version.argtypes = []
         L.rts_version.restype = ctypes.c_char_p
         for f in ("rts_plan_create", "rts_workspace_bytes", "rts_solve", "rts_solve_batched",
-                  "rts_adjoint", "rts_check_status", "rts_plan_get_schedule",
+                  "rts_adjoint", "rts_plan_autotune", "rts_check_status", "rts_plan_get_schedule",
                   "rts_plan_set_schedule", "rts_plan_enable_timing", "rts_plan_last_timing",
                   "rts_selftest_dpp"):
             getattr(L, f).restype = ctypes.c_int
@@ -236,6 +239,39 @@ class Plan:
             rc = lib().rts_solve(self.handle, ci, co, ctypes.c_void_p(ws), nbytes, st)
         _check(rc, "rts_solve_batched" if batched else "rts_solve")
 
+    def autotune(self, ins, outs, reps: int = 3, stream=None) -> dict:
+        """Time every candidate schedule on these inputs (rts_plan_autotune) and keep
+        the fastest; returns it."""
+        n = len(ins)
+        ci = (Inputs * n)()
+        co = (Outputs * n)()
+        for i, ((k, r, s), (q, j, it)) in enumerate(zip(ins, outs)):
+            ci[i] = Inputs(k.data_ptr(), r.data_ptr(), s.data_ptr())
+            co[i] = Outputs(q.data_ptr(), j.data_ptr() if j is not None else None,
+                            it.data_ptr() if it is not None else None)
+        ws, nbytes = self.workspace(RTS_OP_AUTOTUNE)
+        sch = Schedule()
+        _check(lib().rts_plan_autotune(self.handle, n, ci, co, ctypes.c_void_p(ws), nbytes,
+                                       _stream_ptr(stream), reps, ctypes.byref(sch)),
+               "rts_plan_autotune")
+        return {k: getattr(sch, k) for k, _ in Schedule._fields_}
+
+    def adjoint_into(self, ins, seeds, grads, stream=None):
+        """Enqueue an adjoint.  ins: [(kappa, rho, S)]; seeds: [(gQ, gJ, gItop)] (any may be
+        None); grads: [(dS, dchi)] per box."""
+        n = len(ins)
+        ci = (Inputs * n)()
+        cs = (Seeds * n)()
+        cg = (Grads * n)()
+        ptr = (lambda t: t.data_ptr() if t is not None else None)
+        for i, ((k, r, s), (gq, gj, gi), (ds, dc)) in enumerate(zip(ins, seeds, grads)):
+            ci[i] = Inputs(k.data_ptr(), r.data_ptr(), s.data_ptr())
+            cs[i] = Seeds(ptr(gq), ptr(gj), ptr(gi))
+            cg[i] = Grads(ds.data_ptr(), dc.data_ptr())
+        ws, nbytes = self.workspace(RTS_OP_ADJOINT)
+        _check(lib().rts_adjoint(self.handle, n, ci, cs, cg, ctypes.c_void_p(ws), nbytes,
+                                 _stream_ptr(stream)), "rts_adjoint")
+
     def check_status(self, stream=None):
         ws, _ = self.workspace()
         _check(lib().rts_check_status(self.handle, ctypes.c_void_p(ws), _stream_ptr(stream)),
@@ -252,6 +288,23 @@ def solve(p, prec: int = RTS_FP64, plan: Plan | None = None):
     plan.check_status()
     torch.cuda.synchronize()
     return tuple(o.double().cpu().numpy() for o in outs)
+
+
+def adjoint(p, prec: int = RTS_FP64, gQ=None, gJ=None, gItop=None, plan: Plan | None = None):
+    """Gradients (dL/dS, dL/dchi) as numpy [B,nz,ny,nx] of L = <gQ,Q> + <gJ,J> + <gItop,I_top>
+    for one problem on the current GPU."""
+    import torch
+    plan = plan or Plan(p, prec)
+    ins = plan.device_inputs(p)
+    dev = (lambda a, dt: None if a is None else
+           torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt).contiguous())
+    seeds = (dev(gQ, torch.float64), dev(gJ, plan.dtype), dev(gItop, plan.dtype))
+    dS = torch.empty((p.nbands, p.nz, p.ny, p.nx), dtype=plan.dtype, device="cuda")
+    dchi = torch.empty_like(dS)
+    plan.adjoint_into([ins], [seeds], [(dS, dchi)])
+    plan.check_status()
+    torch.cuda.synchronize()
+    return dS.double().cpu().numpy(), dchi.double().cpu().numpy()
 
 
 def selftest_dpp():

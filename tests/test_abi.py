@@ -116,7 +116,58 @@ def test_workspace_and_schedule():
 
 
 def test_adjoint_workspace_query():
-    pl = rts.Plan(_desc_problem())
-    n = ctypes.c_size_t()
-    rc = rts.lib().rts_workspace_bytes(pl.handle, rts.RTS_OP_ADJOINT, ctypes.byref(n))
-    assert rc in (rts.RTS_OK, rts.RTS_E_UNSUPPORTED)
+    # grey S4 on a cube: two z-sweep tasks (one pass) and four x/y-sweep tasks
+    # (n_iter passes); the adjoint stores D of every pass for four slots
+    p = inputs.workload("grey32", size=16)
+    for prec, esz in ((rts.RTS_FP32, 4), (rts.RTS_FP64, 8)):
+        pl = rts.Plan(p, prec)
+        n0 = pl.workspace_bytes(rts.RTS_OP_SOLVE)
+        n1 = pl.workspace_bytes(rts.RTS_OP_ADJOINT)
+        N = p.ncells
+        assert n1 >= n0 + esz * 4 * N * (2 + 4 * p.n_iter)
+
+
+def test_adjoint_argument_errors():
+    p = inputs.workload("grey32", size=16)
+    pl = rts.Plan(p, rts.RTS_FP64)
+    L = rts.lib()
+    ci = rts.Inputs(256, 256, 256)
+    cs = rts.Seeds(None, None, None)
+    cg = rts.Grads(256, 256)
+    ws = ctypes.c_void_p(256)
+    big = 1 << 40
+    assert L.rts_adjoint(None, 1, ctypes.byref(ci), ctypes.byref(cs), ctypes.byref(cg), ws, big,
+                         None) == rts.RTS_E_ARG
+    assert L.rts_adjoint(pl.handle, 2, ctypes.byref(ci), ctypes.byref(cs), ctypes.byref(cg), ws,
+                         big, None) == rts.RTS_E_ARG
+    assert L.rts_adjoint(pl.handle, 1, None, ctypes.byref(cs), ctypes.byref(cg), ws, big,
+                         None) == rts.RTS_E_ARG
+    bad = rts.Grads(None, 256)
+    assert L.rts_adjoint(pl.handle, 1, ctypes.byref(ci), ctypes.byref(cs), ctypes.byref(bad), ws,
+                         big, None) == rts.RTS_E_ARG
+    n0 = pl.workspace_bytes(rts.RTS_OP_SOLVE)
+    assert L.rts_adjoint(pl.handle, 1, ctypes.byref(ci), ctypes.byref(cs), ctypes.byref(cg), ws,
+                         n0, None) == rts.RTS_E_WORKSPACE
+    assert L.rts_adjoint(pl.handle, 1, ctypes.byref(ci), ctypes.byref(cs), ctypes.byref(cg),
+                         ctypes.c_void_p(100), big, None) == rts.RTS_E_WORKSPACE
+
+
+def test_autotune_workspace_and_errors():
+    p = inputs.workload("grey32", size=16)
+    pl = rts.Plan(p, rts.RTS_FP32)
+    n_tune = pl.workspace_bytes(rts.RTS_OP_AUTOTUNE)
+    for h in (2, 4, 6, 8):
+        pl.set_schedule(rows_per_strip=h)
+        assert pl.workspace_bytes(rts.RTS_OP_SOLVE) <= n_tune
+    L = rts.lib()
+    ci = rts.Inputs(256, 256, 256)
+    co = rts.Outputs(256, None, None)
+    sch = rts.Schedule()
+    assert L.rts_plan_autotune(None, 1, ctypes.byref(ci), ctypes.byref(co), ctypes.c_void_p(256),
+                               n_tune, None, 1, ctypes.byref(sch)) == rts.RTS_E_ARG
+    assert L.rts_plan_autotune(pl.handle, 1, ctypes.byref(ci), ctypes.byref(co),
+                               ctypes.c_void_p(256), n_tune, None, 0,
+                               ctypes.byref(sch)) == rts.RTS_E_ARG
+    assert L.rts_plan_autotune(pl.handle, 1, ctypes.byref(ci), ctypes.byref(co),
+                               ctypes.c_void_p(100), n_tune, None, 1,
+                               ctypes.byref(sch)) == rts.RTS_E_WORKSPACE

@@ -22,21 +22,8 @@ from paper_2107_08145_amd import inputs, rts
 pytestmark = pytest.mark.gpu
 
 
-def _cfg(name, **kw):
-    return kw
-
-
-def _rand_problem(nx, ny, nz, seed, bands=1, lo=1e-2, hi=1e2, h_rho=8.0, **kw):
-    r = np.random.default_rng(seed)
-    kap = 10 ** r.uniform(math.log10(lo), math.log10(hi), (bands, nz, ny, nx))
-    z = np.arange(nz, dtype=np.float64)
-    rho = np.broadcast_to(np.exp(-z / h_rho)[:, None, None], (nz, ny, nx)).copy()
-    S = (1 + 2 * np.exp(-z / 10))[None, :, None, None] ** 4 * np.exp(0.1 * r.standard_normal((bands, nz, ny, nx)))
-    mu, w = inputs.s4_quadrature()
-    p = inputs.Problem(nx, ny, nz, 1.0, 1.0, 1.0, mu, w, kap, rho, S, np.ones(bands))
-    for k, v in kw.items():
-        setattr(p, k, v)
-    return p
+def _rand_problem(nx, ny, nz, seed, **kw):
+    return inputs.random_problem(nx, ny, nz, seed, **kw)
 
 
 def _check64(p, got, ref):
@@ -186,3 +173,21 @@ def test_batched_equals_single():
                 single = rts.solve(p, rts.RTS_FP32)
                 for a, b in zip(o, single):
                     assert np.array_equal(a.double().cpu().numpy(), b), (use_graph, rep)
+
+
+def test_autotune_keeps_results():
+    p = _rand_problem(70, 40, 37, seed=4).astype(np.float32)
+    ref = rts.solve(p, rts.RTS_FP32)
+    pl = rts.Plan(p, rts.RTS_FP32)
+    ins = pl.device_inputs(p)
+    outs = pl.new_outputs(p)
+    chosen = pl.autotune([ins], [outs], reps=2)
+    print("autotune chose", chosen, flush=True)
+    assert chosen["rows_per_strip"] in (2, 4, 6, 8) and chosen["order"] in (0, 1)
+    assert pl.schedule() == chosen
+    got = rts.solve(p, rts.RTS_FP32, plan=pl)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+    # cached: a second plan of the same shape takes the same schedule without timing
+    pl2 = rts.Plan(p, rts.RTS_FP32)
+    assert pl2.autotune([ins], [outs], reps=1) == chosen
