@@ -188,11 +188,6 @@ int rts_plan_set_schedule(void* plan, const rts_schedule* s);
 int rts_plan_enable_timing(void* plan, int32_t on);
 int rts_plan_last_timing(void* plan, double* sweep_ms, double* total_ms);
 
-/* In-bounds lane-layout check of the DPP whole-wave shifts the sweep relies
- * on, for one wave: out[i] = in[i-1] (out[0] = -1) and out[64+i] = in[i+1]
- * (out[127] = -2).  `in` holds 64 floats, `out` 128 (device pointers). */
-int rts_selftest_dpp(const float* in, float* out, void* hip_stream);
-
 void rts_plan_destroy(void* plan);
 const char* rts_status_string(int status);
 const char* rts_version(void);

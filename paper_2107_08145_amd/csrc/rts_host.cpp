@@ -44,7 +44,6 @@ hipError_t launch_adj_seed(const void*, const void*, const double*, const void*,
 template <class Real>
 hipError_t launch_adj_reduce(const char*, const Task*, const AdjTask*, const BoxGeo&,
                              const double*, const void*, const void*, void*, void*, hipStream_t);
-hipError_t launch_dpp_selftest(const float*, float*, hipStream_t);
 }  // namespace rts
 
 using namespace rts;
@@ -985,13 +984,5 @@ const char* rts_status_string(int status) {
 }
 
 const char* rts_version(void) { return "librts 0.1 (gfx950)"; }
-
-// In-bounds lane-layout check of the DPP whole-wave shifts used by the sweep:
-// in and out are device arrays of 64 and 128 floats.
-int rts_selftest_dpp(const float* in, float* out, void* hip_stream) {
-  if (!in || !out) return RTS_E_ARG;
-  RTS_HIP(launch_dpp_selftest(in, out, reinterpret_cast<hipStream_t>(hip_stream)));
-  return RTS_OK;
-}
 
 }  // extern "C"

@@ -10,15 +10,15 @@
 //                    (task, strip) tickets from a device counter.  A task is
 //                    up to four rays of one band that share the dominant axis
 //                    and its direction; a strip is H rows x all columns of the
-//                    task's sweep plane.  Each thread owns one column and H
-//                    rows in registers, marches plane by plane (periodic
-//                    directions: n_iter laps), and exchanges its edge rows
-//                    with the neighbouring strips through the workspace and
-//                    per-strip progress flags.  Column neighbours come from
-//                    DPP lane shifts, with the wave-edge lanes patched from a
-//                    small LDS table.  It sweeps D = I - S (see rts.h).
+//                    task's sweep plane.  Each thread owns one column, keeps
+//                    the strip's previous plane in LDS, marches plane by plane
+//                    (periodic directions: n_iter laps), and exchanges its
+//                    edge rows with the neighbouring strips through tagged
+//                    words in the workspace.  It sweeps D = I - S (see rts.h).
 //  * rts_reduce    : FP64 sum of the per-task partial J - S arrays in a fixed
 //                    order, Q, J (the paper's "flux" step).
+//  * rts_adj_*     : the adjoint: seeds, the reverse sweep (one launch per
+//                    plane of every task) and the FP64 gradient reduction.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -60,29 +60,6 @@ __device__ inline double rts_cw(double x, double e) {
   s = fma(s, -x, 1.0);
   if (x < 0.1) return s;
   return (1.0 - e) / x;
-}
-
-// DPP whole-wave shifts: lane i receives lane i-1 (shr) or lane i+1 (shl);
-// the lane with no source keeps `old`.
-__device__ inline float dpp_shr(float old, float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x138, 0xf, 0xf, false));
-}
-__device__ inline float dpp_shl(float old, float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x130, 0xf, 0xf, false));
-}
-__device__ inline double dpp_shr(double old, double v) {
-  int2 o = *reinterpret_cast<int2*>(&old), s = *reinterpret_cast<int2*>(&v);
-  int2 r;
-  r.x = __builtin_amdgcn_update_dpp(o.x, s.x, 0x138, 0xf, 0xf, false);
-  r.y = __builtin_amdgcn_update_dpp(o.y, s.y, 0x138, 0xf, 0xf, false);
-  return *reinterpret_cast<double*>(&r);
-}
-__device__ inline double dpp_shl(double old, double v) {
-  int2 o = *reinterpret_cast<int2*>(&old), s = *reinterpret_cast<int2*>(&v);
-  int2 r;
-  r.x = __builtin_amdgcn_update_dpp(o.x, s.x, 0x130, 0xf, 0xf, false);
-  r.y = __builtin_amdgcn_update_dpp(o.y, s.y, 0x130, 0xf, 0xf, false);
-  return *reinterpret_cast<double*>(&r);
 }
 
 // a + f (b - a) as one explicit fused multiply-add (the library is built with
@@ -973,15 +950,6 @@ __global__ __launch_bounds__(256) void rts_adj_reduce(const char* __restrict__ w
   }
 }
 
-// DPP lane-layout self test: out[i] = in[i-1] (shr, lane 0 keeps -1) and
-// out[64 + i] = in[i+1] (shl, lane 63 keeps -2) for one wave.
-__global__ void rts_dpp_selftest(const float* in, float* out) {
-  const int l = threadIdx.x;
-  const float v = in[l];
-  out[l] = dpp_shr(-1.f, v);
-  out[64 + l] = dpp_shl(-2.f, v);
-}
-
 }  // namespace rts
 
 // ---------------------------------------------------------------------------
@@ -1059,10 +1027,6 @@ hipError_t launch_adj_reduce(const char* ws, const Task* tasks, const AdjTask* a
   return hipGetLastError();
 }
 
-hipError_t launch_dpp_selftest(const float* in, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(rts_dpp_selftest, dim3(1), dim3(64), 0, st, in, out);
-  return hipGetLastError();
-}
 
 // explicit instantiations
 template hipError_t launch_prep<float>(const void*, const void*, const void*, void*, int64_t,

@@ -32,7 +32,7 @@ RTS_OP_AUTOTUNE = 2
 # every symbol declared in include/rts.h
 SYMBOLS = ("rts_plan_create", "rts_workspace_bytes", "rts_solve", "rts_solve_batched",
            "rts_adjoint", "rts_plan_autotune", "rts_check_status", "rts_plan_get_schedule", "rts_plan_set_schedule",
-           "rts_plan_enable_timing", "rts_plan_last_timing", "rts_selftest_dpp",
+           "rts_plan_enable_timing", "rts_plan_last_timing",
            "rts_plan_destroy", "rts_status_string", "rts_version")
 
 
@@ -102,7 +102,6 @@ def lib():
         L.rts_plan_enable_timing.argtypes = [vp, i32]
         L.rts_plan_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_double)]
-        L.rts_selftest_dpp.argtypes = [vp, vp, vp]
         L.rts_plan_destroy.argtypes = [vp]
         L.rts_plan_destroy.restype = None
         L.rts_status_string.argtypes = [ctypes.c_int]
@@ -111,8 +110,7 @@ def lib():
         L.rts_version.restype = ctypes.c_char_p
         for f in ("rts_plan_create", "rts_workspace_bytes", "rts_solve", "rts_solve_batched",
                   "rts_adjoint", "rts_plan_autotune", "rts_check_status", "rts_plan_get_schedule",
-                  "rts_plan_set_schedule", "rts_plan_enable_timing", "rts_plan_last_timing",
-                  "rts_selftest_dpp"):
+                  "rts_plan_set_schedule", "rts_plan_enable_timing", "rts_plan_last_timing"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -305,14 +303,3 @@ def adjoint(p, prec: int = RTS_FP64, gQ=None, gJ=None, gItop=None, plan: Plan | 
     plan.check_status()
     torch.cuda.synchronize()
     return dS.double().cpu().numpy(), dchi.double().cpu().numpy()
-
-
-def selftest_dpp():
-    """Lane layout of the DPP whole-wave shifts (see rts.h)."""
-    import torch
-    x = torch.arange(64, dtype=torch.float32, device="cuda")
-    out = torch.empty(128, dtype=torch.float32, device="cuda")
-    _check(lib().rts_selftest_dpp(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                  _stream_ptr()), "rts_selftest_dpp")
-    torch.cuda.synchronize()
-    return out.cpu().numpy()

@@ -46,14 +46,6 @@ def _check32(p32, got, ref, q_tol=2e-5, j_tol=2e-6):
     return eq, ej, ei
 
 
-def test_dpp_lane_layout():
-    out = rts.selftest_dpp()
-    assert out[0] == -1.0
-    assert np.array_equal(out[1:64], np.arange(0, 63, dtype=np.float32))
-    assert np.array_equal(out[64:127], np.arange(1, 64, dtype=np.float32))
-    assert out[127] == -2.0
-
-
 def test_grey32_fp64_matches_oracle():
     p = inputs.workload("grey32")
     print("case grey32 fp64", flush=True)
