@@ -70,14 +70,6 @@ __device__ inline double lerp(double a, double b, double f) { return fma(f, b - 
 __device__ inline float fmad(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ inline double fmad(double a, double b, double c) { return fma(a, b, c); }
 
-// Error-free sum s + t = u + err (Knuth).
-template <class R>
-__device__ inline void two_sum(R s, R t, R& u, R& err) {
-  u = s + t;
-  R bp = u - s;
-  err = (s - (u - bp)) + (t - bp);
-}
-
 // Cross-workgroup traffic of the sweep (edge rows and progress flags) uses
 // only device-coherent accesses: relaxed agent-scope atomic loads and stores,
 // which gfx950 issues with the sc1 bit, so they neither read nor leave stale
@@ -93,6 +85,17 @@ __device__ inline R ld_dev(const R* p) {
 template <class R>
 __device__ inline void st_dev(R* p, R v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Element of a uniform row at a per-lane 32-bit byte offset: lets the
+// compiler use the scalar-base + 32-bit lane offset form of global memory
+// instructions instead of a 64-bit address add per lane.
+template <class T>
+__device__ inline T* lane_at(T* row, uint32_t boff) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(row) + boff);
+}
+template <class T>
+__device__ inline const T* lane_at(const T* row, uint32_t boff) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(row) + boff);
 }
 __device__ inline void vmem_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
@@ -197,22 +200,38 @@ struct Strip {
   __device__ static constexpr int qd(int i, int r) { return 2 * (H + 2) + kMaxRaysPerTask * i + r; }
 };
 
-// e = exp(-x) and c = (1 - e)/x of the linear-source step.  FP32 takes
-// xs = x log2(e) (the factor is folded into ds/2 by the caller) so that e is
-// one v_exp_f32; c uses its 5-term series below x = 0.1.  FP64 takes xs = x.
-__device__ inline void step_weights(float xs, float& e, float& c) {
-  constexpr float ln2 = 0.69314718055994531f, log2e = 1.4426950408889634f;
-  e = __builtin_amdgcn_exp2f(-xs);
+// c = (1 - e)/x of the linear-source step, e = exp(-x), by its closed form
+// or by its power series (x < 0.1, where 1 - e cancels).  FP32 takes
+// xs = x log2(e) (the factor is folded into the scaled opacities) so that e is
+// one v_exp_f32; its series has 5 terms (truncation 1.4e-8 relative).  FP64
+// takes xs = x and 11 terms.
+__device__ inline float rts_exp_step(float xs) { return __builtin_amdgcn_exp2f(-xs); }
+__device__ inline double rts_exp_step(double x) { return exp(-x); }
+__device__ inline bool rts_small_step(float xs) { return xs < 0.1f * 1.4426950408889634f; }
+__device__ inline bool rts_small_step(double x) { return x < 0.1; }
+__device__ inline float rts_c_closed(float xs, float e) {
+  return (1.f - e) * (__builtin_amdgcn_rcpf(xs) * 1.4426950408889634f);
+}
+__device__ inline double rts_c_closed(double x, double e) { return (1.0 - e) / x; }
+__device__ inline float rts_c_series(float xs) {
   // sum_{n=0}^{4} (-x)^n / (n+1)!  with x = xs ln2
+  constexpr float ln2 = 0.69314718055994531f;
   constexpr float a1 = -ln2 / 2.f, a2 = ln2 * ln2 / 6.f, a3 = -ln2 * ln2 * ln2 / 24.f,
                   a4 = ln2 * ln2 * ln2 * ln2 / 120.f;
-  const float s = fmaf(fmaf(fmaf(fmaf(xs, a4, a3), xs, a2), xs, a1), xs, 1.f);
-  const float l = (1.f - e) * (__builtin_amdgcn_rcpf(xs) * log2e);
-  c = xs < 0.1f * log2e ? s : l;
+  return fmaf(fmaf(fmaf(fmaf(xs, a4, a3), xs, a2), xs, a1), xs, 1.f);
 }
-__device__ inline void step_weights(double x, double& e, double& c) {
-  e = exp(-x);
-  c = rts_cw(x, e);
+__device__ inline double rts_c_series(double x) {
+  double s = 1.0 / 39916800.0;  // 1/11!
+  s = fma(s, -x, 1.0 / 3628800.0);
+  s = fma(s, -x, 1.0 / 362880.0);
+  s = fma(s, -x, 1.0 / 40320.0);
+  s = fma(s, -x, 1.0 / 5040.0);
+  s = fma(s, -x, 1.0 / 720.0);
+  s = fma(s, -x, 1.0 / 120.0);
+  s = fma(s, -x, 1.0 / 24.0);
+  s = fma(s, -x, 1.0 / 6.0);
+  s = fma(s, -x, 0.5);
+  return fma(s, -x, 1.0);
 }
 
 // Column-interpolated values of one old row: chi and S (NC variants) and D of
@@ -253,12 +272,12 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
   const bool act = c < W;
   const int cc = act ? c : W - 1;
   const int cm = cc > 0 ? cc - 1 : W - 1, cp1 = cc + 1 < W ? cc + 1 : 0;
-  const int r0 = strip * T.rows_per_strip;
+  int r0 = strip * T.rows_per_strip;
   const int hr = FULL ? H : min(T.rows_per_strip, T.n_rows - r0);
-  const int ps = (int)T.plane_stride, rs = (int)T.row_stride;
+  int ps = (int)T.plane_stride, rs = (int)T.row_stride;
   int* status = reinterpret_cast<int*>(A.ws);
 
-  // per-slot constants; FP32 folds log2(e) into ds/2 (see step_weights)
+  // per-slot constants; FP32 folds log2(e) into ds/2 (see rts_exp_step)
   const Real kx = sizeof(Real) == 4 ? Real(1.4426950408889634) : Real(1);
   Real f1[R], f2[R], hds[R], wgt[R];
 #pragma unroll
@@ -266,6 +285,9 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
     const TaskRay RTS_CONST& y = T.ray[UNI ? 0 : r];
     f1[r] = (Real)y.f1; f2[r] = (Real)y.f2; hds[r] = (Real)y.hds * kx; wgt[r] = (Real)y.w;
   }
+  // scale of the chi values kept in LDS: ds/2 (times log2 e in FP32) when the
+  // four slots share ds, so that the optical depth step is one add
+  const Real csc = UNI ? hds[0] : Real(1);
   const bool zp = T.z_planes != 0;
   const int bc_up = zp ? -1 : 0, bc_dn = zp ? -1 : T.n_rows - 1;
 
@@ -299,7 +321,10 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
   const Real* lcc = lds + cc * ST::NQP;                 // this column (clamped)
   const Real* lcm = lds + cm * ST::NQP;                 // column c-1
   const Real* lcp = lds + cp1 * ST::NQP;                // column c+1
-  const unsigned ucc = (unsigned)cc, uc = (unsigned)c;
+  // per-lane byte offsets of this column in a Real row and in an exchange row
+  const uint32_t cb = (uint32_t)cc * sizeof(Real), ub = (uint32_t)c * sizeof(Real);
+  const uint32_t xb_c = (uint32_t)cc * NW * 8, xb_m = (uint32_t)cm * NW * 8,
+                 xb_p = (uint32_t)cp1 * NW * 8, xb_u = (uint32_t)c * NW * 8;
   // uniform row pointer (a readfirstlane'd offset, so the compiler keeps one
   // 32-bit lane offset instead of a 64-bit pointer per row)
   auto urow = [&](auto* base, int off) __attribute__((always_inline)) {
@@ -313,31 +338,29 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
 #pragma unroll
     for (int i = 0; i < H; ++i) {
       const int o = qo + (r0 + (FULL || i < hr ? i : 0)) * rs;
-      ncx[i + 1] = urow(chi, o)[ucc];
-      nsx[i + 1] = urow(Sv, o)[ucc];
+      ncx[i + 1] = *lane_at(urow(chi, o), cb) * csc;
+      nsx[i + 1] = *lane_at(urow(Sv, o), cb);
     }
-    ncx[0] = urow(chi, qo + lrow * rs)[ucc];
-    nsx[0] = urow(Sv, qo + lrow * rs)[ucc];
-    ncx[H + 1] = urow(chi, qo + hrow * rs)[ucc];
-    nsx[H + 1] = urow(Sv, qo + hrow * rs)[ucc];
+    ncx[0] = *lane_at(urow(chi, qo + lrow * rs), cb) * csc;
+    nsx[0] = *lane_at(urow(Sv, qo + lrow * rs), cb);
+    ncx[H + 1] = *lane_at(urow(chi, qo + hrow * rs), cb) * csc;
+    nsx[H + 1] = *lane_at(urow(Sv, qo + hrow * rs), cb);
   };
-  // outputs of plane q from the new D and S: the compensated partial sum of
-  // w_r D_r and I_top
+  // outputs of plane q from the new D and S: the pairwise sum of w_r D_r over
+  // the task's four slots (the sums over tasks and bands are FP64) and I_top
   auto write_out = [&](int q, const Real (&Dn)[H][R]) __attribute__((always_inline)) {
     if (!act) return;
     const int qo = q * ps;
 #pragma unroll
     for (int i = 0; i < H; ++i) {
       if (!FULL && i >= hr) break;
-      Real sum = wgt[0] * Dn[i][0], comp = 0;
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        Real u, e;
-        two_sum(sum, wgt[r] * Dn[i][r], u, e);
-        sum = u;
-        comp += e;
+      Real sum;
+      if (UNI) {
+        sum = wgt[0] * ((Dn[i][0] + Dn[i][1]) + (Dn[i][2] + Dn[i][3]));
+      } else {
+        sum = fmad(wgt[1], Dn[i][1], wgt[0] * Dn[i][0]) + fmad(wgt[3], Dn[i][3], wgt[2] * Dn[i][2]);
       }
-      urow(P, qo + (r0 + i) * rs)[uc] = sum + comp;
+      *lane_at(urow(P, qo + (r0 + i) * rs), ub) = sum;
     }
     Real* Itop = reinterpret_cast<Real*>(A.box[T.box].I_top);
     const int it_row = T.it_top - r0;
@@ -364,7 +387,7 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
     for (int i = 0; i < H; ++i) {
       if (!FULL && i >= hr) break;
 #pragma unroll
-      for (int r = 0; r < R; ++r) urow(ds, (r * T.n_rows + r0 + i) * W)[uc] = Dn[i][r];
+      for (int r = 0; r < R; ++r) *lane_at(urow(ds, (r * T.n_rows + r0 + i) * W), ub) = Dn[i][r];
     }
   };
   // store the plane (ncx, nsx, Dn) as the next step's old plane
@@ -416,9 +439,9 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
       const uint64_t* rowp = urow(X, xoff + r * W * NW);
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
-        const unsigned col = (unsigned)(k == 0 ? cc : (r < 2 ? cm : cp1)) * NW;
+        const uint32_t colb = k == 0 ? xb_c : (r < 2 ? xb_m : xb_p);
 #pragma unroll
-        for (int x = 0; x < NW; ++x) hw[r][k][x] = has ? ld_dev(rowp + col + x) : 0ull;
+        for (int x = 0; x < NW; ++x) hw[r][k][x] = has ? ld_dev(lane_at(rowp, colb) + x) : 0ull;
       }
     }
   };
@@ -451,6 +474,11 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
 
   // ---- the march
   for (int t = 0; t < nsteps; ++t) {
+    // Launder the strides, the strip origin and the base pointers each step:
+    // the address arithmetic derived from them is then recomputed in the loop
+    // (scalar ALU) instead of being hoisted as dozens of live row offsets,
+    // which would be spilled.
+    asm volatile("" : "+s"(rs), "+s"(ps), "+s"(r0), "+s"(chi), "+s"(Sv), "+s"(P), "+s"(X));
     const int q = plane_of(t);
     if (t > 0) halo_wait(t);
 
@@ -487,8 +515,12 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
         const Real bc = lerp(lk.c[v], up ? lp.c[v] : ln.c[v], f2[r]);
         const Real bs = lerp(lk.s[v], up ? lp.s[v] : ln.s[v], f2[r]);
         const Real bd = lerp(lk.d[r], up ? lp.d[r] : ln.d[r], f2[r]);
-        Real e, cw;
-        step_weights(hds[r] * (cpv + bc), e, cw);
+        // UNI: chi is stored pre-scaled by ds/2 (and log2 e in FP32)
+        const Real xs = UNI ? cpv + bc : hds[r] * (cpv + bc);
+        // both forms, then a select (a branch here costs registers)
+        const Real e = rts_exp_step(xs);
+        const Real c_ser = rts_c_series(xs), c_cl = rts_c_closed(xs, e);
+        const Real cw = rts_small_step(xs) ? c_ser : c_cl;
         out[r] = fmad(e, bd, cw * (bs - spv));
       }
       const int gr = r0 + i;  // boundary rows (rows are z): set, not integrated
@@ -559,15 +591,14 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
     if (act) {
       const int xe = ((strip * 2 + (t & 1)) * 2) * xstride;
       const uint32_t tag = (uint32_t)(t + 1);
-      const unsigned col = uc * NW;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         Real top = Dn[0][r];
 #pragma unroll
         for (int i = 1; i < H; ++i)
           if (FULL ? (i == H - 1) : (i == hr - 1)) top = Dn[i][r];
-        if ((r & 1) == 1) TG::put(urow(X, xe + r * W * NW) + col, Dn[0][r], tag);          // lower: odd slots
-        if ((r & 1) == 0) TG::put(urow(X, xe + xstride + r * W * NW) + col, top, tag);  // upper: even slots
+        if ((r & 1) == 1) TG::put(lane_at(urow(X, xe + r * W * NW), xb_u), Dn[0][r], tag);  // lower: odd slots
+        if ((r & 1) == 0) TG::put(lane_at(urow(X, xe + xstride + r * W * NW), xb_u), top, tag);  // upper: even
       }
     }
     // ---- interior rows, sliding window of interpolated old rows
