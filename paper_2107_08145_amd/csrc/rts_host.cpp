@@ -37,7 +37,12 @@ hipError_t launch_sweep_h(const SweepArgs&, int, int, hipStream_t);
 template <class Real>
 hipError_t launch_reduce(const char*, const Task*, const BoxGeo&, const BoxPtrs&, hipStream_t);
 template <class Real>
-hipError_t launch_adj_plane(const AdjArgs&, int, hipStream_t);
+size_t reverse_lds_bytes(int);
+template <class Real>
+const void* reverse_fn(int cols);
+int reverse_threads(int cols);
+template <class Real>
+hipError_t launch_reverse(const RevArgs&, int, int, hipStream_t);
 template <class Real>
 hipError_t launch_adj_seed(const void*, const void*, const double*, const void*, void*, void*,
                            double, int, int, int, hipStream_t);
@@ -107,12 +112,14 @@ struct Plan {
   size_t esz = 8;
   rts_schedule sched{4, 0, 0, 0};
   // layout (bytes)
-  size_t off_flags = 0, off_tasks = 0, off_queue = 0, off_atasks = 0, off_data = 0, total = 0;
-  // adjoint: the solve layout, then stored D planes, reverse state, gradient
-  // partials [off_grads, off_grads_end) and seeds
+  size_t off_flags = 0, off_tasks = 0, off_queue = 0, off_atasks = 0, off_rqueue = 0,
+         off_data = 0, total = 0;
+  // adjoint: the solve layout, then stored D planes, the reverse sweep's
+  // exchange buffers and gradient partials [off_grads, off_grads_end), seeds
   size_t off_grads = 0, off_grads_end = 0, total_adj = 0;
-  int adj_launches = 0, adj_blocks = 0;
   std::vector<AdjTask> atasks;
+  std::vector<int32_t> rqueue;
+  int rev_total_strips = 0, rev_max_strips = 1, rev_blocks = 0;
   std::vector<Task> tasks;
   std::vector<int32_t> queue;
   int total_strips = 0;
@@ -304,6 +311,8 @@ void build_layout(Plan& P) {
   off = align_up(off + sizeof(int32_t) * P.queue.size());
   P.off_atasks = off;
   off = align_up(off + sizeof(AdjTask) * P.tasks.size());
+  P.off_rqueue = off;
+  off = align_up(off + 2 * sizeof(int32_t) * P.tasks.size());
   P.off_data = off;
   for (Box& B : P.boxes) {
     const size_t arr = (size_t)B.d.nbands * B.N * esz;
@@ -333,16 +342,24 @@ void build_layout(Plan& P) {
     const size_t pc = (size_t)T.n_rows * T.n_cols;
     T.dstore_off = (int64_t)(off / esz);
     off = align_up(off + (size_t)T.n_unrolled * kMaxRaysPerTask * pc * esz);
-    P.atasks[t].state_off = (int64_t)(off / esz);
-    off = align_up(off + 2 * kMaxRaysPerTask * 3 * pc * esz);
   }
   P.off_grads = off;
   for (size_t t = 0; t < P.tasks.size(); ++t) {
+    const Task& T = P.tasks[t];
+    AdjTask& AT = P.atasks[t];
+    AT.task = (int32_t)t;
+    AT.u_init = T.z_planes ? 0 : -1;
+    AT.strips = (T.n_rows + kRevRows - 1) / kRevRows;
+    AT.xbuf_off = (int64_t)(off / sizeof(uint64_t));
+    off = align_up(off + (size_t)AT.strips * 2 * 2 * 6 * T.n_cols * words * sizeof(uint64_t));
+  }
+  for (size_t t = 0; t < P.tasks.size(); ++t) {
     const Box& B = P.boxes[P.tasks[t].box];
+    // two partials each: the reverse sweep's even-slot and odd-slot threads
     P.atasks[t].gs_off = (int64_t)(off / esz);
-    off = align_up(off + (size_t)B.N * esz);
+    off = align_up(off + 2 * (size_t)B.N * esz);
     P.atasks[t].gc_off = (int64_t)(off / esz);
-    off = align_up(off + (size_t)B.N * esz);
+    off = align_up(off + 2 * (size_t)B.N * esz);
   }
   P.off_grads_end = off;
   for (Box& B : P.boxes) {
@@ -351,20 +368,27 @@ void build_layout(Plan& P) {
     B.seedT_off = (int64_t)(off / esz); off = align_up(off + arr);
   }
   P.total_adj = off;
-  P.adj_launches = 0;
-  P.adj_blocks = 0;
   for (size_t t = 0; t < P.tasks.size(); ++t) {
     const Task& T = P.tasks[t];
     const Box& B = P.boxes[T.box];
-    AdjTask& AT = P.atasks[t];
-    AT.task = (int32_t)t;
-    AT.ncell = T.n_rows * T.n_cols;
-    AT.cell0 = P.adj_blocks * 256;
-    P.adj_blocks += (AT.ncell + 255) / 256;
-    AT.u_init = T.z_planes ? 0 : -1;
-    AT.seed_off = (T.transposed ? B.seedT_off : B.seed_off) + (int64_t)T.band * B.N;
-    P.adj_launches = std::max(P.adj_launches, T.n_unrolled - AT.u_init);
+    P.atasks[t].seed_off = (T.transposed ? B.seedT_off : B.seed_off) + (int64_t)T.band * B.N;
   }
+  // reverse queue: longest sweeps first
+  std::vector<int> rq(P.tasks.size());
+  for (size_t i = 0; i < rq.size(); ++i) rq[i] = (int)i;
+  std::stable_sort(rq.begin(), rq.end(), [&](int a, int b) {
+    return P.tasks[a].n_unrolled - P.atasks[a].u_init > P.tasks[b].n_unrolled - P.atasks[b].u_init;
+  });
+  P.rqueue.clear();
+  P.rev_total_strips = 0;
+  P.rev_max_strips = 1;
+  for (int i : rq) {
+    P.rqueue.push_back(P.rev_total_strips);
+    P.rqueue.push_back(i);
+    P.rev_total_strips += P.atasks[i].strips;
+    P.rev_max_strips = std::max(P.rev_max_strips, (int)P.atasks[i].strips);
+  }
+  P.rev_blocks = 0;
   P.uploaded_ws = nullptr;
   if (P.gexec) {
     (void)hipGraphExecDestroy(P.gexec);
@@ -393,14 +417,29 @@ int dev_init(Plan& P) {
   return RTS_OK;
 }
 
+// Workgroups of `fn` that can be resident on one CU: the runtime's estimate,
+// capped by how a workgroup's waves are placed: each of the CU's four SIMDs
+// must take ceil(waves / 4) of them, and a SIMD holds 512 / VGPRs waves (a
+// five-wave workgroup with 128 VGPRs therefore fits twice, not three times).
+int resident_blocks(const void* fn, int threads, size_t lds, int* out) {
+  int nb = 0;
+  RTS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, lds));
+  hipFuncAttributes fa;
+  RTS_HIP(hipFuncGetAttributes(&fa, fn));
+  const int vgpr = std::max(8, (fa.numRegs + 7) / 8 * 8);
+  const int per_simd = std::min(8, 512 / vgpr);
+  const int need = ((threads + 63) / 64 + 3) / 4;
+  *out = std::min(nb, per_simd / need);
+  return RTS_OK;
+}
+
 template <class Real, int H>
 int occupancy_h(Plan& P) {
-  int nb = 0;
   const void* fn = P.uni ? sweep_fn<Real, H, true>() : sweep_fn<Real, H, false>();
-  RTS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, P.threads,
-                                                       sweep_lds_bytes<Real, H>(P.threads)));
-  P.occupancy_blocks = nb;
-  return RTS_OK;
+  int rc = resident_blocks(fn, P.threads, sweep_lds_bytes<Real, H>(P.threads), &P.occupancy_blocks);
+  if (rc) return rc;
+  return resident_blocks(reverse_fn<Real>(P.threads), reverse_threads(P.threads),
+                         reverse_lds_bytes<Real>(P.threads), &P.rev_blocks);
 }
 
 template <class Real>
@@ -443,6 +482,8 @@ int ensure_pinned(Plan& P) {
               sizeof(int32_t) * P.queue.size());
   std::memcpy((char*)P.pinned + (P.off_atasks - P.off_tasks), P.atasks.data(),
               sizeof(AdjTask) * P.atasks.size());
+  std::memcpy((char*)P.pinned + (P.off_rqueue - P.off_tasks), P.rqueue.data(),
+              sizeof(int32_t) * P.rqueue.size());
   return RTS_OK;
 }
 
@@ -530,20 +571,21 @@ int enqueue_adjoint(Plan& P, const rts_inputs* in, const rts_seeds* g, const rts
                                     base + B.seedT_off + o, qf, B.d.g.nx, B.d.g.ny, B.d.g.nz, st));
     }
   }
-  AdjArgs a;
+  RevArgs a;
   std::memset(&a, 0, sizeof(a));
   a.ws = ws;
   a.tasks = reinterpret_cast<const Task*>(ws + P.off_tasks);
   a.atasks = reinterpret_cast<const AdjTask*>(ws + P.off_atasks);
-  a.natasks = (int)P.atasks.size();
+  a.queue = reinterpret_cast<const int32_t*>(ws + P.off_rqueue);
+  a.ntasks = (int)P.atasks.size();
+  a.total_strips = P.rev_total_strips;
+  a.timeout_ticks = P.timeout_ticks;
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     a.gItop[b] = g[b].gItop;
     a.S[b] = in[b].S;
   }
-  for (int k = 0; k < P.adj_launches; ++k) {
-    a.k = k;
-    RTS_HIP(launch_adj_plane<Real>(a, P.adj_blocks, st));
-  }
+  const int grid = std::max(1, std::min(P.rev_blocks * P.cus, P.rev_total_strips));
+  RTS_HIP(launch_reverse<Real>(a, grid, P.threads, st));
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     const BoxGeo G = box_geo(P, b);
     RTS_HIP(launch_adj_reduce<Real>(ws, a.tasks, a.atasks, G, g[b].gQ, g[b].gJ, g[b].gItop,
@@ -868,6 +910,10 @@ int rts_adjoint(void* plan, int32_t nbox, const rts_inputs* in, const rts_seeds*
   try {
     int rc = prepare(P);
     if (rc) return rc;
+    if (P->rev_blocks < 1 || P->rev_blocks * P->cus < P->rev_max_strips) {
+      g_last_hip = "the strips of one reverse sweep task cannot all be resident";
+      return RTS_E_UNSUPPORTED;
+    }
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     return P->prec == RTS_FP32 ? enqueue_adjoint<float>(*P, in, g, d, (char*)ws, st)
                                : enqueue_adjoint<double>(*P, in, g, d, (char*)ws, st);

@@ -56,24 +56,28 @@ struct Task {
   TaskRay ray[kMaxRaysPerTask];
 };
 
-// Reverse sweep of one task, for the adjoint (one launch per unrolled plane).
+// Reverse sweep of one task, for the adjoint: a persistent strip sweep like
+// the forward one, planes in reverse order, kRevRows rows per strip.
+constexpr int kRevRows = 2;
 struct AdjTask {
   int32_t task;       // index into the Task table (AdjTask i belongs to Task i)
-  int32_t cell0;      // first thread of this task in a launch (a multiple of the block size)
-  int32_t ncell;      // n_rows * n_cols
-  int32_t u_init;     // first unrolled plane: -1 (ghost plane of a periodic sweep) or 0
-  int64_t state_off;  // Real offset of [2][slot][a, b, g][row][col]
+  int32_t u_init;     // last unrolled plane of the reverse: -1 (ghost plane) or 0
+  int32_t strips;     // strips of kRevRows rows
+  int32_t pad;
+  int64_t xbuf_off;   // 64-bit word offset of the exchange buffer [strip][parity][edge][2][3][col][words]
   int64_t gs_off;     // Real offset of this task's dL/dS partial (task array layout)
   int64_t gc_off;     // Real offset of this task's dL/dchi partial (task array layout)
   int64_t seed_off;   // Real offset of the band's seed in the task array layout
 };
 
-struct AdjArgs {
+struct RevArgs {
   char* ws;
   const Task* tasks;
   const AdjTask* atasks;
-  int32_t natasks;
-  int32_t k;  // launch index: each task handles unrolled plane n_unrolled - 1 - k
+  const int32_t* queue;  // [first ticket, AdjTask index] per task, longest first
+  int32_t ntasks;
+  int32_t total_strips;
+  int64_t timeout_ticks;
   const void* gItop[kMaxBoxes];  // per box, [nbands][n_up][ny][nx] or null
   const void* S[kMaxBoxes];      // per box, [nbands][N]
 };
@@ -103,8 +107,9 @@ struct BoxGeo {
 // Workspace header (first 256 bytes).
 struct WsHeader {
   int32_t status;          // 0, or 1 after a neighbour-wait timeout
-  int32_t ticket;          // work-queue counter
-  int32_t pad[62];
+  int32_t ticket;          // work-queue counter of the forward sweep
+  int32_t ticket_rev;      // work-queue counter of the reverse sweep
+  int32_t pad[61];
 };
 
 struct SweepArgs {
