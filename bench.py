@@ -11,8 +11,12 @@ reduction, with inputs already resident in HBM.
 Prints one JSON line.  `value` is nominal cell-ray-band updates per second
 (N * rays * bands per step).  `roofline` describes the sweep kernel, timed
 with HIP events on its own stream inside the timed region.  `cpu_baseline`
-times the FP64 oracle on the grey band of the same workload (full grid, all
-rays) on this host's cores.
+times the FP64 oracle on the whole workload on this host's cores (about 15 s
+with 16 threads).  The schedule (rows per strip, queue order) is picked by
+the library's autotuner before the warm-up unless --rows is given.
+
+Other modes: --adjoint (adjoint/forward time on the 128^3 adjoint workload),
+--workload boxes6 (six uneven boxes in one batched, graph-replayed call).
 """
 import argparse
 import hashlib
@@ -67,9 +71,10 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload):
+def traffic_from_profile(workload, rows):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
+    if it was taken on the current kernel source at the same strip height;
+    else None."""
     f = os.path.join(ROOT, "profiles", f"rts_sweep_{workload}_pmc.json")
     if not os.path.exists(f):
         return None
@@ -77,7 +82,7 @@ def traffic_from_profile(workload):
         d = json.load(open(f))
     except ValueError:
         return None
-    if d.get("kernel_hash") != kernel_hash():
+    if d.get("kernel_hash") != kernel_hash() or d.get("rows_per_strip") != rows:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -125,12 +130,17 @@ def trace_summary(d):
     return out
 
 
-def pmc_summary(workload, fetch_dir, write_dir, cfetch_dir, cwrite_dir):
+def pmc_summary(workload, rows, fetch_dir, write_dir, cfetch_dir, cwrite_dir):
     """HBM bytes per sweep launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
     scaled by the same counters' reading for the plain copy kernel."""
     def per_kernel(d, counter, key):
-        v = [x for n, x in _pmc_rows(d, counter) if key in n]
-        return sum(v) / len(v) if v else None
+        rows = [(n, x) for n, x in _pmc_rows(d, counter) if key in n]
+        if not rows:
+            return None
+        names = [n for n, _ in rows]
+        top = max(set(names), key=names.count)  # the variant the timed steps ran
+        v = [x for n, x in rows if n == top]
+        return sum(v) / len(v)
     f_sweep = per_kernel(fetch_dir, "FETCH_SIZE", "rts_sweep")
     w_sweep = per_kernel(write_dir, "WRITE_SIZE", "rts_sweep")
     rows_cf = [x for n, x in _pmc_rows(cfetch_dir, "FETCH_SIZE") if "copyBuffer" in n]
@@ -140,6 +150,7 @@ def pmc_summary(workload, fetch_dir, write_dir, cfetch_dir, cwrite_dir):
     kf = COPY_BYTES / (cf * 1024) if cf else None
     kw = COPY_BYTES / (cw * 1024) if cw else None
     out = {"workload": workload, "kernel": "rts_sweep", "kernel_hash": kernel_hash(),
+           "rows_per_strip": rows,
            "fetch_kib_per_dispatch": f_sweep, "write_kib_per_dispatch": w_sweep,
            "copy_fetch_kib": cf, "copy_write_kib": cw, "copy_bytes": COPY_BYTES,
            "fetch_scale": kf, "write_scale": kw}
@@ -151,25 +162,22 @@ def pmc_summary(workload, fetch_dir, write_dir, cfetch_dir, cwrite_dir):
     print(json.dumps(out))
 
 
-def cpu_baseline(p_full, seconds_hint=True):
+def cpu_baseline(p_full):
+    """The FP64 oracle on the whole workload (every band, ray and boundary
+    iteration, the same synthetic inputs) on this host's cores."""
     import oracle
-    from paper_2107_08145_amd import inputs
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     threads = max(1, min(16, cores))
-    b = p_full.nbands - 1  # the grey band
-    q = inputs.Problem(p_full.nx, p_full.ny, p_full.nz, p_full.dx, p_full.dy, p_full.dz,
-                       p_full.mu, p_full.w, p_full.kappa[b:b + 1].astype(np.float64),
-                       p_full.rho.astype(np.float64), p_full.S[b:b + 1].astype(np.float64),
-                       np.ones(1), p_full.bot, p_full.top, p_full.i_bot, p_full.n_iter)
+    q = p_full.astype(np.float64)
     oracle._load()
     t0 = time.perf_counter()
     oracle.solve(q, threads=threads)
     dt = time.perf_counter() - t0
-    nominal = q.ncells * q.nrays
+    nominal = q.ncells * q.nrays * q.nbands
     return {"value": nominal / dt, "unit": "cell-ray-band updates/s", "cores": threads,
             "kind": "oracle", "seconds": round(dt, 2),
-            "sample": f"FP64 oracle, grey band of the workload: {q.nx}x{q.ny}x{q.nz}, "
-                      f"{q.nrays} rays, n_iter {q.n_iter}, one band (of {p_full.nbands})"}
+            "sample": f"FP64 oracle, the whole workload: {q.nx}x{q.ny}x{q.nz}, {q.nbands} bands, "
+                      f"{q.nrays} rays, n_iter {q.n_iter} (OpenMP over the cells of a plane)"}
 
 
 def _time_calls(fn, steps, warmup):
@@ -267,7 +275,8 @@ def main():
                     help="time rts_adjoint against rts_solve (default workload adjoint128)")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--size", type=int, default=None, help="cube edge override (debug)")
-    ap.add_argument("--rows", type=int, default=0, help="rows per strip (0: plan default)")
+    ap.add_argument("--rows", type=int, default=0,
+                    help="rows per strip (0: chosen by the library's autotuner)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (scales rocprofv3 byte counters)")
@@ -280,7 +289,7 @@ def main():
         calibrate_copy()
         return
     if args.pmc_summary:
-        pmc_summary(args.workload, *args.pmc_summary)
+        pmc_summary(args.workload, args.rows, *args.pmc_summary)
         return
     if args.trace_summary:
         for n, k, avg_us, tot_ms in trace_summary(args.trace_summary):
@@ -309,10 +318,17 @@ def main():
 
     torch.cuda.set_device(0)
     plan = rts.Plan(pd, prec)
-    if args.rows:
-        plan.set_schedule(rows_per_strip=args.rows)
     ins = plan.device_inputs(pd)
     outs = plan.new_outputs(pd)
+    if args.rows:
+        plan.set_schedule(rows_per_strip=args.rows)
+        tuned = False
+    else:
+        t_tune = time.perf_counter()
+        plan.autotune([ins], [outs], reps=2)
+        tuned = True
+        print(f"# autotuned in {time.perf_counter() - t_tune:.1f}s: {plan.schedule()}",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     for _ in range(args.warmup):
         plan.solve_into([ins], [outs])
@@ -340,7 +356,8 @@ def main():
     gbs = alg_bytes / sw_s / 1e9
     tflops = executed * FLOPS_PER_UPDATE / sw_s / 1e12
     peak_alu = PEAK_FP32_TFLOPS if prec == rts.RTS_FP32 else PEAK_FP64_TFLOPS
-    traffic = traffic_from_profile(args.workload) if args.size is None else None
+    traffic = (traffic_from_profile(args.workload, plan.schedule()["rows_per_strip"])
+               if args.size is None else None)
     if tflops / peak_alu >= gbs / PEAK_HBM_GBS:
         roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": peak_alu, "unit": "TFLOP/s",
                 "frac": round(tflops / peak_alu, 4)}
@@ -359,7 +376,7 @@ def main():
                        f"({'4 opacity bins + grey' if p.nbands == 5 else 'grey'}), "
                        f"{p.nrays} rays S4, n_iter {p.n_iter}, seeded stratified atmosphere",
            "grid": [p.nx, p.ny, p.nz], "bands": p.nbands, "rays": p.nrays, "n_iter": p.n_iter,
-           "schedule": plan.schedule(), "sweep_ms": round(sweep_ms, 4),
+           "schedule": plan.schedule(), "autotuned": tuned, "sweep_ms": round(sweep_ms, 4),
            "call_ms": round(call_ms, 4), "executed_updates_per_s": executed / (ms * 1e-3)}
     out = {"metric": "cell-ray-band updates/sec (288^3 4-band+grey 24-ray RTS)",
            "value": nominal / (ms * 1e-3), "unit": "cell-ray-band updates/s", "n_gpus": 1,
