@@ -78,13 +78,25 @@ __device__ inline double fmad(double a, double b, double c) { return fma(a, b, c
 // that precedes its flag store; a consumer issues its edge-row loads only
 // after its flag load returned the awaited value.  No cache-wide writeback or
 // invalidate is needed, which an agent-scope fence would cost at every plane.
+// Through the global address space explicitly: a generic pointer would make
+// these FLAT instructions, which also count against the LDS wait counter, so
+// every LDS-only barrier would wait for the in-flight neighbour loads.
+#define RTS_GLOBAL __attribute__((address_space(1)))
+// A generic pointer the compiler cannot prove global (loaded from a table or
+// picked by a runtime index) becomes FLAT memory instructions; this cast lets
+// it emit global ones.
+template <class T>
+__device__ inline T* gptr(T* p) {
+  return (T*)(RTS_GLOBAL T*)(uintptr_t)p;
+}
 template <class R>
 __device__ inline R ld_dev(const R* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((const RTS_GLOBAL R*)(uintptr_t)p, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 template <class R>
 __device__ inline void st_dev(R* p, R v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((RTS_GLOBAL R*)(uintptr_t)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Element of a uniform row at a per-lane 32-bit byte offset: lets the
 // compiler use the scalar-base + 32-bit lane offset form of global memory
@@ -275,7 +287,7 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
   int r0 = strip * T.rows_per_strip;
   const int hr = FULL ? H : min(T.rows_per_strip, T.n_rows - r0);
   int ps = (int)T.plane_stride, rs = (int)T.row_stride;
-  int* status = reinterpret_cast<int*>(A.ws);
+  int* status = gptr(reinterpret_cast<int*>(A.ws));
 
   // per-slot constants; FP32 folds log2(e) into ds/2 (see rts_exp_step)
   const Real kx = sizeof(Real) == 4 ? Real(1.4426950408889634) : Real(1);
@@ -291,12 +303,12 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
   const bool zp = T.z_planes != 0;
   const int bc_up = zp ? -1 : 0, bc_dn = zp ? -1 : T.n_rows - 1;
 
-  const Real* chi = reinterpret_cast<const Real*>(A.ws) + T.chi_off;
-  const Real* Sv = T.transposed ? reinterpret_cast<const Real*>(A.ws) + T.s_off
-                                : reinterpret_cast<const Real*>(A.box[T.box].S) + T.s_off;
-  Real* P = reinterpret_cast<Real*>(A.ws) + T.part_off;
+  const Real* chi = gptr(reinterpret_cast<const Real*>(A.ws) + T.chi_off);
+  const Real* Sv = gptr(T.transposed ? reinterpret_cast<const Real*>(A.ws) + T.s_off
+                                     : reinterpret_cast<const Real*>(A.box[T.box].S) + T.s_off);
+  Real* P = gptr(reinterpret_cast<Real*>(A.ws) + T.part_off);
   // exchange buffer of 64-bit words: [strip][parity][edge][slot][column][NW]
-  uint64_t* X = reinterpret_cast<uint64_t*>(A.ws) + T.xbuf_off;
+  uint64_t* X = gptr(reinterpret_cast<uint64_t*>(A.ws) + T.xbuf_off);
 
   const int ns = T.strips;
   const bool per = T.row_periodic != 0;
@@ -362,7 +374,7 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
       }
       *lane_at(urow(P, qo + (r0 + i) * rs), ub) = sum;
     }
-    Real* Itop = reinterpret_cast<Real*>(A.box[T.box].I_top);
+    Real* Itop = gptr(reinterpret_cast<Real*>(A.box[T.box].I_top));
     const int it_row = T.it_top - r0;
     if (Itop && (zp ? (q == T.it_top) : (it_row >= 0 && it_row < hr))) {
 #pragma unroll
@@ -382,7 +394,7 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
   // D of unrolled plane u, kept for the adjoint's reverse sweep
   auto store_d = [&](int u, const Real (&Dn)[H][R]) __attribute__((always_inline)) {
     if (!A.store_d || !act) return;
-    Real* ds = reinterpret_cast<Real*>(A.ws) + T.dstore_off + (int64_t)u * R * T.n_rows * W;
+    Real* ds = gptr(reinterpret_cast<Real*>(A.ws) + T.dstore_off + (int64_t)u * R * T.n_rows * W);
 #pragma unroll
     for (int i = 0; i < H; ++i) {
       if (!FULL && i >= hr) break;
@@ -479,6 +491,10 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
     // (scalar ALU) instead of being hoisted as dozens of live row offsets,
     // which would be spilled.
     asm volatile("" : "+s"(rs), "+s"(ps), "+s"(r0), "+s"(chi), "+s"(Sv), "+s"(P), "+s"(X));
+    chi = gptr(chi);  // the asm hides the address space again
+    Sv = gptr(Sv);
+    P = gptr(P);
+    X = gptr(X);
     const int q = plane_of(t);
     if (t > 0) halo_wait(t);
 
@@ -804,7 +820,7 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
   const int r0 = strip * H;
   const int hr = FULL ? H : min(H, nr - r0);
   const int ps = (int)T.plane_stride, rs = (int)T.row_stride;
-  int* status = reinterpret_cast<int*>(A.ws);
+  int* status = gptr(reinterpret_cast<int*>(A.ws));
   const bool zp = T.z_planes != 0;
   const bool per = T.row_periodic != 0;
   const bool has_lo = per || r0 > 0, has_hi = per || r0 + hr < nr;
@@ -826,16 +842,16 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
     f1[s] = (Real)y.f1; f2[s] = (Real)y.f2; hds[s] = (Real)y.hds; wgt[s] = (Real)y.w;
     itop[s] = y.itop;
   }
-  Real* ws = reinterpret_cast<Real*>(A.ws);
+  Real* ws = gptr(reinterpret_cast<Real*>(A.ws));
   const Real* chi = ws + T.chi_off;
-  const Real* Sv = T.transposed ? ws + T.s_off : reinterpret_cast<const Real*>(A.S[T.box]) + T.s_off;
+  const Real* Sv = gptr(T.transposed ? ws + T.s_off : reinterpret_cast<const Real*>(A.S[T.box]) + T.s_off);
   const Real* Dst = ws + T.dstore_off;
   const Real* seed = ws + AT.seed_off;
   const int64_t N = (int64_t)na * nr * W;
   Real* GS = ws + AT.gs_off + h * N;  // one partial per half
   Real* GC = ws + AT.gc_off + h * N;
-  uint64_t* X = reinterpret_cast<uint64_t*>(A.ws) + AT.xbuf_off;
-  const Real* gI = reinterpret_cast<const Real*>(A.gItop[T.box]);
+  uint64_t* X = gptr(reinterpret_cast<uint64_t*>(A.ws) + AT.xbuf_off);
+  const Real* gI = gptr(reinterpret_cast<const Real*>(A.gItop[T.box]));
   const int64_t pc = (int64_t)nr * W;
   const int xstride = 2 * 3 * W * NW;  // one published edge row: 2 slots x 3 quantities
   const uint32_t cb = (uint32_t)cc * sizeof(Real), xb = (uint32_t)cc * NW * 8;
