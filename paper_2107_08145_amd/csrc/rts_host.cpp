@@ -41,6 +41,7 @@ size_t reverse_lds_bytes(int);
 template <class Real>
 const void* reverse_fn(int cols);
 int reverse_threads(int cols);
+int reverse_parts(int cols);
 template <class Real>
 hipError_t launch_reverse(const RevArgs&, int, int, hipStream_t);
 template <class Real>
@@ -355,11 +356,13 @@ void build_layout(Plan& P) {
   }
   for (size_t t = 0; t < P.tasks.size(); ++t) {
     const Box& B = P.boxes[P.tasks[t].box];
-    // two partials each: the reverse sweep's even-slot and odd-slot threads
+    // one partial per thread of a column of the reverse sweep
+    const int np = reverse_parts(P.threads);
+    P.atasks[t].nparts = np;
     P.atasks[t].gs_off = (int64_t)(off / esz);
-    off = align_up(off + 2 * (size_t)B.N * esz);
+    off = align_up(off + np * (size_t)B.N * esz);
     P.atasks[t].gc_off = (int64_t)(off / esz);
-    off = align_up(off + 2 * (size_t)B.N * esz);
+    off = align_up(off + np * (size_t)B.N * esz);
   }
   P.off_grads_end = off;
   for (Box& B : P.boxes) {

@@ -63,7 +63,7 @@ struct AdjTask {
   int32_t task;       // index into the Task table (AdjTask i belongs to Task i)
   int32_t u_init;     // last unrolled plane of the reverse: -1 (ghost plane) or 0
   int32_t strips;     // strips of kRevRows rows
-  int32_t pad;
+  int32_t nparts;     // gradient partials per quantity (threads per column of the reverse sweep)
   int64_t xbuf_off;   // 64-bit word offset of the exchange buffer [strip][parity][edge][2][3][col][words]
   int64_t gs_off;     // Real offset of this task's dL/dS partial (task array layout)
   int64_t gc_off;     // Real offset of this task's dL/dchi partial (task array layout)

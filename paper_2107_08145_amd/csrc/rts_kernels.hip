@@ -797,11 +797,11 @@ struct RevStrip {
   }
 };
 
-// One strip of one task.  SP slots per thread: with SP = 2 two threads share
-// a column, the first taking the even slots (which read the upper halo and
-// publish the strip's first row), the second the odd slots (lower halo, last
-// row); with SP = 4 one thread takes all four.  Threads of one half form
-// whole waves, so the half is wave-uniform.
+// One strip of one task.  SP slots per thread (4, 2 or 1): NH = 4 / SP
+// threads share a column; part h takes slots h, h + NH, ... (with NH = 2 the
+// even slots, which read the upper halo and publish the strip's first row,
+// and the odd slots, lower halo and last row).  Threads of one part form
+// whole waves, so the part is wave-uniform.
 template <class Real, int H, bool FULL, int SP>
 __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTask& AT,
                                               const int strip, Real* lds) {
@@ -833,7 +833,7 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
   const int last_from = zp ? 0 : (T.laps - 1) * na;
   auto plane_of = [&](int u) { return u < 0 ? q_last : q0 + T.sa * (zp ? u : u % na); };
   // this thread's slots
-  auto slot = [&](int s) { return SP == R ? s : 2 * s + h; };
+  auto slot = [&](int s) { return NH * s + h; };
   Real f1[SP], f2[SP], hds[SP], wgt[SP];
   int itop[SP];
 #pragma unroll
@@ -848,7 +848,7 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
   const Real* Dst = ws + T.dstore_off;
   const Real* seed = ws + AT.seed_off;
   const int64_t N = (int64_t)na * nr * W;
-  Real* GS = ws + AT.gs_off + h * N;  // one partial per half
+  Real* GS = ws + AT.gs_off + h * N;  // one partial per part
   Real* GC = ws + AT.gc_off + h * N;
   uint64_t* X = gptr(reinterpret_cast<uint64_t*>(A.ws) + AT.xbuf_off);
   const Real* gI = gptr(reinterpret_cast<const Real*>(A.gItop[T.box]));
@@ -873,10 +873,11 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
 
   // Global inputs of a step, loaded one step ahead: of the upwind plane u-1,
   // rows -1..H of this column (rows outside a bounded plane are clamped: no
-  // integrated cell reads them), chi or S (by half; both with SP = 4) and D of
-  // this thread's slots; of this plane, chi, S, seeds and gradient partials of
-  // the strip's rows.
+  // integrated cell reads them), chi (part 0) and S (part 1; both with one
+  // part) and D of this thread's slots; of this plane, chi, S, seeds and
+  // gradient partials of the strip's rows.
   constexpr int NQU = NH == 1 ? 2 : 1;
+  const bool loads_cs = NH == 1 || h < 2;
   struct StepIn {
     Real upq[NQU][H + 2], upd[H + 2][SP];
     Real cpv[H], spv[H], sdv[H], gsv[H], gcv[H];
@@ -892,12 +893,13 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
 #pragma unroll
         for (int qq = 0; qq < NQU; ++qq) {
           const bool want_s = NH == 1 ? qq == 1 : h == 1;
-          L.upq[qq][j] = *lane_at(urow(want_s ? Sv : chi, o), cb);
+          if (loads_cs) L.upq[qq][j] = *lane_at(urow(want_s ? Sv : chi, o), cb);
         }
 #pragma unroll
         for (int s = 0; s < SP; ++s)
-          L.upd[j][s] = uu >= 0 ? *lane_at(urow(Dst + (int64_t)uu * R * pc, (slot(s) * nr + up_row(j)) * W), cb)
-                                : Real(0);
+          // unconditional loads (the ghost plane reads plane 0 and ignores it)
+          L.upd[j][s] = *lane_at(urow(Dst + (int64_t)(uu >= 0 ? uu : 0) * R * pc,
+                                      (slot(s) * nr + up_row(j)) * W), cb);
       }
     }
     const int qp = plane_of(u);
@@ -907,7 +909,7 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
       const int o = qp * ps + (r0 + (FULL || i < hr ? i : 0)) * rs;
       L.cpv[i] = *lane_at(urow(chi, o), cb);
       L.spv[i] = *lane_at(urow(Sv, o), cb);
-      L.sdv[i] = last_lap ? *lane_at(urow(seed, o), cb) : Real(0);
+      L.sdv[i] = *lane_at(urow(seed, o), cb);  // used in the last lap only
       L.gsv[i] = *lane_at(urow(GS, o), cb);
       L.gcv[i] = *lane_at(urow(GC, o), cb);
     }
@@ -920,7 +922,7 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
 #pragma unroll
       for (int qq = 0; qq < NQU; ++qq) {
         const bool is_s = NH == 1 ? qq == 1 : h == 1;
-        lc[is_s ? ST::qs(j) : ST::qc(j)] = L.upq[qq][j];
+        if (loads_cs) lc[is_s ? ST::qs(j) : ST::qc(j)] = L.upq[qq][j];
       }
       if (u - 1 >= 0) {
 #pragma unroll
@@ -942,28 +944,26 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
   };
 
   // neighbours' edge words of the downwind state (published at their step
-  // k-1): side 0 (odd slots) from the lower neighbour's last row, side 1 (even
-  // slots) from the upper neighbour's first row; a half takes only its side
-  constexpr int NS = NH == 1 ? 2 : 1;
-  auto side_of = [&](int sd) { return NH == 1 ? sd : 1 - h; };
-  uint64_t hw[NS][2][3][NW];
+  // k-1), for this thread's slots: odd slots from the lower neighbour's last
+  // row (LDS side 0), even slots from the upper neighbour's first row (side 1)
+  uint64_t hw[SP][3][NW];
   auto halo_issue = [&](int k) __attribute__((always_inline)) {
     const int par = (k - 1) & 1;
 #pragma unroll
-    for (int sd = 0; sd < NS; ++sd) {
-      const int side = side_of(sd);
+    for (int s = 0; s < SP; ++s) {
+      const int r = slot(s);
+      const int side = (r & 1) ? 0 : 1;
       const bool has = side == 0 ? has_lo : has_hi;
+      // without a neighbour the strip reads its own words (ignored): no branch
       const int nb = side == 0 ? st_lo : st_hi;
       const int edge = side == 0 ? 1 : 0;
       const int xoff = ((nb * 2 + par) * 2 + edge) * xstride;
 #pragma unroll
-      for (int s2 = 0; s2 < 2; ++s2)
+      for (int m = 0; m < 3; ++m) {
+        const uint64_t* rowp = urow(X, xoff + ((r >> 1) * 3 + m) * W * NW);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          const uint64_t* rowp = urow(X, xoff + (s2 * 3 + m) * W * NW);
-#pragma unroll
-          for (int x = 0; x < NW; ++x) hw[sd][s2][m][x] = has ? ld_dev(lane_at(rowp, xb) + x) : 0ull;
-        }
+        for (int x = 0; x < NW; ++x) hw[s][m][x] = has ? ld_dev(lane_at(rowp, xb) + x) : 0ull;
+      }
     }
   };
   auto halo_wait = [&](int k) __attribute__((always_inline)) {
@@ -971,13 +971,10 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
     auto all_fresh = [&]() __attribute__((always_inline)) {
       bool ok = true;
 #pragma unroll
-      for (int sd = 0; sd < NS; ++sd) {
-        const int side = side_of(sd);
-        const bool has = side == 0 ? has_lo : has_hi;
+      for (int s = 0; s < SP; ++s) {
+        const bool has = (slot(s) & 1) ? has_lo : has_hi;
 #pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-          for (int m = 0; m < 3; ++m) ok = ok && (!has || TG::fresh(hw[sd][s2][m], tag));
+        for (int m = 0; m < 3; ++m) ok = ok && (!has || TG::fresh(hw[s][m], tag));
       }
       return ok;
     };
@@ -995,13 +992,12 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
       }
     }
 #pragma unroll
-    for (int sd = 0; sd < NS; ++sd) {
-      const int side = side_of(sd);
-      const bool has = side == 0 ? has_lo : has_hi;
+    for (int s = 0; s < SP; ++s) {
+      const int r = slot(s);
+      const bool has = (r & 1) ? has_lo : has_hi;
 #pragma unroll
-      for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-        for (int m = 0; m < 3; ++m) lc[ST::qh(side, s2, m)] = has ? TG::value(hw[sd][s2][m]) : Real(0);
+      for (int m = 0; m < 3; ++m)
+        lc[ST::qh((r & 1) ? 0 : 1, r >> 1, m)] = has ? TG::value(hw[s][m]) : Real(0);
     }
   };
 
@@ -1014,9 +1010,9 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
 #pragma unroll
       for (int m = 0; m < 3; ++m) lc[ST::qw(i, slot(s), m)] = Real(0);
 #pragma unroll
-  for (int sd = 0; sd < NS; ++sd)
+  for (int s = 0; s < SP; ++s)
 #pragma unroll
-    for (int q = 0; q < 6; ++q) lc[ST::qh(side_of(sd), 0, 0) + q] = Real(0);
+    for (int m = 0; m < 3; ++m) lc[ST::qh((slot(s) & 1) ? 0 : 1, slot(s) >> 1, m)] = Real(0);
 
   const int top = FULL ? H - 1 : hr - 1;
   // one step; the caller alternates the two input buffers (no register copies)
@@ -1156,7 +1152,8 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
 
 // MAXT: the block-size bound; SP: slots per thread (2: two threads per column)
 template <class Real, int MAXT, int SP>
-__global__ __launch_bounds__(MAXT) void rts_reverse(RevArgs A) {
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(1, 1024 / MAXT * 2)))
+void rts_reverse(RevArgs A) {
   extern __shared__ char smem_raw[];
   Real* lds = reinterpret_cast<Real*>(smem_raw);
   __shared__ int sh_ticket;
@@ -1210,8 +1207,8 @@ __global__ __launch_bounds__(256) void rts_adj_seed(const Real* __restrict__ kap
   }
 }
 
-// Gradients of one box: the task partials (two per task, one per half of the
-// reverse sweep's threads) summed in a fixed order (FP64),
+// Gradients of one box: the task partials (one per part of the reverse
+// sweep's threads of a column) summed in a fixed order (FP64),
 // plus the direct terms dL/dS_b += gJ_b (+ sum_r gItop_b,r in the top layer)
 // and dL/dchi_b += 4 pi qweight_b (J_b - S_b) gQ, where J_b - S_b is the sum
 // of the forward partials.
@@ -1243,8 +1240,10 @@ __global__ __launch_bounds__(256) void rts_adj_reduce(const char* __restrict__ w
           const int y = y0 + ty + 8 * i, x = x0 + tx;
           if (x < nx && y < ny) {
             const int64_t p = ((int64_t)z * ny + y) * nx + x;
-            as[i] += (double)gs[p] + (double)gs[p + N];
-            ac[i] += (double)gc[p] + (double)gc[p + N];
+            for (int h = 0; h < AT.nparts; ++h) {
+              as[i] += (double)gs[p + h * N];
+              ac[i] += (double)gc[p + h * N];
+            }
             aj[i] += (double)pj[p];
           }
         }
@@ -1254,8 +1253,13 @@ __global__ __launch_bounds__(256) void rts_adj_reduce(const char* __restrict__ w
           const int x = x0 + ty + 8 * i, y = y0 + tx;
           if (x < nx && y < ny) {
             const int64_t p = ((int64_t)x * nz + z) * ny + y;
-            t0[ty + 8 * i][tx] = (double)gs[p] + (double)gs[p + N];
-            t1[ty + 8 * i][tx] = (double)gc[p] + (double)gc[p + N];
+            double vs = 0, vc = 0;
+            for (int h = 0; h < AT.nparts; ++h) {
+              vs += (double)gs[p + h * N];
+              vc += (double)gc[p + h * N];
+            }
+            t0[ty + 8 * i][tx] = vs;
+            t1[ty + 8 * i][tx] = vc;
             t2[ty + 8 * i][tx] = (double)pj[p];
           }
         }
@@ -1338,14 +1342,16 @@ hipError_t launch_reduce(const char* ws, const Task* tasks, const BoxGeo& g, con
   return hipGetLastError();
 }
 
-// Reverse sweep launch shape for `cols` padded columns: two threads per column
-// up to 512 columns (block bound 512 up to 256 columns), else one.
+// Reverse sweep launch shape for `cols` padded columns: two threads per
+// column up to 512 columns (block bound 512, i.e. up to 256 VGPRs, up to 256
+// columns), else one.
 template <class Real>
 size_t reverse_lds_bytes(int cols) {
   return (size_t)RevStrip<Real, kRevRows>::NQP * cols * sizeof(Real);
 }
 
-int reverse_threads(int cols) { return cols <= 512 ? 2 * cols : cols; }
+int reverse_parts(int cols) { return cols <= 512 ? 2 : 1; }
+int reverse_threads(int cols) { return reverse_parts(cols) * cols; }
 
 template <class Real>
 const void* reverse_fn(int cols) {
