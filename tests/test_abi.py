@@ -171,3 +171,26 @@ def test_autotune_workspace_and_errors():
     assert L.rts_plan_autotune(pl.handle, 1, ctypes.byref(ci), ctypes.byref(co),
                                ctypes.c_void_p(100), n_tune, None, 1,
                                ctypes.byref(sch)) == rts.RTS_E_WORKSPACE
+
+
+def test_size_limits_rejected():
+    p = inputs.workload("grey32", size=8)
+    for field, value, code in (("nx", 1025, rts.RTS_E_UNSUPPORTED), ("nx", 1, rts.RTS_E_ARG)):
+        q = inputs.workload("grey32", size=8)
+        setattr(q, field, value)
+        q.kappa = np.ones((1, q.nz, q.ny, q.nx))
+        q.S = np.ones((1, q.nz, q.ny, q.nx))
+        q.rho = np.ones((q.nz, q.ny, q.nx))
+        with pytest.raises(rts.RTSError) as e:
+            rts.Plan(q)
+        assert e.value.status == code
+    q = inputs.random_problem(4, 4, 4, seed=1, bands=17)
+    with pytest.raises(rts.RTSError) as e:
+        rts.Plan(q)
+    assert e.value.status == rts.RTS_E_UNSUPPORTED
+    q = inputs.random_problem(4, 4, 4, seed=1)
+    q.mu = np.array([[1.0, 0.0, 0.0]])  # mu_z = 0: no vertical boundary
+    q.w = np.ones(1)
+    with pytest.raises(rts.RTSError) as e:
+        rts.Plan(q)
+    assert e.value.status == rts.RTS_E_ARG

@@ -183,3 +183,40 @@ def test_autotune_keeps_results():
     # cached: a second plan of the same shape takes the same schedule without timing
     pl2 = rts.Plan(p, rts.RTS_FP32)
     assert pl2.autotune([ins], [outs], reps=1) == chosen
+
+
+def test_max_columns_and_extreme_opacity():
+    # 1024 columns (the largest supported row), 16 + 1 threads' waves per strip;
+    # opacities from 1e-6 (optically thin: x << 0.1, the series branch) to 1e4
+    # (optically thick: e underflows to 0)
+    p = _rand_problem(1024, 6, 5, seed=77, lo=1e-6, hi=1e4)
+    print("case max columns", flush=True)
+    _check64(p, rts.solve(p, rts.RTS_FP64), oracle.solve(p, threads=8))
+    p32 = p.astype(np.float32)
+    _check32(p32, rts.solve(p32, rts.RTS_FP32), oracle.solve(p32.astype(np.float64), threads=8))
+
+
+def test_many_bands_and_rays():
+    # the largest band count (16) and a 64-ray quadrature of random directions
+    r = np.random.default_rng(5)
+    p = _rand_problem(12, 10, 9, seed=78, bands=16)
+    mu = r.standard_normal((64, 3))
+    mu[:, 2] = np.where(np.abs(mu[:, 2]) < 0.05, 0.3, mu[:, 2])
+    mu /= np.linalg.norm(mu, axis=1, keepdims=True)
+    p.mu = mu
+    p.w = np.full(64, 1 / 64)
+    p.qweight = r.uniform(0, 1, 16)
+    print("case 16 bands 64 rays", flush=True)
+    _check64(p, rts.solve(p, rts.RTS_FP64), oracle.solve(p, threads=8))
+
+
+def test_axis_aligned_in_plane_components():
+    # rays with a zero in-plane component (f = 0: the upwind point is on a
+    # grid line) and exactly diagonal ones (ties of the dominant axis)
+    p = _rand_problem(14, 12, 10, seed=79)
+    s = 1 / math.sqrt(2)
+    t = 1 / math.sqrt(3)
+    p.mu = np.array([[0, 0, 1.0], [0, 0, -1.0], [s, 0, s], [0, -s, -s], [t, t, t], [-t, t, -t]])
+    p.w = np.full(6, 1 / 6)
+    print("case axis-aligned rays", flush=True)
+    _check64(p, rts.solve(p, rts.RTS_FP64), oracle.solve(p, threads=8))
