@@ -246,11 +246,13 @@ def bench_batched(args):
     pds = [p.astype(np.float32 if prec == rts.RTS_FP32 else np.float64) for p in ps]
     torch.cuda.set_device(0)
     plan = rts.Plan(pds, prec)
-    if args.rows:
-        plan.set_schedule(rows_per_strip=args.rows)
-    plan.set_schedule(use_graph=1)
     ins = [plan.device_inputs(p) for p in pds]
     outs = [plan.new_outputs(p) for p in pds]
+    if args.rows:
+        plan.set_schedule(rows_per_strip=args.rows)
+    else:
+        plan.autotune(ins, outs, reps=1)
+    plan.set_schedule(use_graph=1)
     ms = _time_calls(lambda: plan.solve_into(ins, outs, batched=True), args.steps, args.warmup)
     plan.check_status()
     nominal = sum(p.ncells * p.nrays * p.nbands for p in ps)
