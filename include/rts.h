@@ -128,7 +128,10 @@ typedef struct {
  * share `prec`.  On success *out receives the plan. */
 int rts_plan_create(const rts_desc* descs, int32_t nbox, void** out);
 
-/* Bytes of device workspace needed by `op` (rts_op) on this plan. */
+/* Bytes of device workspace needed by `op` (rts_op) on this plan: RTS_OP_SOLVE
+ * for rts_solve / rts_solve_batched, RTS_OP_ADJOINT for rts_adjoint (it also
+ * holds D of every plane of every ray group: at 128^3 with 24 rays and 3
+ * iterations, 0.8 GB in FP32), RTS_OP_AUTOTUNE for rts_plan_autotune. */
 int rts_workspace_bytes(void* plan, int32_t op, size_t* bytes);
 
 /* Forward solve of box 0 of the plan (paper: the RTS call of one time step). */
@@ -150,8 +153,10 @@ int rts_solve_batched(void* plan, int32_t nbox, const rts_inputs* in, const rts_
  * "Summary of the Radiation Transport Solver" section as implemented by
  * rts_solve): the call re-runs the forward sweep, storing D of every plane
  * and lap in the workspace, then sweeps the transposed recursion downwind to
- * upwind, one launch per plane, recomputing the exp and interpolation weights
- * from the stored upwind D.  Seeds may be NULL (zero).  dS and dchi are
+ * upwind in one persistent launch (strips of two rows exchanging edge rows,
+ * like the forward sweep), recomputing the exp and interpolation weights from
+ * the stored upwind D.  Returns RTS_E_UNSUPPORTED if the strips of one task
+ * cannot all be resident.  Seeds may be NULL (zero).  dS and dchi are
  * overwritten; chi = kappa * rho, so dL/dkappa_b = rho dL/dchi_b and
  * dL/drho = sum_b kappa_b dL/dchi_b.  Per-task partials are summed in a
  * fixed order in FP64: results are bitwise reproducible for a fixed plan. */

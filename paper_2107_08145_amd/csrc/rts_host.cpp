@@ -304,7 +304,6 @@ void build_layout(Plan& P) {
   for (Task& T : P.tasks) {
     T.xbuf_off = (int64_t)(off / sizeof(uint64_t));
     off = align_up(off + (size_t)T.strips * 2 * 2 * kMaxRaysPerTask * T.n_cols * words * sizeof(uint64_t));
-    T.flag_off = 0;
   }
   P.off_tasks = off;
   off = align_up(off + sizeof(Task) * P.tasks.size());

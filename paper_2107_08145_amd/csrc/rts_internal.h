@@ -42,14 +42,13 @@ struct Task {
   int64_t s_off;           // element offset of S: into the box's S (natural) or workspace
   int64_t part_off;        // element offset of the partial sum array in the workspace
   int64_t xbuf_off;        // 64-bit-word offset of the neighbour exchange buffer
-  int64_t flag_off;        // unused
   int64_t it_off;          // element offset of this band's I_top block in the box I_top
   int64_t itp, itr, itc;   // I_top strides for (plane, row, col)
   int64_t it_ray;          // I_top stride between up rays (ny * nx)
   int64_t dstore_off;      // element offset of the stored D of every plane [u][slot][row][col]
   int32_t n_unrolled;      // planes u of the unrolled sweep (u = 0 first plane after the ghost,
                            // or the boundary plane when planes are z)
-  int32_t pad1;
+  int32_t pad;
   double pl_a, pl_b;       // boundary-plane value D = pl_a * S + pl_b (z_planes)
   double bu_a, bu_b;       // boundary row 0 of even slots (rows are z, mu_z > 0)
   double bd_a, bd_b;       // boundary row n_rows-1 of odd slots (rows are z, mu_z < 0)

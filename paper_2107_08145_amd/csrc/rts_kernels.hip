@@ -109,7 +109,6 @@ template <class T>
 __device__ inline const T* lane_at(const T* row, uint32_t boff) {
   return reinterpret_cast<const T*>(reinterpret_cast<const char*>(row) + boff);
 }
-__device__ inline void vmem_drain() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS accesses,
 // not for its outstanding global stores (the sweep's global stores are read by
