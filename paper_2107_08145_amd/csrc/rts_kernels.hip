@@ -1121,24 +1121,21 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
           const Real v1 = lerp(lcc[qo_], cn[qo_], f1[s]);
           tq[m] = lerp(v0, v1, f2[s]);
         }
-        Real lam = tq[0];
-        if (last_lap) {
-          lam = fmad(wgt[s], cur.sdv[i], lam);
-          if (gI && itop[s] >= 0 && (zp ? qp == T.it_top : gi == T.it_top))
-            lam += gI[T.it_off + itop[s] * T.it_ray + (int64_t)qp * T.itp + (int64_t)gi * T.itr +
-                      (int64_t)cc * T.itc];
-        }
+        Real lam = fmad(wgt[s], last_lap ? cur.sdv[i] : Real(0), tq[0]);
+        if (last_lap && gI && itop[s] >= 0 && (zp ? qp == T.it_top : gi == T.it_top))
+          lam += gI[T.it_off + itop[s] * T.it_ray + (int64_t)qp * T.itp + (int64_t)gi * T.itr +
+                    (int64_t)cc * T.itc];
+        // Branch-free: the forward step is recomputed for every cell (the LDS
+        // rows it reads always hold finite values) and selected away for
+        // boundary cells, D = coef S + const, which pass coef lambda to S.
         const int br = up ? 0 : nr - 1;
         const Real bca = up ? bua : bda;
+        const bool bc_row = !zp && gi == br;
+        const bool comp = !ghost && !bcplane && !bc_row;
+        const Real coef = ghost ? (gi == br ? bca : Real(0)) : (bcplane ? pla : bca);
         Real a = 0, b = 0, g = 0;
-        if (ghost) {
-          if (gi == br) gs = fmad(bca, lam, gs);
-        } else if (bcplane) {
-          gs = fmad(pla, lam, gs);
-        } else if (!zp && gi == br) {
-          gs = fmad(bca, lam, gs);
-        } else {
-          // the forward step of this cell from the upwind plane in LDS
+        // (FP64 keeps the branch: its longer recompute would cost registers)
+        if (sizeof(Real) == 4 || comp) {
           const int ju = up ? j - 1 : j + 1;
           const Real* cu = r < 2 ? lcm : lcp;  // upwind column c + sc
           const Real bcx = lerp(lerp(lcc[ST::qc(j)], cu[ST::qc(j)], f1[s]),
@@ -1151,14 +1148,12 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
           const Real e = rts_exp_neg(x);
           const Real cw = rts_cw(x, e);
           const Real dc = rts_dcw(x, e, cw);
-          a = e * lam;
-          b = cw * lam;
-          g = hds[s] * lam * fmad(-e, bdx, dc * (bsx - cur.spv[i]));
-          gs -= b;
-          gc += g;
+          a = comp ? e * lam : Real(0);
+          b = comp ? cw * lam : Real(0);
+          g = comp ? hds[s] * lam * fmad(-e, bdx, dc * (bsx - cur.spv[i])) : Real(0);
         }
-        gs += tq[1];
-        gc += tq[2];
+        gs = fmad(comp ? Real(0) : coef, lam, gs) - b + tq[1];
+        gc += g + tq[2];
         nst[i][s][0] = a;
         nst[i][s][1] = b;
         nst[i][s][2] = g;
@@ -1360,6 +1355,99 @@ __global__ __launch_bounds__(256) void rts_adj_reduce(const char* __restrict__ w
   }
 }
 
+// The same with 16-byte accesses, for FP32 and nx a multiple of 4: a thread
+// owns four consecutive x of one row; partials of x-sweeps go through LDS.
+__global__ __launch_bounds__(256) void rts_adj_reduce_v4(const char* __restrict__ ws,
+                                                        const Task* __restrict__ tasks,
+                                                        const AdjTask* __restrict__ atasks,
+                                                        BoxGeo G, const double* __restrict__ gQ,
+                                                        const float* __restrict__ gJ,
+                                                        const float* __restrict__ gItop,
+                                                        float* __restrict__ dS,
+                                                        float* __restrict__ dchi) {
+  __shared__ double t0[32][33], t1[32][33], t2[32][33];
+  const int t = threadIdx.x;
+  const int qx = (t & 7) * 4, ry = t >> 3;
+  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32, z = blockIdx.z;
+  const int nx = G.nx, ny = G.ny, nz = G.nz;
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int x = x0 + qx, y = y0 + ry;
+  const bool in = x < nx && y < ny;
+  const int64_t p = ((int64_t)z * ny + y) * nx + x;
+  const float* w = gptr(reinterpret_cast<const float*>(ws));
+  for (int b = 0; b < G.nbands; ++b) {
+    double as[4] = {0, 0, 0, 0}, ac[4] = {0, 0, 0, 0}, aj[4] = {0, 0, 0, 0};
+    for (int k = 0; k < G.tasks_per_band; ++k) {
+      const int ti = G.task0 + b * G.tasks_per_band + k;
+      const Task& T = tasks[ti];
+      const AdjTask& AT = atasks[ti];
+      const float* gs = w + AT.gs_off;
+      const float* gc = w + AT.gc_off;
+      const float* pj = w + T.part_off;
+      if (!T.transposed) {
+        if (in) {
+          for (int h = 0; h < AT.nparts; ++h) {
+            const float4 a = *reinterpret_cast<const float4*>(gs + p + h * N);
+            const float4 c = *reinterpret_cast<const float4*>(gc + p + h * N);
+            as[0] += (double)a.x; as[1] += (double)a.y; as[2] += (double)a.z; as[3] += (double)a.w;
+            ac[0] += (double)c.x; ac[1] += (double)c.y; ac[2] += (double)c.z; ac[3] += (double)c.w;
+          }
+          const float4 j = *reinterpret_cast<const float4*>(pj + p);
+          aj[0] += (double)j.x; aj[1] += (double)j.y; aj[2] += (double)j.z; aj[3] += (double)j.w;
+        }
+      } else {
+        __syncthreads();
+        const int yc = t & 31;
+        for (int xr = t >> 5; xr < 32; xr += 8) {
+          const int xx = x0 + xr, yy = y0 + yc;
+          if (xx < nx && yy < ny) {
+            const int64_t q = ((int64_t)xx * nz + z) * ny + yy;
+            double vs = 0, vc = 0;
+            for (int h = 0; h < AT.nparts; ++h) {
+              vs += (double)gs[q + h * N];
+              vc += (double)gc[q + h * N];
+            }
+            t0[xr][yc] = vs;
+            t1[xr][yc] = vc;
+            t2[xr][yc] = (double)pj[q];
+          }
+        }
+        __syncthreads();
+        if (in) {
+          for (int e = 0; e < 4; ++e) {
+            as[e] += t0[qx + e][ry];
+            ac[e] += t1[qx + e][ry];
+            aj[e] += t2[qx + e][ry];
+          }
+        }
+      }
+    }
+    if (in) {
+      const double qf = 4.0 * 3.14159265358979323846 * G.qweight[b];
+      double vs[4] = {as[0], as[1], as[2], as[3]}, vc[4] = {ac[0], ac[1], ac[2], ac[3]};
+      if (gJ) {
+        const float4 j = *reinterpret_cast<const float4*>(gJ + b * N + p);
+        vs[0] += (double)j.x; vs[1] += (double)j.y; vs[2] += (double)j.z; vs[3] += (double)j.w;
+      }
+      if (gItop && z == nz - 1)
+        for (int r = 0; r < G.n_up; ++r) {
+          const float4 g = *reinterpret_cast<const float4*>(gItop + (((int64_t)b * G.n_up + r) * ny + y) * nx + x);
+          vs[0] += (double)g.x; vs[1] += (double)g.y; vs[2] += (double)g.z; vs[3] += (double)g.w;
+        }
+      if (gQ) {
+        const double2 q01 = *reinterpret_cast<const double2*>(gQ + p);
+        const double2 q23 = *reinterpret_cast<const double2*>(gQ + p + 2);
+        vc[0] += qf * aj[0] * q01.x; vc[1] += qf * aj[1] * q01.y;
+        vc[2] += qf * aj[2] * q23.x; vc[3] += qf * aj[3] * q23.y;
+      }
+      *reinterpret_cast<float4*>(dS + b * N + p) =
+          make_float4((float)vs[0], (float)vs[1], (float)vs[2], (float)vs[3]);
+      *reinterpret_cast<float4*>(dchi + b * N + p) =
+          make_float4((float)vc[0], (float)vc[1], (float)vc[2], (float)vc[3]);
+    }
+  }
+}
+
 }  // namespace rts
 
 // ---------------------------------------------------------------------------
@@ -1459,8 +1547,14 @@ hipError_t launch_adj_reduce(const char* ws, const Task* tasks, const AdjTask* a
                              const BoxGeo& g, const double* gQ, const void* gJ, const void* gItop,
                              void* dS, void* dchi, hipStream_t st) {
   dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, g.nz);
-  hipLaunchKernelGGL(rts_adj_reduce<Real>, grid, dim3(256), 0, st, ws, tasks, atasks, g, gQ,
-                     (const Real*)gJ, (const Real*)gItop, (Real*)dS, (Real*)dchi);
+  const uintptr_t al = (uintptr_t)gQ | (uintptr_t)gJ | (uintptr_t)gItop | (uintptr_t)dS |
+                       (uintptr_t)dchi;
+  if (sizeof(Real) == 4 && g.nx % 4 == 0 && al % 16 == 0)
+    hipLaunchKernelGGL(rts_adj_reduce_v4, grid, dim3(256), 0, st, ws, tasks, atasks, g, gQ,
+                       (const float*)gJ, (const float*)gItop, (float*)dS, (float*)dchi);
+  else
+    hipLaunchKernelGGL(rts_adj_reduce<Real>, grid, dim3(256), 0, st, ws, tasks, atasks, g, gQ,
+                       (const Real*)gJ, (const Real*)gItop, (Real*)dS, (Real*)dchi);
   return hipGetLastError();
 }
 
