@@ -259,6 +259,7 @@ def bench_batched(args):
     plan.set_schedule(use_graph=1)
     ms = _time_calls(lambda: plan.solve_into(ins, outs, batched=True), args.steps, args.warmup)
     plan.check_status()
+    print(f"# batched forward {ms:.3f} ms", file=sys.stderr, flush=True)
     nominal = sum(p.ncells * p.nrays * p.nbands for p in ps)
     out = {"metric": "cell-ray-band updates/sec (six uneven boxes, 4-band+grey, 24 rays, batched)",
            "value": nominal / (ms * 1e-3), "unit": "cell-ray-band updates/s", "n_gpus": 1,
@@ -267,6 +268,58 @@ def bench_batched(args):
            "dtype": "f32" if prec == rts.RTS_FP32 else "f64", "data": "synthetic",
            "config": {"workload": "boxes6: " + ", ".join(f"{p.nx}x{p.ny}x{p.nz}" for p in ps),
                       "schedule": plan.schedule()}}
+    if args.adjoint:
+        # one rts_adjoint call over the boxes whose reverse sweep fits: the
+        # 576^2 planes of the first box need more LDS per strip than a CU has
+        # at the strip count its 576 rows need (rts_adjoint: RTS_E_UNSUPPORTED)
+        sub = [i for i, p in enumerate(ps) if max(p.nx, p.ny) <= 512]
+        aplan = rts.Plan([pds[i] for i in sub], prec)
+        ains = [ins[i] for i in sub]
+        fwd_sub = _time_calls(lambda: aplan.solve_into(ains, [outs[i] for i in sub], batched=True),
+                              max(1, args.steps // 2), 1)
+        seeds, grads = [], []
+        for i in sub:
+            p = ps[i]
+            g = np.random.default_rng(5000 + i + 2).random((p.nz, p.ny, p.nx))
+            seeds.append((torch.as_tensor(g, device="cuda"), None, None))
+            grads.append((torch.empty(p.S.shape, dtype=plan.dtype, device="cuda"),
+                          torch.empty(p.S.shape, dtype=plan.dtype, device="cuda")))
+        adj_ms = _time_calls(lambda: aplan.adjoint_into(ains, seeds, grads), max(1, args.steps // 2), 1)
+        aplan.check_status()
+        print(f"# adjoint of {len(sub)} boxes {adj_ms:.3f} ms, forward {fwd_sub:.3f} ms",
+              file=sys.stderr, flush=True)
+        out["adjoint"] = {"boxes": [f"{ps[i].nx}x{ps[i].ny}x{ps[i].nz}" for i in sub],
+                          "ms": round(adj_ms, 3), "forward_ms": round(fwd_sub, 3),
+                          "ratio_to_forward": round(adj_ms / fwd_sub, 3),
+                          "workspace_bytes": aplan.workspace_bytes(rts.RTS_OP_ADJOINT)}
+        if args.errors:
+            import oracle
+            errs = []
+            for n, i in enumerate(sub):
+                p = ps[i]
+                if p.ncells > 5_000_000:
+                    continue  # the oracle's reverse mode keeps every sweep: small boxes only
+                ref = oracle.adjoint(pds[i].astype(np.float64), seeds[n][0].cpu().numpy(),
+                                     threads=16)
+                got = [t.double().cpu().numpy() for t in grads[n]]
+                errs.append({"box": f"{p.nx}x{p.ny}x{p.nz}",
+                             "dS": float(np.abs(got[0] - ref[0]).max() / np.abs(ref[0]).max()),
+                             "dchi": float(np.abs(got[1] - ref[1]).max() / np.abs(ref[1]).max())})
+                print(f"# adjoint box {errs[-1]}", file=sys.stderr, flush=True)
+            out["adjoint"]["errors_vs_oracle"] = errs
+    if args.errors:
+        import oracle
+        plan.solve_into(ins, outs, batched=True)
+        torch.cuda.synchronize()
+        errs = []
+        for p, pd, o in zip(ps, pds, outs):
+            ref = oracle.solve(pd.astype(np.float64), threads=16)
+            got = [t.double().cpu().numpy() for t in o]
+            errs.append({"box": f"{p.nx}x{p.ny}x{p.nz}"} |
+                        {k: float(np.abs(g - r).max() / np.abs(r).max())
+                         for k, g, r in zip(("Q", "J", "I_top"), got, ref)})
+            print(f"# box {errs[-1]}", file=sys.stderr, flush=True)
+        out["errors_vs_oracle"] = errs
     print(json.dumps(out), flush=True)
 
 
@@ -280,6 +333,8 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="time rts_adjoint against rts_solve (default workload adjoint128)")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--errors", action="store_true",
+                    help="boxes6: also the max relative error of every box against the oracle")
     ap.add_argument("--size", type=int, default=None, help="cube edge override (debug)")
     ap.add_argument("--rows", type=int, default=0,
                     help="rows per strip (0: chosen by the library's autotuner)")
@@ -309,11 +364,11 @@ def main():
     import torch
     from paper_2107_08145_amd import inputs, rts
 
-    if args.adjoint:
-        bench_adjoint(args)
-        return
     if args.workload == "boxes6":
         bench_batched(args)
+        return
+    if args.adjoint:
+        bench_adjoint(args)
         return
     t_gen = time.perf_counter()
     p = inputs.workload(args.workload, size=args.size)

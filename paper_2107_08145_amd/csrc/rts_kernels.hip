@@ -1503,21 +1503,24 @@ hipError_t launch_reduce(const char* ws, const Task* tasks, const BoxGeo& g, con
   return hipGetLastError();
 }
 
-// Reverse sweep launch shape for `cols` padded columns: two threads per
-// column up to 512 columns (block bound 512, i.e. up to 256 VGPRs, up to 256
-// columns), else one.
+// Reverse sweep launch shape for `cols` padded columns: up to 256 columns,
+// two threads per column (two slots each) in a block of at most 512 threads;
+// up to 512 columns, one thread per column (four slots) in 512 threads; above,
+// one thread per column in 1024 threads.  A block bound of 512 allows 256
+// VGPRs per lane, which the four-slot state nearly fills; 1024 allows 128 and
+// spills.
 template <class Real>
 size_t reverse_lds_bytes(int cols) {
   return (size_t)RevStrip<Real, kRevRows>::NQP * cols * sizeof(Real);
 }
 
-int reverse_parts(int cols) { return cols <= 512 ? 2 : 1; }
+int reverse_parts(int cols) { return cols <= 256 ? 2 : 1; }
 int reverse_threads(int cols) { return reverse_parts(cols) * cols; }
 
 template <class Real>
 const void* reverse_fn(int cols) {
   if (cols <= 256) return reinterpret_cast<const void*>(&rts_reverse<Real, 512, 2>);
-  if (cols <= 512) return reinterpret_cast<const void*>(&rts_reverse<Real, 1024, 2>);
+  if (cols <= 512) return reinterpret_cast<const void*>(&rts_reverse<Real, 512, 4>);
   return reinterpret_cast<const void*>(&rts_reverse<Real, 1024, 4>);
 }
 
@@ -1526,7 +1529,7 @@ hipError_t launch_reverse(const RevArgs& a, int grid, int cols, hipStream_t st) 
   const size_t lds = reverse_lds_bytes<Real>(cols);
   const dim3 b(reverse_threads(cols));
   if (cols <= 256) rts_reverse<Real, 512, 2><<<dim3(grid), b, lds, st>>>(a);
-  else if (cols <= 512) rts_reverse<Real, 1024, 2><<<dim3(grid), b, lds, st>>>(a);
+  else if (cols <= 512) rts_reverse<Real, 512, 4><<<dim3(grid), b, lds, st>>>(a);
   else rts_reverse<Real, 1024, 4><<<dim3(grid), b, lds, st>>>(a);
   return hipGetLastError();
 }

@@ -100,6 +100,28 @@ def test_adjoint_fp32_matches_oracle():
     print(f"adjoint fp32: {e:.2e}")
 
 
+# Planes wider than 256 columns take the one-thread-per-column reverse shapes:
+# a 512-thread block up to 512 columns, a 1024-thread block above.
+@pytest.mark.parametrize("prec,shape", [(rts.RTS_FP32, (300, 20, 9)),
+                                        (rts.RTS_FP64, (300, 12, 8)),
+                                        (rts.RTS_FP32, (520, 10, 6))])
+def test_adjoint_wide_planes(prec, shape):
+    nx, ny, nz = shape
+    p = inputs.random_problem(nx, ny, nz, seed=nx + ny, bands=2)
+    print("case adjoint wide", prec, shape, flush=True)
+    tol = 1e-10 if prec == rts.RTS_FP64 else 2e-4
+    e = _run(p, prec, _seeds(p, 8), tol)
+    print(f"adjoint wide {shape}: {e:.2e}")
+
+
+def test_adjoint_fp64_plane_beyond_lds_is_unsupported():
+    # 520 FP64 columns need more LDS per reverse strip than a CU has
+    p = inputs.random_problem(520, 6, 4, seed=3)
+    print("case adjoint fp64 520 columns", flush=True)
+    with pytest.raises(rts.RTSError, match="UNSUPPORTED"):
+        rts.adjoint(p, rts.RTS_FP64, *_seeds(p, 9))
+
+
 def test_adjoint128_fp32_small_matches_oracle():
     p = inputs.workload("adjoint128", size=32)
     print("case adjoint128 size 32 fp32", flush=True)
