@@ -77,7 +77,7 @@ def kernel_hash():
 
 def traffic_from_profile(workload, rows):
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source at the same strip height;
+    if it was taken on the current kernel source and holds this strip height;
     else None."""
     f = os.path.join(ROOT, "profiles", f"rts_sweep_{workload}_pmc.json")
     if not os.path.exists(f):
@@ -86,9 +86,9 @@ def traffic_from_profile(workload, rows):
         d = json.load(open(f))
     except ValueError:
         return None
-    if d.get("kernel_hash") != kernel_hash() or d.get("rows_per_strip") != rows:
+    if d.get("kernel_hash") != kernel_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("by_rows", {}).get(str(rows), {}).get("hbm_bytes_per_launch")
 
 
 COPY_BYTES = 1 << 30
@@ -136,7 +136,8 @@ def trace_summary(d):
 
 def pmc_summary(workload, rows, fetch_dir, write_dir, cfetch_dir, cwrite_dir):
     """HBM bytes per sweep launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
-    scaled by the same counters' reading for the plain copy kernel."""
+    scaled by the same counters' reading for the plain copy kernel.  Merged
+    into the summary file by strip height while the kernel source is unchanged."""
     def per_kernel(d, counter, key):
         rows = [(n, x) for n, x in _pmc_rows(d, counter) if key in n]
         if not rows:
@@ -153,15 +154,24 @@ def pmc_summary(workload, rows, fetch_dir, write_dir, cfetch_dir, cwrite_dir):
     cw = max(rows_cw) if rows_cw else None
     kf = COPY_BYTES / (cf * 1024) if cf else None
     kw = COPY_BYTES / (cw * 1024) if cw else None
-    out = {"workload": workload, "kernel": "rts_sweep", "kernel_hash": kernel_hash(),
-           "rows_per_strip": rows,
-           "fetch_kib_per_dispatch": f_sweep, "write_kib_per_dispatch": w_sweep,
-           "copy_fetch_kib": cf, "copy_write_kib": cw, "copy_bytes": COPY_BYTES,
-           "fetch_scale": kf, "write_scale": kw}
+    entry = {"fetch_kib_per_dispatch": f_sweep, "write_kib_per_dispatch": w_sweep}
     if f_sweep and w_sweep and kf and kw:
-        out["hbm_bytes_per_launch"] = f_sweep * 1024 * kf + w_sweep * 1024 * kw
+        entry["hbm_bytes_per_launch"] = f_sweep * 1024 * kf + w_sweep * 1024 * kw
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     path = os.path.join(ROOT, "profiles", f"rts_sweep_{workload}_pmc.json")
+    by_rows = {}
+    if os.path.exists(path):
+        try:
+            old = json.load(open(path))
+            if old.get("kernel_hash") == kernel_hash():
+                by_rows = old.get("by_rows", {})
+        except ValueError:
+            pass
+    by_rows[str(rows)] = entry
+    out = {"workload": workload, "kernel": "rts_sweep", "kernel_hash": kernel_hash(),
+           "copy_fetch_kib": cf, "copy_write_kib": cw, "copy_bytes": COPY_BYTES,
+           "fetch_scale": kf, "write_scale": kw,
+           "by_rows": dict(sorted(by_rows.items(), key=lambda kv: int(kv[0])))}
     json.dump(out, open(path, "w"), indent=1)
     print(json.dumps(out))
 
