@@ -46,12 +46,14 @@ def _load():
         head = [i, i, i, d, d, d, i, i, p, p, p, i, i, d, i]
         lib.oracle_solve.argtypes = head + [p, p, p, p, p, p, i]
         lib.oracle_solve_chi.argtypes = head + [p, p, p, p, p, i]
+        lib.oracle_flux.argtypes = head + [p, p, p, p, p, p, p, p, i]
+        lib.oracle_flux_divergence.argtypes = [i, i, i, d, d, d, p, p]
         lib.oracle_adjoint.argtypes = head + [p, p, p, p, p, p, p, i]
         lib.oracle_complex_step.argtypes = head + [p, p, i, i64, d, p, p, p, i]
         lib.oracle_ray.argtypes = [i, i, i, d, d, d, p, i, i, d, i, p, p, p]
         lib.oracle_weights.argtypes = [d, p, p, p, p]
         for f in ("oracle_solve", "oracle_solve_chi", "oracle_adjoint",
-                  "oracle_complex_step", "oracle_ray"):
+                  "oracle_complex_step", "oracle_ray", "oracle_flux", "oracle_flux_divergence"):
             getattr(lib, f).restype = i
         lib.oracle_weights.restype = None
         _lib = lib
@@ -97,6 +99,40 @@ def solve(p, threads: int = 1, chi=None):
         raise ValueError("oracle rejected the problem")
     del keep
     return Q, J, It
+
+
+def flux(p, threads: int = 1):
+    """Forward solve with the radiative flux vector.
+
+    Returns (Q, J, I_top, F [3,nz,ny,nx] (x, y, z components of
+    sum_b qweight_b 4 pi sum_r w_r mu_r I_r), QF [nz,ny,nx] = -div F) in float64.
+    """
+    lib = _load()
+    keep, head = _head(p)
+    B = p.nbands
+    Q = np.empty((p.nz, p.ny, p.nx))
+    J = np.empty((B, p.nz, p.ny, p.nx))
+    It = np.empty((B, p.n_up, p.ny, p.nx))
+    F = np.empty((3, p.nz, p.ny, p.nx))
+    QF = np.empty((p.nz, p.ny, p.nx))
+    kap, rho, S = _f64(p.kappa), _f64(p.rho), _f64(p.S)
+    rc = lib.oracle_flux(*head, _ptr(kap), _ptr(rho), _ptr(S), _ptr(Q), _ptr(J), _ptr(It),
+                         _ptr(F), _ptr(QF), threads)
+    if rc:
+        raise ValueError("oracle rejected the problem")
+    del keep
+    return Q, J, It, F, QF
+
+
+def flux_divergence(F, dx: float, dy: float, dz: float):
+    """-div F [nz,ny,nx] of a flux field F [3,nz,ny,nx], with the differences of flux()."""
+    lib = _load()
+    F = _f64(F)
+    _, nz, ny, nx = F.shape
+    QF = np.empty((nz, ny, nx))
+    if lib.oracle_flux_divergence(nx, ny, nz, dx, dy, dz, _ptr(F), _ptr(QF)):
+        raise ValueError("oracle rejected the grid")
+    return QF
 
 
 def chi_of(p):

@@ -37,6 +37,10 @@
 //     n_iter sweeps.  Rays with a z dominant axis need no ghost: one sweep.
 //   * Flux: J_b = sum_r w_r I_r after the last sweep; I_top = I in the top
 //     layer for mu_z > 0 rays; Q = sum_b qweight_b 4 pi chi_b (J_b - S_b).
+//   * Radiative flux vector (the flux step computes mean intensity and fluxes
+//     from the same rays): F = sum_b qweight_b 4 pi sum_r w_r mu_r I_r, and the
+//     heating -div F by central differences (periodic in x and y; second-order
+//     one-sided differences in the bottom and top layers).
 //   * Adjoint: the reverse-mode derivative of the above (downwind to upwind,
 //     last sweep first, ghost sensitivities carried into the previous sweep).
 //
@@ -245,12 +249,14 @@ void solve_ray(const Desc& D, const Ray& r, const T* chi, const T* S, T* I,
 
 template <class T>
 int forward(const Desc& D, const T* chi, const T* S, T* Q, T* J, T* Itop, int nt,
-            std::vector<std::vector<T>>* store, std::vector<T>* Jall) {
+            std::vector<std::vector<T>>* store, std::vector<T>* Jall, T* F = nullptr) {
   const int64_t N = D.cells();
   std::vector<Ray> rays(D.nr);
   for (int r = 0; r < D.nr; ++r)
     if (!make_ray(D, D.mu + 3 * r, rays[r])) return -1;
   for (int64_t p = 0; p < N; ++p) Q[p] = 0.0;
+  if (F)
+    for (int64_t p = 0; p < 3 * N; ++p) F[p] = 0.0;
   std::vector<T> I(N), Jb(N);
   const int64_t plane = (int64_t)D.n[0] * D.n[1];
   int nup = 0;
@@ -263,6 +269,11 @@ int forward(const Desc& D, const T* chi, const T* S, T* Q, T* J, T* Itop, int nt
     for (int r = 0; r < D.nr; ++r) {
       solve_ray(D, rays[r], chib, Sb, I.data(), store, nt);
       for (int64_t p = 0; p < N; ++p) Jb[p] += D.w[r] * I[p];
+      if (F)
+        for (int k = 0; k < 3; ++k) {
+          const double fk = 4.0 * kPi * D.qw[b] * D.w[r] * D.mu[3 * r + k];
+          for (int64_t p = 0; p < N; ++p) F[k * N + p] += fk * I[p];
+        }
       if (rays[r].up) {
         if (Itop) {
           T* dst = Itop + ((int64_t)b * nup + ru) * plane;
@@ -425,6 +436,37 @@ int adjoint(const Desc& D, const double* chi, const double* S, const double* gQ,
   return 0;
 }
 
+// Heating by the flux divergence, QF = -(dFx/dx + dFy/dy + dFz/dz): central
+// differences, periodic in x and y; in z one-sided second-order differences in
+// the bottom and top layers (first-order differences when nz = 2).
+void flux_divergence(const Desc& D, const double* F, double* QF) {
+  const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
+  const int64_t N = D.cells();
+  const double* Fx = F;
+  const double* Fy = F + N;
+  const double* Fz = F + 2 * N;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int ip = (i + 1) % nx, im = (i + nx - 1) % nx;
+        const int jp = (j + 1) % ny, jm = (j + ny - 1) % ny;
+        const double ddx = (Fx[D.at(ip, j, k)] - Fx[D.at(im, j, k)]) / (2 * D.d[0]);
+        const double ddy = (Fy[D.at(i, jp, k)] - Fy[D.at(i, jm, k)]) / (2 * D.d[1]);
+        double ddz;
+        if (nz == 2) {
+          ddz = (Fz[D.at(i, j, 1)] - Fz[D.at(i, j, 0)]) / D.d[2];
+        } else if (k == 0) {
+          ddz = (-3 * Fz[D.at(i, j, 0)] + 4 * Fz[D.at(i, j, 1)] - Fz[D.at(i, j, 2)]) / (2 * D.d[2]);
+        } else if (k == nz - 1) {
+          ddz = (3 * Fz[D.at(i, j, k)] - 4 * Fz[D.at(i, j, k - 1)] + Fz[D.at(i, j, k - 2)]) /
+                (2 * D.d[2]);
+        } else {
+          ddz = (Fz[D.at(i, j, k + 1)] - Fz[D.at(i, j, k - 1)]) / (2 * D.d[2]);
+        }
+        QF[D.at(i, j, k)] = -(ddx + ddy + ddz);
+      }
+}
+
 Desc make_desc(int nx, int ny, int nz, double dx, double dy, double dz, int nb, int nr,
                const double* mu, const double* w, const double* qw, int bot, int top,
                double ibot, int n_iter) {
@@ -471,6 +513,38 @@ int oracle_solve(int nx, int ny, int nz, double dx, double dy, double dz, int nb
     for (int64_t p = 0; p < N; ++p) chi[b * N + p] = kappa[b * N + p] * rho[p];
   return forward<double>(D, chi.data(), S, Q, J, Itop, nthreads > 0 ? nthreads : 1, nullptr,
                          nullptr);
+}
+
+// Forward solve with the radiative flux vector F [3][N] (x, y, z components,
+// summed over bands with qweight) and, if QF is not null, the heating -div F
+// [N]; Q, J and Itop as in oracle_solve (J, Itop may be null).
+int oracle_flux(int nx, int ny, int nz, double dx, double dy, double dz, int nb, int nr,
+                const double* mu, const double* w, const double* qw, int bot, int top,
+                double ibot, int n_iter, const double* kappa, const double* rho,
+                const double* S, double* Q, double* J, double* Itop, double* F, double* QF,
+                int nthreads) {
+  Desc D = make_desc(nx, ny, nz, dx, dy, dz, nb, nr, mu, w, qw, bot, top, ibot, n_iter);
+  if (!valid(D) || !F) return -1;
+  const int64_t N = D.cells();
+  std::vector<double> chi((size_t)nb * N);
+  for (int b = 0; b < nb; ++b)
+    for (int64_t p = 0; p < N; ++p) chi[b * N + p] = kappa[b * N + p] * rho[p];
+  const int rc = forward<double>(D, chi.data(), S, Q, J, Itop, nthreads > 0 ? nthreads : 1,
+                                 nullptr, nullptr, F);
+  if (rc) return rc;
+  if (QF) flux_divergence(D, F, QF);
+  return 0;
+}
+
+// Divergence heating -div F [N] of a given flux field F [3][N] (the same
+// differences as oracle_flux).
+int oracle_flux_divergence(int nx, int ny, int nz, double dx, double dy, double dz,
+                           const double* F, double* QF) {
+  Desc D = make_desc(nx, ny, nz, dx, dy, dz, 1, 1, nullptr, nullptr, nullptr, 0, 0, 0.0, 1);
+  for (int d = 0; d < 3; ++d)
+    if (D.n[d] < 2 || !(D.d[d] > 0)) return -1;
+  flux_divergence(D, F, QF);
+  return 0;
 }
 
 // Intensity of one ray for one band (I [N]) after all its sweeps.

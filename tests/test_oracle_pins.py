@@ -421,3 +421,87 @@ def test_adjoint_central_difference(oracle_mod):
         Lm = (gQ * oracle_mod.solve(p, chi=cm)[0]).sum()
         fd = (Lp - Lm) / (2 * h)
         assert abs(dchi.flat[idx] - fd) <= 1e-6 * abs(fd) + 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Radiative flux vector F = sum_b qw_b 4 pi sum_r w_r mu_r I_r and -div F
+
+
+def test_flux_isothermal_box_is_zero(oracle_mod):
+    # I = B for every ray: F = 4 pi B sum_r w_r mu_r = 0 for the symmetric S4 set
+    nx, ny, nz = 6, 5, 7
+    chi, _ = _rand_atm(nx, ny, nz, 3, 1e-3, 1e3)
+    B0 = 2.75
+    p = _problem(nx, ny, nz, chi, np.full((nz, ny, nx), B0), top=1)
+    _, _, _, F, QF = oracle_mod.flux(p)
+    assert np.abs(F).max() < 1e-12 * 4 * math.pi * B0
+    assert np.abs(QF).max() < 1e-11 * 4 * math.pi * B0
+
+
+def test_flux_source_linear_in_tau_closed_form(oracle_mod):
+    # every ray z-dominant (dx = dy = 3 dz), chi constant, S = a + b tau: the
+    # exact intensities give F_z in closed form; deep inside a thick slab F_z
+    # is the diffusion flux 4 pi b / 3 (second moment of S4 = 1/3), F_x = F_y = 0
+    nx, ny, nz = 4, 4, 40
+    dz = 0.5
+    chi0, a, bb = 3.0, 0.8, 0.6
+    z = np.arange(nz) * dz
+    tau = chi0 * (z[-1] - z)
+    S = (a + bb * tau)[:, None, None] * np.ones((nz, ny, nx))
+    p = _problem(nx, ny, nz, np.full((nz, ny, nx), chi0), S, dx=3 * dz, dy=3 * dz, dz=dz,
+                 qw=np.array([1.0]))
+    _, _, _, F, QF = oracle_mod.flux(p)
+    mu, w = p.mu, p.w
+    Fz = np.zeros(nz)
+    for r in range(24):
+        mz = abs(mu[r, 2])
+        if mu[r, 2] > 0:
+            I = a + bb * tau + bb * mz - bb * mz * np.exp(-(tau[0] - tau) / mz)
+        else:
+            I = a * (1 - np.exp(-tau / mz)) + bb * (tau - mz + mz * np.exp(-tau / mz))
+        Fz += 4 * math.pi * w[r] * mu[r, 2] * I
+    assert np.allclose(F[2], Fz[:, None, None], rtol=1e-12, atol=1e-13)
+    assert np.abs(F[:2]).max() < 1e-12 * np.abs(Fz).max()
+    mid = nz // 2
+    assert abs(F[2, mid, 0, 0] - 4 * math.pi * bb / 3) < 1e-12
+    # F is uniform in the interior: no heating there
+    assert np.abs(QF[nz // 3:2 * nz // 3]).max() < 1e-9
+
+
+def test_flux_divergence_exact_differences(oracle_mod):
+    # central differences of a periodic sine and second-order one-sided and
+    # central differences of a quadratic are exact
+    nx, ny, nz = 8, 6, 7
+    dx, dy, dz = 0.7, 1.3, 0.4
+    i = np.arange(nx)[None, None, :]
+    j = np.arange(ny)[None, :, None]
+    zz = (np.arange(nz) * dz)[:, None, None]
+    tx, ty = 2 * math.pi / nx, 2 * math.pi / ny
+    al, be, ga = 0.3, -1.1, 0.45
+    F = np.zeros((3, nz, ny, nx))
+    F[0] = np.sin(tx * i) * np.ones((nz, ny, nx))
+    F[1] = np.cos(ty * j) * np.ones((nz, ny, nx))
+    F[2] = (al + be * zz + ga * zz * zz) * np.ones((nz, ny, nx))
+    want = -(np.cos(tx * i) * math.sin(tx) / dx - np.sin(ty * j) * math.sin(ty) / dy
+             + be + 2 * ga * zz)
+    got = oracle_mod.flux_divergence(F, dx, dy, dz)
+    assert np.allclose(got, want * np.ones((nz, ny, nx)), rtol=0, atol=1e-12)
+
+
+def test_flux_divergence_approaches_heating(oracle_mod):
+    # summing the transfer equation over the quadrature gives
+    # div F = 4 pi chi (S - J): the flux-divergence heating approaches
+    # Q = 4 pi chi (J - S) as the grid is refined (first order for short
+    # characteristics with bilinear interpolation)
+    def run(n, L=4.0):
+        dz = L / n
+        x = (np.arange(n) + 0.5) * dz
+        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+        chi = 2.0 * np.exp(-Z / 2.0) * (1 + 0.2 * np.sin(2 * math.pi * X / L))
+        S = (1 + 0.3 * np.exp(-Z)) * (1 + 0.2 * np.cos(2 * math.pi * Y / L))
+        p = _problem(n, n, n, chi, S, dx=dz, dy=dz, dz=dz, top=1, qw=np.array([1.0]))
+        Q, _, _, _, QF = oracle_mod.flux(p, threads=8)
+        return np.abs(QF - Q)[n // 4:3 * n // 4].max() / np.abs(Q).max()
+    d = [run(n) for n in (12, 24, 48)]
+    assert d[0] / d[1] > 1.8 and d[1] / d[2] > 1.8, d
+    assert d[2] < 0.05, d
