@@ -251,6 +251,69 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_flux(args):
+    """The radiative flux vector F and its divergence heating QF on the
+    benchmark workload: one flux plan, autotuned with the flux outputs, timed
+    with (F, QF) and without them (F = QF = NULL: the same kernels as the plain
+    solve).  The flux's own kernels are timed with HIP events on the stream."""
+    import torch
+    from paper_2107_08145_amd import inputs, rts
+    p = inputs.workload(args.workload, size=args.size)
+    prec = rts.RTS_FP32 if args.prec == "fp32" else rts.RTS_FP64
+    pd = p.astype(np.float32 if prec == rts.RTS_FP32 else np.float64)
+    torch.cuda.set_device(0)
+    plan = rts.Plan(pd, prec, flux=True)
+    ins = plan.device_inputs(pd)
+    outs = plan.new_outputs(pd, want_flux=True)
+    if args.rows:
+        plan.set_schedule(rows_per_strip=args.rows)
+    else:
+        plan.autotune([ins], [outs], reps=1)
+    print(f"# flux plan schedule {plan.schedule()}", file=sys.stderr, flush=True)
+
+    def timed(o):
+        plan.enable_timing(True)
+        ms = _time_calls(lambda: plan.solve_into([ins], [o]), args.steps, args.warmup)
+        sweep_ms, call_ms = plan.last_timing()
+        plan.enable_timing(False)
+        plan.check_status()
+        return ms, sweep_ms, call_ms
+    ms_f, sw_f, call_f = timed(outs)
+    ms_0, sw_0, call_0 = timed(outs[:3])
+    print(f"# with flux {ms_f:.3f} ms (sweep {sw_f:.3f}), without {ms_0:.3f} ms (sweep {sw_0:.3f})",
+          file=sys.stderr, flush=True)
+    N = p.ncells
+    nominal = N * p.nrays * p.nbands
+    out = {"metric": "cell-ray-band updates/sec with the flux vector F and -div F "
+                     "(288^3 4-band+grey 24-ray RTS)",
+           "value": nominal / (ms_f * 1e-3), "unit": "cell-ray-band updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_f, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if prec == rts.RTS_FP32 else "f64", "data": "synthetic",
+           "sweep_ms": round(sw_f, 4), "call_ms": round(call_f, 4),
+           "without_flux": {"ms_per_step": round(ms_0, 4), "sweep_ms": round(sw_0, 4),
+                            "call_ms": round(call_0, 4)},
+           "flux_overhead": round(ms_f / ms_0 - 1, 4),
+           # flux partial writes: 3 x esz per cell, task and last lap; reduce_flux reads
+           # them and S and writes F (3 x 8 B); the divergence reads F, writes QF
+           "config": {"workload": f"{args.workload}: {p.nx}x{p.ny}x{p.nz}, {p.nbands} bands, "
+                                  f"{p.nrays} rays, n_iter {p.n_iter}; outputs Q, J, I_top, F, QF",
+                      "schedule": plan.schedule()}}
+    if args.errors:
+        import oracle
+        plan.solve_into([ins], [outs])
+        torch.cuda.synchronize()
+        got = [o.double().cpu().numpy() for o in outs]
+        ref = oracle.flux(pd.astype(np.float64), threads=16)
+        scale = 4 * np.pi * np.abs(ref[1]).max()
+        out["errors_vs_oracle"] = {
+            "F_of_4pi_max_J": float(np.abs(got[3] - ref[3]).max() / scale),
+            "F_of_max_F": float(np.abs(got[3] - ref[3]).max() / np.abs(ref[3]).max()),
+            "QF_of_max_QF": float(np.abs(got[4] - ref[4]).max() / np.abs(ref[4]).max()),
+            "Q": float(np.abs(got[0] - ref[0]).max() / np.abs(ref[0]).max())}
+    print(json.dumps(out), flush=True)
+
+
 def bench_batched(args):
     """All boxes of the six-box workload in one rts_solve_batched call (graph replay)."""
     import torch
@@ -343,8 +406,10 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="time rts_adjoint against rts_solve (default workload adjoint128)")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--flux", action="store_true",
+                    help="time the solve with the flux vector F and -div F (flux plan)")
     ap.add_argument("--errors", action="store_true",
-                    help="boxes6: also the max relative error of every box against the oracle")
+                    help="boxes6 and --flux: also the max relative errors against the oracle")
     ap.add_argument("--size", type=int, default=None, help="cube edge override (debug)")
     ap.add_argument("--rows", type=int, default=0,
                     help="rows per strip (0: chosen by the library's autotuner)")
@@ -379,6 +444,9 @@ def main():
         return
     if args.adjoint:
         bench_adjoint(args)
+        return
+    if args.flux:
+        bench_flux(args)
         return
     t_gen = time.perf_counter()
     p = inputs.workload(args.workload, size=args.size)

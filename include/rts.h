@@ -16,6 +16,9 @@
  *   chi_b = kappa_b * rho;  dtau = ds/2 (chi_p + chi_u) with bilinear upwind
  *   values;  I_p = e I_u + w0 S_p + w1 S_u (S linear in tau), e = exp(-dtau);
  *   J_b = sum_r w_r I_r;  Q = sum_b qweight_b * 4 pi * chi_b * (J_b - S_b).
+ *   Optional radiative flux vector (the flux step computes the mean intensity
+ *   and the radiative fluxes from the same rays):
+ *   F = sum_b qweight_b * 4 pi * sum_r w_r mu_r I_r, and its heating QF = -div F.
  *   The library sweeps D = I - S, an exact rewrite of the same recursion:
  *   D_p = e D_u + c (S_u - S_p), c = (1 - e)/dtau.
  *
@@ -85,6 +88,8 @@ typedef struct {
   double i_bot;           /* intensity for RTS_BOT_FIXED */
   int32_t n_iter;         /* >= 1: sweeps of rays whose dominant axis is x or y */
   int32_t prec;           /* rts_precision */
+  int32_t flux;           /* 0 or 1: the workspace also holds three flux partials per sweep
+                             task, so that rts_solve / rts_solve_batched can write F and QF */
 } rts_desc;
 
 typedef struct {
@@ -98,6 +103,10 @@ typedef struct {
   void* J;     /* [nbands][N] mean intensity, or NULL */
   void* I_top; /* [nbands][n_up][ny][nx] intensity of the top layer for the n_up rays with
                   mu_z > 0 (in ray order), or NULL */
+  double* F;   /* [3][N] flux vector (x, y, z components) sum_b qweight_b 4 pi sum_r w_r mu_r I_r,
+                  or NULL; non-NULL needs the box's desc.flux (else RTS_E_ARG) */
+  double* QF;  /* [N] heating -div F, or NULL; needs F: central differences, periodic in x and
+                  y, second-order one-sided in the bottom and top layers (first-order if nz = 2) */
 } rts_outputs;
 
 /* Adjoint seeds: L = <gQ, Q> + <gJ, J> + <gItop, I_top>; any may be NULL. */

@@ -37,6 +37,11 @@ hipError_t launch_sweep_h(const SweepArgs&, int, int, hipStream_t);
 template <class Real>
 hipError_t launch_reduce(const char*, const Task*, const BoxGeo&, const BoxPtrs&, hipStream_t);
 template <class Real>
+hipError_t launch_reduce_flux(const char*, const Task*, const BoxGeo&, const void*, double*,
+                              hipStream_t);
+hipError_t launch_flux_div(const double*, double*, int, int, int, double, double, double,
+                           hipStream_t);
+template <class Real>
 size_t reverse_lds_bytes(int);
 template <class Real>
 const void* reverse_fn(int cols);
@@ -158,6 +163,7 @@ int validate_desc(const rts_desc& d) {
   if (d.bot != RTS_BOT_THERMAL && d.bot != RTS_BOT_FIXED) return RTS_E_ARG;
   if (d.top != RTS_TOP_ZERO && d.top != RTS_TOP_THERMAL) return RTS_E_ARG;
   if (d.prec != RTS_FP64 && d.prec != RTS_FP32) return RTS_E_ARG;
+  if (d.flux != 0 && d.flux != 1) return RTS_E_ARG;
   if (!finite(d.i_bot)) return RTS_E_ARG;
   for (int r = 0; r < d.nrays; ++r) {
     const double* m = d.mu + 3 * r;
@@ -252,6 +258,7 @@ void build_layout(Plan& P) {
       }
       ++T.nrays;
       RayGeo g = ray_geo(d.g, &B.mu[3 * r]);
+      for (int m = 0; m < 3; ++m) y.wm[m] = B.w[r] * B.mu[3 * r + m];
       y.f1 = g.ds * std::fabs(g.mu[col_axis]) / dd[col_axis];
       y.f2 = g.ds * std::fabs(g.mu[row_axis]) / dd[row_axis];
       y.hds = 0.5 * g.ds;
@@ -332,6 +339,12 @@ void build_layout(Plan& P) {
     }
     T.part_off = (int64_t)(off / esz);
     off = align_up(off + (size_t)B.N * esz);
+    T.n_cells = B.N;
+    T.flux_off = -1;
+    if (B.d.flux) {  // x, y, z flux partials of the task
+      T.flux_off = (int64_t)(off / esz);
+      off = align_up(off + 3 * (size_t)B.N * esz);
+    }
   }
   P.total = off;
 
@@ -500,6 +513,8 @@ BoxGeo box_geo(const Plan& P, size_t b) {
   for (size_t t = 0; t < P.tasks.size(); ++t)
     if (P.tasks[t].box == (int)b) { G.task0 = (int)t; break; }
   for (int k = 0; k < B.d.nbands; ++k) G.qweight[k] = B.qw[k];
+  for (int r = 0; r < B.d.nrays; ++r)
+    for (int m = 0; m < 3; ++m) G.msum[m] += B.w[r] * B.mu[3 * r + m];
   return G;
 }
 
@@ -533,6 +548,9 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
     a.box[b] = out ? BoxPtrs{in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top}
                    : BoxPtrs{in[b].kappa, in[b].rho, in[b].S, nullptr, nullptr, nullptr};
   a.store_d = out ? 0 : 1;
+  a.flux = 0;
+  if (out)
+    for (size_t b = 0; b < P.boxes.size(); ++b) a.flux |= out[b].F != nullptr;
   // Every strip of a task must be resident together (neighbouring strips wait
   // on each other), so the grid never drops below the largest task's strip
   // count; tickets are claimed in order, hence with that many resident
@@ -548,6 +566,14 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
     const BoxGeo G = box_geo(P, b);
     RTS_HIP(launch_reduce<Real>(ws, reinterpret_cast<const Task*>(ws + P.off_tasks), G,
                                 a.box[b], st));
+    if (out[b].F) {
+      RTS_HIP(launch_reduce_flux<Real>(ws, reinterpret_cast<const Task*>(ws + P.off_tasks), G,
+                                       in[b].S, out[b].F, st));
+      if (out[b].QF) {
+        const rts_grid& g = P.boxes[b].d.g;
+        RTS_HIP(launch_flux_div(out[b].F, out[b].QF, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, st));
+      }
+    }
   }
   return RTS_OK;
 }
@@ -602,6 +628,9 @@ int check_call(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
   if (nbox != (int)P->boxes.size()) return RTS_E_ARG;
   for (int b = 0; b < nbox; ++b) {
     if (!in[b].kappa || !in[b].rho || !in[b].S || !out[b].Q) return RTS_E_ARG;
+    // the flux vector needs the plan's flux partials; its divergence needs F
+    if (out[b].F && !P->boxes[b].d.flux) return RTS_E_ARG;
+    if (out[b].QF && !out[b].F) return RTS_E_ARG;
   }
   if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 || ws_bytes < P->total)
     return RTS_E_WORKSPACE;
@@ -653,7 +682,8 @@ int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
   // graph path: key on every pointer the captured work uses
   std::vector<const void*> key{ws};
   for (int b = 0; b < nbox; ++b) {
-    key.insert(key.end(), {in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top});
+    key.insert(key.end(), {in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top,
+                           out[b].F, out[b].QF});
   }
   if (!P->gexec || key != P->gkey) {
     if (P->gexec) {

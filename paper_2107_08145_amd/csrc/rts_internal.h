@@ -19,6 +19,7 @@ struct TaskRay {
   double w;        // quadrature weight
   int32_t itop;    // index among rays with mu_z > 0, or -1
   int32_t ray;     // input ray index, or -1 for an unused slot
+  double wm[3];    // w mu_x, w mu_y, w mu_z: weights of the flux partials
 };
 
 // One sweep task: up to four rays of one band of one box that share the
@@ -41,6 +42,8 @@ struct Task {
   int64_t chi_off;         // element offset of this band's chi view in the workspace
   int64_t s_off;           // element offset of S: into the box's S (natural) or workspace
   int64_t part_off;        // element offset of the partial sum array in the workspace
+  int64_t flux_off;        // element offset of the three flux partials [3][n_cells], or -1
+  int64_t n_cells;         // cells of the box
   int64_t xbuf_off;        // 64-bit-word offset of the neighbour exchange buffer
   int64_t it_off;          // element offset of this band's I_top block in the box I_top
   int64_t itp, itr, itc;   // I_top strides for (plane, row, col)
@@ -101,6 +104,7 @@ struct BoxGeo {
   int64_t chiT_off;        // chi^T [nbands][nx][nz][ny]
   int64_t sT_off;          // S^T   [nbands][nx][nz][ny]
   double qweight[16];
+  double msum[3];          // sum_r w_r mu_r (the flux of an isotropic unit intensity / 4 pi)
 };
 
 // Workspace header (first 256 bytes).
@@ -119,7 +123,7 @@ struct SweepArgs {
   int32_t total_strips;
   int64_t timeout_ticks;   // s_memrealtime ticks before a wait gives up
   int32_t store_d;         // also store D of every plane (forward pass of the adjoint)
-  int32_t pad;
+  int32_t flux;            // also write the flux partials sum_r w_r mu_r D_r
   BoxPtrs box[kMaxBoxes];
 };
 

@@ -15,10 +15,13 @@
 //                    (periodic directions: n_iter laps), and exchanges its
 //                    edge rows with the neighbouring strips through tagged
 //                    words in the workspace.  It sweeps D = I - S (see rts.h).
+//  * rts_reduce_flux, rts_flux_div : the radiative flux vector from the
+//                    per-task flux partials (FP64), and its divergence heating.
 //  * rts_reduce    : FP64 sum of the per-task partial J - S arrays in a fixed
 //                    order, Q, J (the paper's "flux" step).
-//  * rts_adj_*     : the adjoint: seeds, the reverse sweep (one launch per
-//                    plane of every task) and the FP64 gradient reduction.
+//  * rts_adj_*, rts_reverse : the adjoint: seeds, the reverse sweep (one
+//                    persistent launch over the strips of every task) and the
+//                    FP64 gradient reduction.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -269,7 +272,7 @@ struct LRow {
 // then the interior rows) and, after a barrier, a write phase that stores the
 // new plane; a second barrier ends the step.  Addresses of global data are a
 // uniform row pointer plus the thread's column.
-template <class Real, int H, bool UNI, bool FULL>
+template <class Real, int H, bool UNI, bool FULL, bool FLUX>
 __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const int strip,
                                           Real* lds) {
   using ST = Strip<Real, H>;
@@ -372,6 +375,21 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
         sum = fmad(wgt[1], Dn[i][1], wgt[0] * Dn[i][0]) + fmad(wgt[3], Dn[i][3], wgt[2] * Dn[i][2]);
       }
       *lane_at(urow(P, qo + (r0 + i) * rs), ub) = sum;
+    }
+    if (FLUX && T.flux_off >= 0) {  // (a box without flux partials writes none)
+      // flux partials sum_r (w mu_k)_r D_r, k = x, y, z, in the same layout
+      Real* Fp = gptr(reinterpret_cast<Real*>(A.ws) + T.flux_off);
+#pragma unroll
+      for (int i = 0; i < H; ++i) {
+        if (!FULL && i >= hr) break;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          Real f = Real(0);
+#pragma unroll
+          for (int r = 0; r < R; ++r) f = fmad((Real)T.ray[r].wm[m], Dn[i][r], f);
+          *lane_at(urow(Fp + m * T.n_cells, qo + (r0 + i) * rs), ub) = f;
+        }
+      }
     }
     Real* Itop = gptr(reinterpret_cast<Real*>(A.box[T.box].I_top));
     const int it_row = T.it_top - r0;
@@ -642,7 +660,9 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
   }
 }
 
-template <class Real, int H, bool UNI>
+// FLUX: also write the flux partials (a separate instantiation, so that the
+// solve without them keeps its register allocation)
+template <class Real, int H, bool UNI, bool FLUX>
 __global__ __launch_bounds__(1024) void rts_sweep(SweepArgs A) {
   extern __shared__ char smem_raw[];
   Real* lds = reinterpret_cast<Real*>(smem_raw);
@@ -659,9 +679,99 @@ __global__ __launch_bounds__(1024) void rts_sweep(SweepArgs A) {
     while (qi + 1 < A.ntasks && queue[2 * (qi + 1)] <= tk) ++qi;
     CTask& T = ((CTask*)(uintptr_t)A.tasks)[queue[2 * qi + 1]];
     const int strip = tk - queue[2 * qi];
-    if ((strip + 1) * T.rows_per_strip <= T.n_rows) run_strip<Real, H, UNI, true>(A, T, strip, lds);
-    else run_strip<Real, H, UNI, false>(A, T, strip, lds);
+    if ((strip + 1) * T.rows_per_strip <= T.n_rows) run_strip<Real, H, UNI, true, FLUX>(A, T, strip, lds);
+    else run_strip<Real, H, UNI, false, FLUX>(A, T, strip, lds);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Radiative flux vector F = sum_b qweight_b 4 pi (sum_tasks flux partial +
+// S_b sum_r w_r mu_r) in FP64, fixed order; partials of transposed tasks
+// through an LDS tile as in rts_reduce.  F is [3][N].
+template <class Real>
+__global__ __launch_bounds__(256) void rts_reduce_flux(const char* __restrict__ ws,
+                                                      const Task* __restrict__ tasks, BoxGeo G,
+                                                      const Real* __restrict__ S,
+                                                      double* __restrict__ F) {
+  __shared__ Real tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32, z = blockIdx.z;
+  const int nx = G.nx, ny = G.ny, nz = G.nz;
+  const int64_t N = (int64_t)nx * ny * nz;
+  double f[3][4] = {};
+  for (int b = 0; b < G.nbands; ++b) {
+    double acc[3][4] = {};
+    for (int k = 0; k < G.tasks_per_band; ++k) {
+      const Task& T = tasks[G.task0 + b * G.tasks_per_band + k];
+      for (int m = 0; m < 3; ++m) {
+        const Real* part = reinterpret_cast<const Real*>(ws) + T.flux_off + m * N;
+        if (!T.transposed) {
+          for (int i = 0; i < 4; ++i) {
+            const int y = y0 + ty + 8 * i, x = x0 + tx;
+            if (x < nx && y < ny) acc[m][i] += (double)part[((int64_t)z * ny + y) * nx + x];
+          }
+        } else {
+          __syncthreads();
+          for (int i = 0; i < 4; ++i) {
+            const int x = x0 + ty + 8 * i, y = y0 + tx;
+            if (x < nx && y < ny) tile[ty + 8 * i][tx] = part[((int64_t)x * nz + z) * ny + y];
+          }
+          __syncthreads();
+          for (int i = 0; i < 4; ++i) {
+            const int y = y0 + ty + 8 * i, x = x0 + tx;
+            if (x < nx && y < ny) acc[m][i] += (double)tile[tx][ty + 8 * i];
+          }
+        }
+      }
+    }
+    const double qf = 4.0 * 3.14159265358979323846 * G.qweight[b];
+    for (int i = 0; i < 4; ++i) {
+      const int y = y0 + ty + 8 * i, x = x0 + tx;
+      if (x < nx && y < ny) {
+        const double sv = (double)S[b * N + ((int64_t)z * ny + y) * nx + x];
+        for (int m = 0; m < 3; ++m) f[m][i] += qf * (acc[m][i] + sv * G.msum[m]);
+      }
+    }
+  }
+  for (int i = 0; i < 4; ++i) {
+    const int y = y0 + ty + 8 * i, x = x0 + tx;
+    if (x < nx && y < ny)
+      for (int m = 0; m < 3; ++m) F[m * N + ((int64_t)z * ny + y) * nx + x] = f[m][i];
+  }
+}
+
+// Heating by the flux divergence, QF = -(dFx/dx + dFy/dy + dFz/dz), FP64:
+// central differences, periodic in x and y; second-order one-sided in z in
+// the bottom and top layers (first-order when nz = 2).  One thread per cell.
+__global__ __launch_bounds__(256) void rts_flux_div(const double* __restrict__ F,
+                                                   double* __restrict__ QF, int nx, int ny,
+                                                   int nz, double rdx, double rdy, double rdz) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int i = (int)(p % nx);
+  const int j = (int)((p / nx) % ny);
+  const int k = (int)(p / ((int64_t)nx * ny));
+  const int64_t plane = (int64_t)nx * ny;
+  const double* Fx = F;
+  const double* Fy = F + N;
+  const double* Fz = F + 2 * N;
+  const int64_t row = p - i, pl = p - (int64_t)j * nx;
+  const int ip = i + 1 < nx ? i + 1 : 0, im = i > 0 ? i - 1 : nx - 1;
+  const int jp = j + 1 < ny ? j + 1 : 0, jm = j > 0 ? j - 1 : ny - 1;
+  const double ddx = (Fx[row + ip] - Fx[row + im]) * (0.5 * rdx);
+  const double ddy = (Fy[pl + (int64_t)jp * nx] - Fy[pl + (int64_t)jm * nx]) * (0.5 * rdy);
+  double ddz;
+  if (nz == 2) {
+    ddz = (Fz[p + (k == 0 ? plane : 0)] - Fz[p - (k == 0 ? 0 : plane)]) * rdz;
+  } else if (k == 0) {
+    ddz = (-3.0 * Fz[p] + 4.0 * Fz[p + plane] - Fz[p + 2 * plane]) * (0.5 * rdz);
+  } else if (k == nz - 1) {
+    ddz = (3.0 * Fz[p] - 4.0 * Fz[p - plane] + Fz[p - 2 * plane]) * (0.5 * rdz);
+  } else {
+    ddz = (Fz[p + plane] - Fz[p - plane]) * (0.5 * rdz);
+  }
+  QF[p] = -(ddx + ddy + ddz);
 }
 
 // ---------------------------------------------------------------------------
@@ -1481,12 +1591,16 @@ size_t sweep_lds_bytes(int threads) {
 
 template <class Real, int H, bool UNI>
 const void* sweep_fn() {
-  return reinterpret_cast<const void*>(&rts_sweep<Real, H, UNI>);
+  return reinterpret_cast<const void*>(&rts_sweep<Real, H, UNI, false>);
 }
 
 template <class Real, int H, bool UNI>
 hipError_t launch_sweep_h(const SweepArgs& a, int grid, int threads, hipStream_t st) {
-  rts_sweep<Real, H, UNI><<<dim3(grid), dim3(threads), sweep_lds_bytes<Real, H>(threads), st>>>(a);
+  // (the flux variant has the same LDS and register bounds)
+  if (a.flux)
+    rts_sweep<Real, H, UNI, true><<<dim3(grid), dim3(threads), sweep_lds_bytes<Real, H>(threads), st>>>(a);
+  else
+    rts_sweep<Real, H, UNI, false><<<dim3(grid), dim3(threads), sweep_lds_bytes<Real, H>(threads), st>>>(a);
   return hipGetLastError();
 }
 
@@ -1535,6 +1649,23 @@ hipError_t launch_reverse(const RevArgs& a, int grid, int cols, hipStream_t st) 
 }
 
 template <class Real>
+hipError_t launch_reduce_flux(const char* ws, const Task* tasks, const BoxGeo& g, const void* S,
+                              double* F, hipStream_t st) {
+  dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, g.nz);
+  hipLaunchKernelGGL(rts_reduce_flux<Real>, grid, dim3(256), 0, st, ws, tasks, g,
+                     reinterpret_cast<const Real*>(S), F);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_div(const double* F, double* QF, int nx, int ny, int nz, double dx,
+                           double dy, double dz, hipStream_t st) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  hipLaunchKernelGGL(rts_flux_div, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, F, QF,
+                     nx, ny, nz, 1.0 / dx, 1.0 / dy, 1.0 / dz);
+  return hipGetLastError();
+}
+
+template <class Real>
 hipError_t launch_adj_seed(const void* kappa, const void* rho, const double* gQ, const void* gJ,
                            void* seed, void* seedT, double qf, int nx, int ny, int nz,
                            hipStream_t st) {
@@ -1571,6 +1702,10 @@ template hipError_t launch_reduce<float>(const char*, const Task*, const BoxGeo&
                                          hipStream_t);
 template hipError_t launch_reduce<double>(const char*, const Task*, const BoxGeo&, const BoxPtrs&,
                                           hipStream_t);
+template hipError_t launch_reduce_flux<float>(const char*, const Task*, const BoxGeo&,
+                                              const void*, double*, hipStream_t);
+template hipError_t launch_reduce_flux<double>(const char*, const Task*, const BoxGeo&,
+                                               const void*, double*, hipStream_t);
 #define RTS_ADJ_INST(Real)                                                                      \
   template size_t reverse_lds_bytes<Real>(int);                                                 \
   template const void* reverse_fn<Real>(int);                                                   \

@@ -46,7 +46,7 @@ class Desc(ctypes.Structure):
                 ("mu", ctypes.POINTER(ctypes.c_double)), ("w", ctypes.POINTER(ctypes.c_double)),
                 ("qweight", ctypes.POINTER(ctypes.c_double)), ("bot", ctypes.c_int32),
                 ("top", ctypes.c_int32), ("i_bot", ctypes.c_double), ("n_iter", ctypes.c_int32),
-                ("prec", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("flux", ctypes.c_int32)]
 
 
 class Inputs(ctypes.Structure):
@@ -54,7 +54,25 @@ class Inputs(ctypes.Structure):
 
 
 class Outputs(ctypes.Structure):
-    _fields_ = [("Q", ctypes.c_void_p), ("J", ctypes.c_void_p), ("I_top", ctypes.c_void_p)]
+    _fields_ = [("Q", ctypes.c_void_p), ("J", ctypes.c_void_p), ("I_top", ctypes.c_void_p),
+                ("F", ctypes.c_void_p), ("QF", ctypes.c_void_p)]
+
+
+def _ptr_or_none(t):
+    return t.data_ptr() if t is not None else None
+
+
+def _marshal(ins, outs):
+    """C arrays of rts_inputs / rts_outputs; outs entries are (Q, J, I_top) or
+    (Q, J, I_top, F, QF), any but Q may be None."""
+    n = len(ins)
+    ci = (Inputs * n)()
+    co = (Outputs * n)()
+    for i, ((k, r, s), o) in enumerate(zip(ins, outs)):
+        ci[i] = Inputs(k.data_ptr(), r.data_ptr(), s.data_ptr())
+        o = tuple(o) + (None,) * (5 - len(o))
+        co[i] = Outputs(*(_ptr_or_none(t) for t in o))
+    return ci, co
 
 
 class Seeds(ctypes.Structure):
@@ -134,9 +152,11 @@ def _stream_ptr(stream=None):
 class Plan:
     """A librts plan for one or more boxes (paper_2107_08145_amd.inputs.Problem)."""
 
-    def __init__(self, problems, prec: int = RTS_FP64):
+    def __init__(self, problems, prec: int = RTS_FP64, flux=False):
+        """flux: bool, or one bool per box (desc.flux: room for the flux vector)."""
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
+        flags = list(flux) if isinstance(flux, (list, tuple)) else [flux] * len(problems)
         self.problems = list(problems)
         self.prec = prec
         self._keep = []
@@ -153,6 +173,7 @@ class Plan:
             d.w = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             d.qweight = qw.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             d.bot, d.top, d.i_bot, d.n_iter, d.prec = p.bot, p.top, p.i_bot, p.n_iter, prec
+            d.flux = 1 if flags[i] else 0
         h = ctypes.c_void_p()
         _check(lib().rts_plan_create(descs, len(problems), ctypes.byref(h)), "rts_plan_create")
         self.handle = h
@@ -212,23 +233,25 @@ class Plan:
                 torch.as_tensor(np.ascontiguousarray(p.rho)).to("cuda", dt).contiguous(),
                 torch.as_tensor(np.ascontiguousarray(p.S)).to("cuda", dt).contiguous())
 
-    def new_outputs(self, p, want_j=True, want_itop=True):
+    def new_outputs(self, p, want_j=True, want_itop=True, want_flux=False):
+        """(Q, J, I_top), or (Q, J, I_top, F, QF) with want_flux (F [3,nz,ny,nx], QF
+        [nz,ny,nx], float64)."""
         import torch
         Q = torch.empty((p.nz, p.ny, p.nx), dtype=torch.float64, device="cuda")
         J = torch.empty((p.nbands, p.nz, p.ny, p.nx), dtype=self.dtype, device="cuda") if want_j else None
         It = (torch.empty((p.nbands, p.n_up, p.ny, p.nx), dtype=self.dtype, device="cuda")
               if want_itop else None)
-        return Q, J, It
+        if not want_flux:
+            return Q, J, It
+        F = torch.empty((3, p.nz, p.ny, p.nx), dtype=torch.float64, device="cuda")
+        QF = torch.empty((p.nz, p.ny, p.nx), dtype=torch.float64, device="cuda")
+        return Q, J, It, F, QF
 
     def solve_into(self, ins, outs, stream=None, batched=False):
-        """Enqueue a forward solve.  ins: [(kappa, rho, S)] per box; outs: [(Q, J, I_top)]."""
+        """Enqueue a forward solve.  ins: [(kappa, rho, S)] per box; outs: [(Q, J, I_top)] or
+        [(Q, J, I_top, F, QF)] per box."""
         n = len(ins)
-        ci = (Inputs * n)()
-        co = (Outputs * n)()
-        for i, ((k, r, s), (q, j, it)) in enumerate(zip(ins, outs)):
-            ci[i] = Inputs(k.data_ptr(), r.data_ptr(), s.data_ptr())
-            co[i] = Outputs(q.data_ptr(), j.data_ptr() if j is not None else None,
-                            it.data_ptr() if it is not None else None)
+        ci, co = _marshal(ins, outs)
         ws, nbytes = self.workspace()
         st = _stream_ptr(stream)
         if batched:
@@ -241,12 +264,7 @@ class Plan:
         """Time every candidate schedule on these inputs (rts_plan_autotune) and keep
         the fastest; returns it."""
         n = len(ins)
-        ci = (Inputs * n)()
-        co = (Outputs * n)()
-        for i, ((k, r, s), (q, j, it)) in enumerate(zip(ins, outs)):
-            ci[i] = Inputs(k.data_ptr(), r.data_ptr(), s.data_ptr())
-            co[i] = Outputs(q.data_ptr(), j.data_ptr() if j is not None else None,
-                            it.data_ptr() if it is not None else None)
+        ci, co = _marshal(ins, outs)
         ws, nbytes = self.workspace(RTS_OP_AUTOTUNE)
         sch = Schedule()
         _check(lib().rts_plan_autotune(self.handle, n, ci, co, ctypes.c_void_p(ws), nbytes,
@@ -276,12 +294,13 @@ class Plan:
                "rts_check_status")
 
 
-def solve(p, prec: int = RTS_FP64, plan: Plan | None = None):
-    """Forward solve of one problem on the current GPU; returns numpy (Q, J, I_top)."""
+def solve(p, prec: int = RTS_FP64, plan: Plan | None = None, flux: bool = False):
+    """Forward solve of one problem on the current GPU; returns numpy (Q, J, I_top), or
+    (Q, J, I_top, F, QF) with flux."""
     import torch
-    plan = plan or Plan(p, prec)
+    plan = plan or Plan(p, prec, flux=flux)
     ins = plan.device_inputs(p)
-    outs = plan.new_outputs(p)
+    outs = plan.new_outputs(p, want_flux=flux)
     plan.solve_into([ins], [outs])
     plan.check_status()
     torch.cuda.synchronize()

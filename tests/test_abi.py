@@ -194,3 +194,43 @@ def test_size_limits_rejected():
     with pytest.raises(rts.RTSError) as e:
         rts.Plan(q)
     assert e.value.status == rts.RTS_E_ARG
+
+
+def test_flux_plan_workspace_and_argument_errors():
+    # a flux plan keeps three more partial arrays per sweep task (six tasks for
+    # grey S4 on a cube); F needs such a plan and QF needs F, checked before
+    # any HIP call
+    p = inputs.workload("grey32", size=16)
+    N = p.ncells
+    for prec, esz in ((rts.RTS_FP32, 4), (rts.RTS_FP64, 8)):
+        n0 = rts.Plan(p, prec).workspace_bytes()
+        n1 = rts.Plan(p, prec, flux=True).workspace_bytes()
+        assert n1 - n0 >= 6 * 3 * N * esz
+        assert n1 - n0 <= 6 * 3 * (N * esz + 256)
+    L = rts.lib()
+    ci = rts.Inputs(256, 256, 256)
+    ws, big = ctypes.c_void_p(256), 1 << 40
+    plain = rts.Plan(p, rts.RTS_FP32)
+    co = rts.Outputs(256, None, None, 256, None)
+    assert L.rts_solve(plain.handle, ctypes.byref(ci), ctypes.byref(co), ws, big,
+                       None) == rts.RTS_E_ARG
+    fl = rts.Plan(p, rts.RTS_FP32, flux=True)
+    co = rts.Outputs(256, None, None, None, 256)
+    assert L.rts_solve(fl.handle, ctypes.byref(ci), ctypes.byref(co), ws, big,
+                       None) == rts.RTS_E_ARG
+    # the flux flag is 0 or 1
+    p2 = _desc_problem()
+    mu = np.ascontiguousarray(p2.mu, dtype=np.float64)
+    w = np.ascontiguousarray(p2.w, dtype=np.float64)
+    descs = (rts.Desc * 1)()
+    dd = descs[0]
+    dd.g = rts.Grid(p2.nx, p2.ny, p2.nz, p2.dx, p2.dy, p2.dz)
+    dd.nbands, dd.nrays = p2.nbands, p2.nrays
+    dd.mu = mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    dd.w = w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    dd.n_iter, dd.prec = 3, rts.RTS_FP64
+    h = ctypes.c_void_p()
+    for flag, want in ((2, rts.RTS_E_ARG), (1, rts.RTS_OK)):
+        dd.flux = flag
+        assert L.rts_plan_create(descs, 1, ctypes.byref(h)) == want
+    L.rts_plan_destroy(h)

@@ -64,6 +64,31 @@ def test_full_size_grey288_fp64():
     assert np.abs(Ig - Io).max() <= 1e-13 * np.abs(Io).max()
 
 
+def test_full_size_bands288_flux_fp32():
+    # the flux vector and its divergence at 288^3 x 5 bands (bars as in
+    # test_gpu_flux: F within 2e-6 of 4 pi max|J|, QF within sum_d 4/delta_d of that)
+    import torch
+    p = inputs.workload("bands288").astype(np.float32)
+    print("case full size bands288 flux fp32", flush=True)
+    pl = rts.Plan(p, rts.RTS_FP32, flux=True)
+    ins = pl.device_inputs(p)
+    outs = pl.new_outputs(p, want_flux=True)
+    pl.solve_into([ins], [outs])
+    pl.check_status()
+    torch.cuda.synchronize()
+    got = [o.double().cpu().numpy() for o in outs]
+    ref = oracle.flux(p.astype(np.float64), threads=THREADS)
+    scale = 4 * math.pi * np.abs(ref[1]).max()
+    ef = np.abs(got[3] - ref[3]).max()
+    eqf = np.abs(got[4] - ref[4]).max()
+    print(f"bands288 flux fp32: F {ef / scale:.2e} of 4 pi max J ({ef / np.abs(ref[3]).max():.2e} "
+          f"of max|F|), QF {eqf / np.abs(ref[4]).max():.2e} of max|QF|", flush=True)
+    assert ef <= 2e-6 * scale
+    assert eqf <= (4 / p.dx + 4 / p.dy + 4 / p.dz) * 2e-6 * scale
+    eq, ej, ei = _errs(got[:3], ref[:3])
+    assert eq <= 1e-5 and ej <= 2e-6 and ei <= 2e-6
+
+
 def _adjoint128_seeds(p, prec):
     s_target, g = inputs.adjoint_seeds(p, 4000)
     t = p.astype(p.S.dtype)
