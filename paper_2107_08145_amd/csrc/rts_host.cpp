@@ -36,11 +36,7 @@ template <class Real, int H, bool UNI>
 hipError_t launch_sweep_h(const SweepArgs&, int, int, hipStream_t);
 template <class Real>
 hipError_t launch_reduce(const char*, const Task*, const BoxGeo&, const BoxPtrs&, hipStream_t);
-template <class Real>
-hipError_t launch_reduce_flux(const char*, const Task*, const BoxGeo&, const void*, double*,
-                              hipStream_t);
-hipError_t launch_flux_div(const double*, double*, int, int, int, double, double, double,
-                           hipStream_t);
+
 template <class Real>
 size_t reverse_lds_bytes(int);
 template <class Real>
@@ -258,7 +254,9 @@ void build_layout(Plan& P) {
       }
       ++T.nrays;
       RayGeo g = ray_geo(d.g, &B.mu[3 * r]);
-      for (int m = 0; m < 3; ++m) y.wm[m] = B.w[r] * B.mu[3 * r + m];
+      y.wm[0] = B.w[r] * B.mu[3 * r + col_axis];
+      y.wm[1] = B.w[r] * B.mu[3 * r + row_axis];
+      y.wm[2] = B.w[r] * B.mu[3 * r + g0.axis];
       y.f1 = g.ds * std::fabs(g.mu[col_axis]) / dd[col_axis];
       y.f2 = g.ds * std::fabs(g.mu[row_axis]) / dd[row_axis];
       y.hds = 0.5 * g.ds;
@@ -269,6 +267,9 @@ void build_layout(Plan& P) {
       uni = T.ray[k].f1 == T.ray[0].f1 && T.ray[k].f2 == T.ray[0].f2 &&
             T.ray[k].hds == T.ray[0].hds && T.ray[k].w == T.ray[0].w;
     T.uni = uni ? 1 : 0;
+    T.frame[0] = col_axis;
+    T.frame[1] = row_axis;
+    T.frame[2] = g0.axis;
     T.it_ray = (int64_t)nx * ny;
     T.it_off = (int64_t)T.band * B.n_up * nx * ny;
     T.rows_per_strip = std::min(H, T.n_rows);
@@ -341,9 +342,9 @@ void build_layout(Plan& P) {
     off = align_up(off + (size_t)B.N * esz);
     T.n_cells = B.N;
     T.flux_off = -1;
-    if (B.d.flux) {  // x, y, z flux partials of the task
+    if (B.d.flux) {  // flux partials along cols, rows and, unless uni, the plane axis
       T.flux_off = (int64_t)(off / esz);
-      off = align_up(off + 3 * (size_t)B.N * esz);
+      off = align_up(off + (T.uni ? 2 : 3) * (size_t)B.N * esz);
     }
   }
   P.total = off;
@@ -515,6 +516,7 @@ BoxGeo box_geo(const Plan& P, size_t b) {
   for (int k = 0; k < B.d.nbands; ++k) G.qweight[k] = B.qw[k];
   for (int r = 0; r < B.d.nrays; ++r)
     for (int m = 0; m < 3; ++m) G.msum[m] += B.w[r] * B.mu[3 * r + m];
+  G.dx = B.d.g.dx; G.dy = B.d.g.dy; G.dz = B.d.g.dz;
   return G;
 }
 
@@ -545,8 +547,10 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
   a.total_strips = P.total_strips;
   a.timeout_ticks = P.timeout_ticks;
   for (size_t b = 0; b < P.boxes.size(); ++b)
-    a.box[b] = out ? BoxPtrs{in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top}
-                   : BoxPtrs{in[b].kappa, in[b].rho, in[b].S, nullptr, nullptr, nullptr};
+    a.box[b] = out ? BoxPtrs{in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top,
+                             out[b].F, out[b].QF}
+                   : BoxPtrs{in[b].kappa, in[b].rho, in[b].S, nullptr, nullptr, nullptr, nullptr,
+                             nullptr};
   a.store_d = out ? 0 : 1;
   a.flux = 0;
   if (out)
@@ -564,16 +568,9 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
   if (!out) return RTS_OK;
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     const BoxGeo G = box_geo(P, b);
+    // J, Q and, with F requested, the flux vector and its divergence
     RTS_HIP(launch_reduce<Real>(ws, reinterpret_cast<const Task*>(ws + P.off_tasks), G,
                                 a.box[b], st));
-    if (out[b].F) {
-      RTS_HIP(launch_reduce_flux<Real>(ws, reinterpret_cast<const Task*>(ws + P.off_tasks), G,
-                                       in[b].S, out[b].F, st));
-      if (out[b].QF) {
-        const rts_grid& g = P.boxes[b].d.g;
-        RTS_HIP(launch_flux_div(out[b].F, out[b].QF, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, st));
-      }
-    }
   }
   return RTS_OK;
 }

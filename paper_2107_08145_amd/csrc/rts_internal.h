@@ -19,7 +19,7 @@ struct TaskRay {
   double w;        // quadrature weight
   int32_t itop;    // index among rays with mu_z > 0, or -1
   int32_t ray;     // input ray index, or -1 for an unused slot
-  double wm[3];    // w mu_x, w mu_y, w mu_z: weights of the flux partials
+  double wm[3];    // w mu along (cols, rows, plane axis): weights of the flux partials
 };
 
 // One sweep task: up to four rays of one band of one box that share the
@@ -42,7 +42,11 @@ struct Task {
   int64_t chi_off;         // element offset of this band's chi view in the workspace
   int64_t s_off;           // element offset of S: into the box's S (natural) or workspace
   int64_t part_off;        // element offset of the partial sum array in the workspace
-  int64_t flux_off;        // element offset of the three flux partials [3][n_cells], or -1
+  int64_t flux_off;        // element offset of the flux partials along (cols, rows[, plane
+                           // axis]) [2 or 3][n_cells], or -1; with uni the plane-axis
+                           // component is mu_axis times the partial sum, not stored
+  int32_t frame[3];        // grid axis (0 x, 1 y, 2 z) of cols, rows and the plane axis
+  int32_t pad2;
   int64_t n_cells;         // cells of the box
   int64_t xbuf_off;        // 64-bit-word offset of the neighbour exchange buffer
   int64_t it_off;          // element offset of this band's I_top block in the box I_top
@@ -91,6 +95,8 @@ struct BoxPtrs {
   double* Q;
   void* J;
   void* I_top;
+  double* F;   // [3][N] flux vector, or null
+  double* QF;  // [N] its divergence heating, or null
 };
 
 // Per-box geometry for the prep and reduce kernels.
@@ -105,6 +111,7 @@ struct BoxGeo {
   int64_t sT_off;          // S^T   [nbands][nx][nz][ny]
   double qweight[16];
   double msum[3];          // sum_r w_r mu_r (the flux of an isotropic unit intensity / 4 pi)
+  double dx, dy, dz;       // grid spacing (flux divergence)
 };
 
 // Workspace header (first 256 bytes).

@@ -377,17 +377,27 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
       *lane_at(urow(P, qo + (r0 + i) * rs), ub) = sum;
     }
     if (FLUX && T.flux_off >= 0) {  // (a box without flux partials writes none)
-      // flux partials sum_r (w mu_k)_r D_r, k = x, y, z, in the same layout
+      // flux partials sum_r (w mu_k)_r D_r along k = cols, rows (and the plane
+      // axis unless uni), in the layout of the partial sum.  With uni the
+      // slots share |w mu_k| and the signs follow the slot order (cols: + for
+      // slots 0 and 1; rows: + for even slots).
       Real* Fp = gptr(reinterpret_cast<Real*>(A.ws) + T.flux_off);
 #pragma unroll
       for (int i = 0; i < H; ++i) {
         if (!FULL && i >= hr) break;
+        const int o = qo + (r0 + i) * rs;
+        if (UNI || T.uni) {  // (a uni task in a launch for general tasks too)
+          const Real wc = (Real)T.ray[0].wm[0], wr = (Real)T.ray[0].wm[1];
+          *lane_at(urow(Fp, o), ub) = wc * ((Dn[i][0] + Dn[i][1]) - (Dn[i][2] + Dn[i][3]));
+          *lane_at(urow(Fp + T.n_cells, o), ub) = wr * ((Dn[i][0] + Dn[i][2]) - (Dn[i][1] + Dn[i][3]));
+        } else {
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          Real f = Real(0);
+          for (int m = 0; m < 3; ++m) {
+            Real f = Real(0);
 #pragma unroll
-          for (int r = 0; r < R; ++r) f = fmad((Real)T.ray[r].wm[m], Dn[i][r], f);
-          *lane_at(urow(Fp + m * T.n_cells, qo + (r0 + i) * rs), ub) = f;
+            for (int r = 0; r < R; ++r) f = fmad((Real)T.ray[r].wm[m], Dn[i][r], f);
+            *lane_at(urow(Fp + m * T.n_cells, o), ub) = f;
+          }
         }
       }
     }
@@ -699,30 +709,43 @@ __global__ __launch_bounds__(256) void rts_reduce_flux(const char* __restrict__ 
   const int nx = G.nx, ny = G.ny, nz = G.nz;
   const int64_t N = (int64_t)nx * ny * nz;
   double f[3][4] = {};
+  // one task array (natural or [x][z][y] layout) at this thread's four cells
+  auto load4 = [&](const Real* part, bool transposed, double (&v)[4]) {
+    if (!transposed) {
+      for (int i = 0; i < 4; ++i) {
+        const int y = y0 + ty + 8 * i, x = x0 + tx;
+        v[i] = x < nx && y < ny ? (double)part[((int64_t)z * ny + y) * nx + x] : 0.0;
+      }
+    } else {
+      __syncthreads();
+      for (int i = 0; i < 4; ++i) {
+        const int x = x0 + ty + 8 * i, y = y0 + tx;
+        if (x < nx && y < ny) tile[ty + 8 * i][tx] = part[((int64_t)x * nz + z) * ny + y];
+      }
+      __syncthreads();
+      for (int i = 0; i < 4; ++i) {
+        const int y = y0 + ty + 8 * i, x = x0 + tx;
+        v[i] = x < nx && y < ny ? (double)tile[tx][ty + 8 * i] : 0.0;
+      }
+    }
+  };
   for (int b = 0; b < G.nbands; ++b) {
     double acc[3][4] = {};
     for (int k = 0; k < G.tasks_per_band; ++k) {
       const Task& T = tasks[G.task0 + b * G.tasks_per_band + k];
-      for (int m = 0; m < 3; ++m) {
-        const Real* part = reinterpret_cast<const Real*>(ws) + T.flux_off + m * N;
-        if (!T.transposed) {
-          for (int i = 0; i < 4; ++i) {
-            const int y = y0 + ty + 8 * i, x = x0 + tx;
-            if (x < nx && y < ny) acc[m][i] += (double)part[((int64_t)z * ny + y) * nx + x];
-          }
-        } else {
-          __syncthreads();
-          for (int i = 0; i < 4; ++i) {
-            const int x = x0 + ty + 8 * i, y = y0 + tx;
-            if (x < nx && y < ny) tile[ty + 8 * i][tx] = part[((int64_t)x * nz + z) * ny + y];
-          }
-          __syncthreads();
-          for (int i = 0; i < 4; ++i) {
-            const int y = y0 + ty + 8 * i, x = x0 + tx;
-            if (x < nx && y < ny) acc[m][i] += (double)tile[tx][ty + 8 * i];
-          }
-        }
+      const Real* fp = reinterpret_cast<const Real*>(ws) + T.flux_off;
+      double v[3][4];
+      load4(fp, T.transposed, v[0]);
+      load4(fp + N, T.transposed, v[1]);
+      if (T.uni) {  // plane-axis component: mu_axis times the partial sum
+        load4(reinterpret_cast<const Real*>(ws) + T.part_off, T.transposed, v[2]);
+        const double mua = T.ray[0].wm[2] / T.ray[0].w;
+        for (int i = 0; i < 4; ++i) v[2][i] *= mua;
+      } else {
+        load4(fp + 2 * N, T.transposed, v[2]);
       }
+      for (int m = 0; m < 3; ++m)
+        for (int i = 0; i < 4; ++i) acc[T.frame[m]][i] += v[m][i];
     }
     const double qf = 4.0 * 3.14159265358979323846 * G.qweight[b];
     for (int i = 0; i < 4; ++i) {
@@ -835,6 +858,9 @@ __global__ __launch_bounds__(256) void rts_reduce(const char* __restrict__ ws,
 // The same reduction with 16-byte accesses, for FP32 and nx a multiple of 4:
 // a thread owns four consecutive x of one row; partials of x-sweeps ([x][z][y])
 // go through an LDS tile.  Sums in the same order as rts_reduce.
+// FLUX: also the flux vector F from the tasks' flux partials (rts_reduce_flux's
+// sums, in the same order), reading S once for both.
+template <bool FLUX>
 __global__ __launch_bounds__(256) void rts_reduce_v4(const char* __restrict__ ws,
                                                     const Task* __restrict__ tasks, BoxGeo G,
                                                     BoxPtrs P) {
@@ -853,32 +879,58 @@ __global__ __launch_bounds__(256) void rts_reduce_v4(const char* __restrict__ ws
   float* J = P.J ? gptr(reinterpret_cast<float*>(P.J)) : nullptr;
   const float4 r4 = in ? *reinterpret_cast<const float4*>(rho + p) : make_float4(0, 0, 0, 0);
   double q[4] = {0, 0, 0, 0};
+  double f[3][4] = {};
+  // one partial array of a task (natural or [x][z][y] layout) into acc
+  auto add_part = [&](const float* part, bool transposed, double (&acc)[4]) {
+    if (!transposed) {
+      if (in) {
+        const float4 v = *reinterpret_cast<const float4*>(part + p);
+        acc[0] += (double)v.x; acc[1] += (double)v.y; acc[2] += (double)v.z; acc[3] += (double)v.w;
+      }
+    } else {
+      __syncthreads();
+      // tile[xr][yc] = part[x0 + xr][z][y0 + yc], coalesced along y
+      const int yc = t & 31;
+      for (int xr = t >> 5; xr < 32; xr += 8) {
+        const int xx = x0 + xr, yy = y0 + yc;
+        if (xx < nx && yy < ny) tile[xr][yc] = part[((int64_t)xx * nz + z) * ny + yy];
+      }
+      __syncthreads();
+      if (in) {
+        acc[0] += (double)tile[qx][ry];
+        acc[1] += (double)tile[qx + 1][ry];
+        acc[2] += (double)tile[qx + 2][ry];
+        acc[3] += (double)tile[qx + 3][ry];
+      }
+    }
+  };
   for (int b = 0; b < G.nbands; ++b) {
     double acc[4] = {0, 0, 0, 0};
+    double fa[3][4] = {};
     for (int k = 0; k < G.tasks_per_band; ++k) {
       const Task& T = tasks[G.task0 + b * G.tasks_per_band + k];
       const float* part = gptr(reinterpret_cast<const float*>(ws) + T.part_off);
-      if (!T.transposed) {
-        if (in) {
-          const float4 v = *reinterpret_cast<const float4*>(part + p);
-          acc[0] += (double)v.x; acc[1] += (double)v.y; acc[2] += (double)v.z; acc[3] += (double)v.w;
-        }
-      } else {
-        __syncthreads();
-        // tile[xr][yc] = part[x0 + xr][z][y0 + yc], coalesced along y
-        const int yc = t & 31;
-        for (int xr = t >> 5; xr < 32; xr += 8) {
-          const int xx = x0 + xr, yy = y0 + yc;
-          if (xx < nx && yy < ny) tile[xr][yc] = part[((int64_t)xx * nz + z) * ny + yy];
-        }
-        __syncthreads();
-        if (in) {
-          acc[0] += (double)tile[qx][ry];
-          acc[1] += (double)tile[qx + 1][ry];
-          acc[2] += (double)tile[qx + 2][ry];
-          acc[3] += (double)tile[qx + 3][ry];
-        }
+      if (!FLUX) {
+        add_part(part, T.transposed, acc);
+        continue;
       }
+      // flux components along (cols, rows, plane axis) of the task, mapped to x, y, z;
+      // with uni the plane-axis one is mu_axis times the partial sum
+      double v[3][4] = {};
+      add_part(part, T.transposed, v[2]);
+      for (int i = 0; i < 4; ++i) acc[i] += v[2][i];
+      const float* fp = gptr(reinterpret_cast<const float*>(ws) + T.flux_off);
+      add_part(fp, T.transposed, v[0]);
+      add_part(fp + N, T.transposed, v[1]);
+      if (T.uni) {
+        const double mua = T.ray[0].wm[2] / T.ray[0].w;
+        for (int i = 0; i < 4; ++i) v[2][i] *= mua;
+      } else {
+        for (int i = 0; i < 4; ++i) v[2][i] = 0.0;
+        add_part(fp + 2 * N, T.transposed, v[2]);
+      }
+      for (int m = 0; m < 3; ++m)
+        for (int i = 0; i < 4; ++i) fa[T.frame[m]][i] += v[m][i];
     }
     if (in) {
       const double qf = 4.0 * 3.14159265358979323846 * G.qweight[b];
@@ -892,12 +944,24 @@ __global__ __launch_bounds__(256) void rts_reduce_v4(const char* __restrict__ ws
         *reinterpret_cast<float4*>(J + b * N + p) =
             make_float4((float)((double)s4.x + acc[0]), (float)((double)s4.y + acc[1]),
                         (float)((double)s4.z + acc[2]), (float)((double)s4.w + acc[3]));
+      if (FLUX) {
+        const double sv[4] = {(double)s4.x, (double)s4.y, (double)s4.z, (double)s4.w};
+        for (int m = 0; m < 3; ++m)
+          for (int i = 0; i < 4; ++i) f[m][i] += qf * (fa[m][i] + sv[i] * G.msum[m]);
+      }
     }
   }
   if (in) {
     double* Q = gptr(P.Q);
     *reinterpret_cast<double2*>(Q + p) = make_double2(q[0], q[1]);
     *reinterpret_cast<double2*>(Q + p + 2) = make_double2(q[2], q[3]);
+    if (FLUX) {
+      double* F = gptr(P.F);
+      for (int m = 0; m < 3; ++m) {
+        *reinterpret_cast<double2*>(F + m * N + p) = make_double2(f[m][0], f[m][1]);
+        *reinterpret_cast<double2*>(F + m * N + p + 2) = make_double2(f[m][2], f[m][3]);
+      }
+    }
   }
 }
 
@@ -1609,11 +1673,21 @@ hipError_t launch_reduce(const char* ws, const Task* tasks, const BoxGeo& g, con
                          hipStream_t st) {
   dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, g.nz);
   const uintptr_t al = (uintptr_t)p.kappa | (uintptr_t)p.rho | (uintptr_t)p.S |
-                       (uintptr_t)p.J | (uintptr_t)p.Q;
-  if (sizeof(Real) == 4 && g.nx % 4 == 0 && al % 16 == 0)
-    hipLaunchKernelGGL(rts_reduce_v4, grid, dim3(256), 0, st, ws, tasks, g, p);
-  else
+                       (uintptr_t)p.J | (uintptr_t)p.Q | (uintptr_t)p.F;
+  if (sizeof(Real) == 4 && g.nx % 4 == 0 && al % 16 == 0) {
+    // 16-byte accesses; with F, the flux sums in the same pass
+    if (p.F) hipLaunchKernelGGL(rts_reduce_v4<true>, grid, dim3(256), 0, st, ws, tasks, g, p);
+    else hipLaunchKernelGGL(rts_reduce_v4<false>, grid, dim3(256), 0, st, ws, tasks, g, p);
+  } else {
     hipLaunchKernelGGL(rts_reduce<Real>, grid, dim3(256), 0, st, ws, tasks, g, p);
+    if (p.F)
+      hipLaunchKernelGGL(rts_reduce_flux<Real>, grid, dim3(256), 0, st, ws, tasks, g,
+                         reinterpret_cast<const Real*>(p.S), p.F);
+  }
+  if (p.F && p.QF)
+    hipLaunchKernelGGL(rts_flux_div, dim3((unsigned)(((int64_t)g.nx * g.ny * g.nz + 255) / 256)),
+                       dim3(256), 0, st, p.F, p.QF, g.nx, g.ny, g.nz, 1.0 / g.dx, 1.0 / g.dy,
+                       1.0 / g.dz);
   return hipGetLastError();
 }
 
@@ -1645,23 +1719,6 @@ hipError_t launch_reverse(const RevArgs& a, int grid, int cols, hipStream_t st) 
   if (cols <= 256) rts_reverse<Real, 512, 2><<<dim3(grid), b, lds, st>>>(a);
   else if (cols <= 512) rts_reverse<Real, 512, 4><<<dim3(grid), b, lds, st>>>(a);
   else rts_reverse<Real, 1024, 4><<<dim3(grid), b, lds, st>>>(a);
-  return hipGetLastError();
-}
-
-template <class Real>
-hipError_t launch_reduce_flux(const char* ws, const Task* tasks, const BoxGeo& g, const void* S,
-                              double* F, hipStream_t st) {
-  dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, g.nz);
-  hipLaunchKernelGGL(rts_reduce_flux<Real>, grid, dim3(256), 0, st, ws, tasks, g,
-                     reinterpret_cast<const Real*>(S), F);
-  return hipGetLastError();
-}
-
-hipError_t launch_flux_div(const double* F, double* QF, int nx, int ny, int nz, double dx,
-                           double dy, double dz, hipStream_t st) {
-  const int64_t N = (int64_t)nx * ny * nz;
-  hipLaunchKernelGGL(rts_flux_div, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, F, QF,
-                     nx, ny, nz, 1.0 / dx, 1.0 / dy, 1.0 / dz);
   return hipGetLastError();
 }
 
@@ -1702,10 +1759,7 @@ template hipError_t launch_reduce<float>(const char*, const Task*, const BoxGeo&
                                          hipStream_t);
 template hipError_t launch_reduce<double>(const char*, const Task*, const BoxGeo&, const BoxPtrs&,
                                           hipStream_t);
-template hipError_t launch_reduce_flux<float>(const char*, const Task*, const BoxGeo&,
-                                              const void*, double*, hipStream_t);
-template hipError_t launch_reduce_flux<double>(const char*, const Task*, const BoxGeo&,
-                                               const void*, double*, hipStream_t);
+
 #define RTS_ADJ_INST(Real)                                                                      \
   template size_t reverse_lds_bytes<Real>(int);                                                 \
   template const void* reverse_fn<Real>(int);                                                   \

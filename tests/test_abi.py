@@ -197,16 +197,22 @@ def test_size_limits_rejected():
 
 
 def test_flux_plan_workspace_and_argument_errors():
-    # a flux plan keeps three more partial arrays per sweep task (six tasks for
-    # grey S4 on a cube); F needs such a plan and QF needs F, checked before
-    # any HIP call
+    # a flux plan keeps two more partial arrays per sweep task whose four rays
+    # share |mu| (S4: six such tasks for grey on a cube; the plane-axis
+    # component follows from the partial sum), three per other task; F needs
+    # such a plan and QF needs F, checked before any HIP call
     p = inputs.workload("grey32", size=16)
     N = p.ncells
     for prec, esz in ((rts.RTS_FP32, 4), (rts.RTS_FP64, 8)):
         n0 = rts.Plan(p, prec).workspace_bytes()
         n1 = rts.Plan(p, prec, flux=True).workspace_bytes()
-        assert n1 - n0 >= 6 * 3 * N * esz
-        assert n1 - n0 <= 6 * 3 * (N * esz + 256)
+        assert 6 * 2 * N * esz <= n1 - n0 <= 6 * 2 * (N * esz + 256)
+    q = inputs.workload("grey32", size=16)
+    q.mu = np.array([[0.3, 0.2, np.sqrt(1 - 0.13)], [0.1, -0.4, -np.sqrt(1 - 0.17)]])
+    q.w = np.array([0.5, 0.5])
+    n0 = rts.Plan(q, rts.RTS_FP32).workspace_bytes()
+    n1 = rts.Plan(q, rts.RTS_FP32, flux=True).workspace_bytes()
+    assert 2 * 3 * N * 4 <= n1 - n0 <= 2 * 3 * (N * 4 + 256)   # two one-ray tasks
     L = rts.lib()
     ci = rts.Inputs(256, 256, 256)
     ws, big = ctypes.c_void_p(256), 1 << 40

@@ -123,3 +123,20 @@ def test_flux_on_one_box_of_two():
     plain = rts.solve(ps[1], rts.RTS_FP32)
     for a, b in zip(outs[1], plain):
         assert np.array_equal(a.double().cpu().numpy(), b)
+
+
+@pytest.mark.parametrize("prec", [rts.RTS_FP64, rts.RTS_FP32])
+def test_flux_mixed_uniform_and_general_tasks(prec):
+    # S4 without one ray: one three-ray task, the others four-ray tasks whose
+    # rays share |mu| (two flux partials, the plane-axis one from the partial
+    # sum) swept by the kernel for general tasks
+    p = inputs.random_problem(22, 19, 13, seed=61, bands=2)
+    p.mu = np.delete(p.mu, 5, axis=0)
+    p.w = np.delete(p.w, 5)
+    p.w = p.w / p.w.sum()
+    pp = p.astype(np.float32) if prec == rts.RTS_FP32 else p
+    print("case flux mixed tasks", prec, flush=True)
+    got = rts.solve(pp, prec, flux=True)
+    ref = oracle.flux(pp.astype(np.float64), threads=8)
+    ef, eq = _check(pp, got, ref, 1e-13 if prec == rts.RTS_FP64 else 2e-6)
+    print(f"flux mixed tasks {prec}: F {ef:.2e}, QF {eq:.2e}")
