@@ -505,3 +505,59 @@ def test_flux_divergence_approaches_heating(oracle_mod):
     d = [run(n) for n in (12, 24, 48)]
     assert d[0] / d[1] > 1.8 and d[1] / d[2] > 1.8, d
     assert d[2] < 0.05, d
+
+
+# ---------------------------------------------------------------------------
+# C8: the scheme against the continuous transfer equation.  Long
+# characteristics: from a point, integrate dI/ds = chi (S - I) exactly along
+# the ray back to the bottom (I = S) or top (I = 0) boundary, through smooth
+# analytic chi and S (fine trapezoid quadrature); J at fixed physical points
+# converges to it at first order as the grid is refined.
+
+
+def test_converges_to_long_characteristics(oracle_mod):
+    Lx = Ly = Lz = 4.0
+
+    def chi_f(x, y, z):
+        return 2.0 * np.exp(-z / 2.0) * (1 + 0.2 * np.sin(2 * np.pi * x / Lx))
+
+    def S_f(x, y, z):
+        return (1 + 0.3 * np.exp(-z)) * (1 + 0.2 * np.cos(2 * np.pi * y / Ly))
+
+    mu, w = inputs.s4_quadrature()
+    n0 = 12
+    rng = np.random.default_rng(0)
+    idx = [(rng.integers(0, n0), rng.integers(0, n0), rng.integers(1, n0)) for _ in range(40)]
+    pts = np.array([[i * Lx / n0, j * Ly / n0, k * Lz / n0] for i, j, k in idx])
+
+    Jlc = np.zeros(len(pts))
+    M = 4000
+    for r in range(24):
+        m = mu[r]
+        z0 = pts[:, 2]
+        sb = z0 / m[2] if m[2] > 0 else (Lz - z0) / (-m[2])   # path length to the boundary
+        s = sb[:, None] * np.linspace(0.0, 1.0, M + 1)[None, :]
+        X, Y, Z = (pts[:, d:d + 1] - s * m[d] for d in range(3))
+        c, Sv = chi_f(X, Y, Z), S_f(X, Y, Z)
+        ds = (sb / M)[:, None]
+        tau = np.concatenate([np.zeros((len(pts), 1)),
+                              np.cumsum(0.5 * (c[:, 1:] + c[:, :-1]) * ds, axis=1)], axis=1)
+        g = Sv * c * np.exp(-tau)
+        I = np.sum(0.5 * (g[:, 1:] + g[:, :-1]) * ds, axis=1)
+        if m[2] > 0:
+            I += S_f(X[:, -1], Y[:, -1], Z[:, -1]) * np.exp(-tau[:, -1])
+        Jlc += w[r] * I
+
+    errs = []
+    for n in (12, 24, 48):
+        d = Lx / n
+        x = np.arange(n) * d
+        z = np.arange(n + 1) * (Lz / n)
+        Zg, Yg, Xg = np.meshgrid(z, x, x, indexing="ij")
+        p = _problem(n, n, n + 1, chi_f(Xg, Yg, Zg), S_f(Xg, Yg, Zg), dx=d, dy=d, dz=Lz / n)
+        _, J, _ = oracle_mod.solve(p, threads=8)
+        f = n // n0
+        Jsc = np.array([J[0, k * f, j * f, i * f] for i, j, k in idx])
+        errs.append(np.abs(Jsc - Jlc).max() / np.abs(Jlc).max())
+    assert errs[0] / errs[1] > 1.7 and errs[1] / errs[2] > 1.7, errs
+    assert errs[2] < 3e-3, errs
