@@ -507,6 +507,8 @@ def main():
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(gbs / PEAK_HBM_GBS, 4)}
     roof["traffic"] = traffic
+    # measured HBM rate of the sweep: counter bytes per launch over the timed launch
+    roof["traffic_GBs"] = round(traffic / sw_s / 1e9, 1) if traffic else None
     roof["kernel"] = "rts_sweep"
     roof["kernel_ms"] = round(sweep_ms, 4)
     roof["alg_bytes_per_launch"] = alg_bytes
