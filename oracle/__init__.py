@@ -48,12 +48,14 @@ def _load():
         lib.oracle_solve_chi.argtypes = head + [p, p, p, p, p, i]
         lib.oracle_flux.argtypes = head + [p, p, p, p, p, p, p, p, i]
         lib.oracle_flux_divergence.argtypes = [i, i, i, d, d, d, p, p]
+        lib.oracle_solve_tol.argtypes = head + [d, p, p, p, p, p, p, p, p, p, i]
         lib.oracle_adjoint.argtypes = head + [p, p, p, p, p, p, p, i]
         lib.oracle_complex_step.argtypes = head + [p, p, i, i64, d, p, p, p, i]
         lib.oracle_ray.argtypes = [i, i, i, d, d, d, p, i, i, d, i, p, p, p]
         lib.oracle_weights.argtypes = [d, p, p, p, p]
         for f in ("oracle_solve", "oracle_solve_chi", "oracle_adjoint",
-                  "oracle_complex_step", "oracle_ray", "oracle_flux", "oracle_flux_divergence"):
+                  "oracle_complex_step", "oracle_ray", "oracle_flux", "oracle_flux_divergence",
+                  "oracle_solve_tol"):
             getattr(lib, f).restype = i
         lib.oracle_weights.restype = None
         _lib = lib
@@ -122,6 +124,32 @@ def flux(p, threads: int = 1):
         raise ValueError("oracle rejected the problem")
     del keep
     return Q, J, It, F, QF
+
+
+def solve_tol(p, tol: float, threads: int = 1, flux: bool = False):
+    """Forward solve with tolerance-driven boundary iteration: rays of a band
+    sharing an x or y dominant axis and its direction sweep together until the
+    largest change of their outflow planes is <= tol * their largest outflow
+    intensity (p.n_iter sweeps at most).
+
+    Returns (Q, J, I_top, sweeps [B, nrays]) or, with flux, (Q, J, I_top, F, QF,
+    sweeps)."""
+    lib = _load()
+    keep, head = _head(p)
+    B = p.nbands
+    Q = np.empty((p.nz, p.ny, p.nx))
+    J = np.empty((B, p.nz, p.ny, p.nx))
+    It = np.empty((B, p.n_up, p.ny, p.nx))
+    F = np.empty((3, p.nz, p.ny, p.nx)) if flux else None
+    QF = np.empty((p.nz, p.ny, p.nx)) if flux else None
+    sw = np.zeros((B, p.nrays), dtype=np.int32)
+    kap, rho, S = _f64(p.kappa), _f64(p.rho), _f64(p.S)
+    rc = lib.oracle_solve_tol(*head, float(tol), _ptr(kap), _ptr(rho), _ptr(S), _ptr(Q), _ptr(J),
+                              _ptr(It), _ptr(F), _ptr(QF), _ptr(sw), threads)
+    if rc:
+        raise ValueError("oracle rejected the problem")
+    del keep
+    return (Q, J, It, F, QF, sw) if flux else (Q, J, It, sw)
 
 
 def flux_divergence(F, dx: float, dy: float, dz: float):

@@ -37,6 +37,13 @@
 //     n_iter sweeps.  Rays with a z dominant axis need no ghost: one sweep.
 //   * Flux: J_b = sum_r w_r I_r after the last sweep; I_top = I in the top
 //     layer for mu_z > 0 rays; Q = sum_b qweight_b 4 pi chi_b (J_b - S_b).
+//   * Tolerance-driven boundary iteration (the paper iterates the boundary
+//     intensities until their error is within a prescribed tolerance): with
+//     tol > 0, the rays of one band that share an x or y dominant axis and its
+//     direction (a group swept together) repeat their sweeps until the largest
+//     change of their outflow-plane intensities between successive sweeps is
+//     at most tol times the largest outflow-plane intensity (the first sweep
+//     compares with the initial ghost), n_iter sweeps at most.
 //   * Radiative flux vector (the flux step computes mean intensity and fluxes
 //     from the same rays): F = sum_b qweight_b 4 pi sum_r w_r mu_r I_r, and the
 //     heating -div F by central differences (periodic in x and y; second-order
@@ -45,6 +52,7 @@
 //     last sweep first, ghost sensitivities carried into the previous sweep).
 //
 // Build: g++ -O2 -std=c++17 -fPIC -shared -ffp-contract=off -fno-fast-math -fopenmp
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -75,6 +83,7 @@ struct Desc {
   int bot, top;      // 0: thermal bottom / zero top, 1: fixed bottom / thermal top
   double ibot;
   int n_iter;
+  double tol = 0.0;  // > 0: sweeps of a group stop at this relative change (n_iter at most)
   int64_t cells() const { return (int64_t)n[0] * n[1] * n[2]; }
   int64_t at(int i, int j, int k) const { return ((int64_t)k * n[1] + j) * n[0] + i; }
 };
@@ -164,51 +173,64 @@ inline bool is_bc_layer(const Desc& D, const Ray& r, int k) {
   return r.up ? (k == 0) : (k == D.n[2] - 1);
 }
 
-// One ray of one band: n_sweeps sweeps (1 for z-dominant rays), I overwritten.
-// If `store` is given, the intensities after every sweep are appended to it.
+// The sweeps of one ray of one band, I overwritten: set-up (boundary layer
+// and initial ghost plane), then one sweep per call of sweep().
 template <class T>
-void solve_ray(const Desc& D, const Ray& r, const T* chi, const T* S, T* I,
-               std::vector<std::vector<T>>* store, int nt) {
-  const int na = D.n[r.axis], nA = D.n[r.ea], nB = D.n[r.eb];
-  const bool periodic = r.axis != 2;
-  const int sweeps = periodic ? D.n_iter : 1;
-  auto cell = [&](int q, int a, int b) {
+struct RaySweeper {
+  const Desc& D;
+  const Ray& r;
+  const T* chi;
+  const T* S;
+  T* I;
+  int nt;
+  int na, nA, nB, q_first, q_last;
+  bool periodic;
+  double b00, b10, b01, b11;
+  std::vector<T> ghost;
+
+  int64_t cell(int q, int a, int b) const {
     int c[3];
     c[r.axis] = q; c[r.ea] = a; c[r.eb] = b;
     return D.at(c[0], c[1], c[2]);
-  };
-  auto kz = [&](int q, int a, int b) {
+  }
+  int kz(int q, int a, int b) const {
     int c[3];
     c[r.axis] = q; c[r.ea] = a; c[r.eb] = b;
     return c[2];
-  };
-  const double b00 = (1 - r.fa) * (1 - r.fb), b10 = r.fa * (1 - r.fb);
-  const double b01 = (1 - r.fa) * r.fb, b11 = r.fa * r.fb;
-  const int q_first = r.sa > 0 ? 0 : na - 1;
-  const int q_last = r.sa > 0 ? na - 1 : 0;
-
-  // Boundary layer: set, not integrated.
-  for (int q = 0; q < na; ++q)
-    for (int a = 0; a < nA; ++a)
-      for (int b = 0; b < nB; ++b)
-        if (is_bc_layer(D, r, kz(q, a, b))) {
-          int64_t p = cell(q, a, b);
-          I[p] = bc_value(D, r, S[p]);
-        }
-
-  // Ghost plane for periodic sweeps: I = S of the wrapped upwind plane.
-  std::vector<T> ghost;
-  if (periodic) {
-    ghost.resize((size_t)nA * nB);
-    for (int a = 0; a < nA; ++a)
-      for (int b = 0; b < nB; ++b) {
-        int64_t p = cell(q_last, a, b);
-        ghost[(size_t)a * nB + b] =
-            is_bc_layer(D, r, kz(q_last, a, b)) ? bc_value(D, r, S[p]) : S[p];
-      }
   }
 
-  for (int sweep = 0; sweep < sweeps; ++sweep) {
+  RaySweeper(const Desc& D_, const Ray& r_, const T* chi_, const T* S_, T* I_, int nt_)
+      : D(D_), r(r_), chi(chi_), S(S_), I(I_), nt(nt_) {
+    na = D.n[r.axis]; nA = D.n[r.ea]; nB = D.n[r.eb];
+    periodic = r.axis != 2;
+    b00 = (1 - r.fa) * (1 - r.fb); b10 = r.fa * (1 - r.fb);
+    b01 = (1 - r.fa) * r.fb; b11 = r.fa * r.fb;
+    q_first = r.sa > 0 ? 0 : na - 1;
+    q_last = r.sa > 0 ? na - 1 : 0;
+    // Boundary layer: set, not integrated.
+    for (int q = 0; q < na; ++q)
+      for (int a = 0; a < nA; ++a)
+        for (int b = 0; b < nB; ++b)
+          if (is_bc_layer(D, r, kz(q, a, b))) {
+            int64_t p = cell(q, a, b);
+            I[p] = bc_value(D, r, S[p]);
+          }
+    // Ghost plane for periodic sweeps: I = S of the wrapped upwind plane.
+    if (periodic) {
+      ghost.resize((size_t)nA * nB);
+      for (int a = 0; a < nA; ++a)
+        for (int b = 0; b < nB; ++b) {
+          int64_t p = cell(q_last, a, b);
+          ghost[(size_t)a * nB + b] =
+              is_bc_layer(D, r, kz(q_last, a, b)) ? bc_value(D, r, S[p]) : S[p];
+        }
+    }
+  }
+
+  // One sweep; the outflow plane becomes the next sweep's ghost.  Returns the
+  // largest change of the ghost plane's intensities and its largest intensity
+  // (periodic rays; zeros otherwise).
+  std::pair<double, double> sweep() {
     // z-dominant rays start one plane in: their first plane is the boundary layer.
     for (int t = periodic ? 0 : 1; t < na; ++t) {
       const int q = q_first + r.sa * t;
@@ -239,17 +261,38 @@ void solve_ray(const Desc& D, const Ray& r, const T* chi, const T* S, T* I,
           I[p] = wt.e * iu + wt.w0 * S[p] + wt.w1 * su;
         }
     }
+    double diff = 0.0, scale = 0.0;
     if (periodic) {  // exchange: the outflow plane becomes the next sweep's ghost
       for (int a = 0; a < nA; ++a)
-        for (int b = 0; b < nB; ++b) ghost[(size_t)a * nB + b] = I[cell(q_last, a, b)];
+        for (int b = 0; b < nB; ++b) {
+          const T v = I[cell(q_last, a, b)];
+          T& g = ghost[(size_t)a * nB + b];
+          diff = std::max(diff, std::fabs(re(v) - re(g)));
+          scale = std::max(scale, std::fabs(re(v)));
+          g = v;
+        }
     }
+    return {diff, scale};
+  }
+};
+
+// One ray of one band: n_iter sweeps (1 for z-dominant rays), I overwritten.
+// If `store` is given, the intensities after every sweep are appended to it.
+template <class T>
+void solve_ray(const Desc& D, const Ray& r, const T* chi, const T* S, T* I,
+               std::vector<std::vector<T>>* store, int nt) {
+  RaySweeper<T> w(D, r, chi, S, I, nt);
+  const int sweeps = w.periodic ? D.n_iter : 1;
+  for (int sweep = 0; sweep < sweeps; ++sweep) {
+    w.sweep();
     if (store) store->emplace_back(I, I + D.cells());
   }
 }
 
 template <class T>
 int forward(const Desc& D, const T* chi, const T* S, T* Q, T* J, T* Itop, int nt,
-            std::vector<std::vector<T>>* store, std::vector<T>* Jall, T* F = nullptr) {
+            std::vector<std::vector<T>>* store, std::vector<T>* Jall, T* F = nullptr,
+            int* sweeps_used = nullptr) {
   const int64_t N = D.cells();
   std::vector<Ray> rays(D.nr);
   for (int r = 0; r < D.nr; ++r)
@@ -261,13 +304,45 @@ int forward(const Desc& D, const T* chi, const T* S, T* Q, T* J, T* Itop, int nt
   const int64_t plane = (int64_t)D.n[0] * D.n[1];
   int nup = 0;
   for (int r = 0; r < D.nr; ++r) nup += rays[r].up;
+  std::vector<std::vector<T>> Iall;
+  if (D.tol > 0) Iall.assign(D.nr, std::vector<T>(N));
   for (int b = 0; b < D.nb; ++b) {
     const T* chib = chi + b * N;
     const T* Sb = S + b * N;
     for (int64_t p = 0; p < N; ++p) Jb[p] = 0.0;
+    if (D.tol > 0) {
+      // every ray first; groups (x or y dominant axis, direction) in lock step
+      std::vector<char> done(D.nr, 0);
+      for (int r0 = 0; r0 < D.nr; ++r0) {
+        if (done[r0]) continue;
+        std::vector<int> grp;
+        for (int r = r0; r < D.nr; ++r)
+          if (!done[r] && rays[r].axis == rays[r0].axis && rays[r].sa == rays[r0].sa) grp.push_back(r);
+        std::vector<RaySweeper<T>> ws;
+        for (int r : grp) {
+          done[r] = 1;
+          ws.emplace_back(D, rays[r], chib, Sb, Iall[r].data(), nt);
+        }
+        const int max_sweeps = rays[r0].axis != 2 ? D.n_iter : 1;
+        int used = 0;
+        for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+          double diff = 0.0, scale = 0.0;
+          for (auto& w : ws) {
+            const auto ds = w.sweep();
+            diff = std::max(diff, ds.first);
+            scale = std::max(scale, ds.second);
+          }
+          used = sweep + 1;
+          if (rays[r0].axis != 2 && diff <= D.tol * scale) break;
+        }
+        if (sweeps_used)
+          for (int r : grp) sweeps_used[b * D.nr + r] = used;
+      }
+    }
     int ru = 0;
     for (int r = 0; r < D.nr; ++r) {
-      solve_ray(D, rays[r], chib, Sb, I.data(), store, nt);
+      if (D.tol > 0) std::copy(Iall[r].begin(), Iall[r].end(), I.begin());
+      else solve_ray(D, rays[r], chib, Sb, I.data(), store, nt);
       for (int64_t p = 0; p < N; ++p) Jb[p] += D.w[r] * I[p];
       if (F)
         for (int k = 0; k < 3; ++k) {
@@ -533,6 +608,29 @@ int oracle_flux(int nx, int ny, int nz, double dx, double dy, double dz, int nb,
                                  nullptr, nullptr, F);
   if (rc) return rc;
   if (QF) flux_divergence(D, F, QF);
+  return 0;
+}
+
+// Forward solve with tolerance-driven boundary iteration (tol > 0; n_iter is
+// the largest sweep count): Q, J, Itop as in oracle_solve, F and QF as in
+// oracle_flux when F is not null, and sweeps [nb][nr] the sweeps each ray
+// used.
+int oracle_solve_tol(int nx, int ny, int nz, double dx, double dy, double dz, int nb, int nr,
+                     const double* mu, const double* w, const double* qw, int bot, int top,
+                     double ibot, int n_iter, double tol, const double* kappa, const double* rho,
+                     const double* S, double* Q, double* J, double* Itop, double* F, double* QF,
+                     int* sweeps, int nthreads) {
+  Desc D = make_desc(nx, ny, nz, dx, dy, dz, nb, nr, mu, w, qw, bot, top, ibot, n_iter);
+  if (!valid(D) || !(tol > 0) || !std::isfinite(tol)) return -1;
+  D.tol = tol;
+  const int64_t N = D.cells();
+  std::vector<double> chi((size_t)nb * N);
+  for (int b = 0; b < nb; ++b)
+    for (int64_t p = 0; p < N; ++p) chi[b * N + p] = kappa[b * N + p] * rho[p];
+  const int rc = forward<double>(D, chi.data(), S, Q, J, Itop, nthreads > 0 ? nthreads : 1,
+                                 nullptr, nullptr, F, sweeps);
+  if (rc) return rc;
+  if (F && QF) flux_divergence(D, F, QF);
   return 0;
 }
 

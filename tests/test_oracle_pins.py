@@ -561,3 +561,74 @@ def test_converges_to_long_characteristics(oracle_mod):
         errs.append(np.abs(Jsc - Jlc).max() / np.abs(Jlc).max())
     assert errs[0] / errs[1] > 1.7 and errs[1] / errs[2] > 1.7, errs
     assert errs[2] < 3e-3, errs
+
+
+# ---------------------------------------------------------------------------
+# Tolerance-driven boundary iteration: the rays of a band that share an x or
+# y dominant axis and its direction sweep together until the largest change
+# of their outflow planes is <= tol * their largest outflow intensity.
+
+
+def _thin_problem(n_iter):
+    nx, ny, nz = 9, 8, 7
+    chi, S = _rand_atm(nx, ny, nz, 11, 0.02, 0.3)   # thin: the periodic iteration converges slowly
+    return _problem(nx, ny, nz, chi, S, n_iter=n_iter)
+
+
+def test_tolerance_limits(oracle_mod):
+    p = _thin_problem(6)
+    q1 = _thin_problem(1)
+    Q1, J1, I1 = oracle_mod.solve(q1)
+    Qh, Jh, Ih, sw = oracle_mod.solve_tol(p, 1e30)         # one sweep each
+    assert (sw == 1).all()
+    assert np.array_equal(Jh, J1) and np.array_equal(Qh, Q1) and np.array_equal(Ih, I1)
+    Q6, J6, I6 = oracle_mod.solve(p)
+    Qt, Jt, It, sw = oracle_mod.solve_tol(p, 1e-300)       # never within tolerance here
+    mu = p.mu
+    zdom = np.abs(mu[:, 2]) * 1.0 >= np.maximum(np.abs(mu[:, 0]), np.abs(mu[:, 1])) - 1e-12
+    assert (sw[0][zdom] == 1).all() and (sw[0][~zdom] == 6).all(), sw
+    assert np.array_equal(Jt, J6) and np.array_equal(Qt, Q6)
+
+
+def test_tolerance_stopping_rule(oracle_mod):
+    # each group stops at the first sweep whose outflow change is within tol;
+    # J is the weighted sum of the rays' intensities after their own counts
+    p = _thin_problem(8)
+    chi, S = p.kappa[0] * p.rho, p.S[0]
+    tol = 3e-4
+    _, J, _, sw = oracle_mod.solve_tol(p, tol)
+    assert 1 < sw.max() < 8, sw
+    Jx = np.zeros_like(J[0])
+    groups = {}
+    for r in range(p.nrays):
+        m = p.mu[r]
+        I = oracle_mod.ray_intensity(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, m, chi, S,
+                                     n_iter=int(sw[0, r]))
+        Jx += p.w[r] * I
+        ax = int(np.argmax(np.abs(m) / np.array([p.dx, p.dy, p.dz]) + np.array([0, 1e-12, 2e-12])))
+        if ax != 2:
+            groups.setdefault((ax, m[ax] > 0), []).append(r)
+    assert np.allclose(J[0], Jx, rtol=1e-14, atol=0)
+    for (ax, pos), rs in groups.items():
+        s = int(sw[0, rs[0]])
+        assert all(int(sw[0, r]) == s for r in rs)
+        out = (p.nx - 1 if pos else 0) if ax == 0 else (p.ny - 1 if pos else 0)
+
+        def outflow(r, n):
+            if n == 0:     # the initial ghost: I = S (the bottom boundary layer at I = S too)
+                I = S.copy()
+                if p.mu[r, 2] < 0:
+                    I[-1] = 0.0
+            else:
+                I = oracle_mod.ray_intensity(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.mu[r], chi,
+                                             S, n_iter=n)
+            return I[:, :, out] if ax == 0 else I[:, out, :]
+
+        def change(n):
+            d = max(np.abs(outflow(r, n) - outflow(r, n - 1)).max() for r in rs)
+            sc = max(np.abs(outflow(r, n)).max() for r in rs)
+            return d, sc
+        d, sc = change(s)
+        assert s == 8 or d <= tol * sc, (ax, pos, s, d, sc)
+        d, sc = change(s - 1) if s > 1 else (np.inf, 0.0)
+        assert d > tol * sc, (ax, pos, s, d, sc)
