@@ -406,6 +406,8 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="time rts_adjoint against rts_solve (default workload adjoint128)")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--tol", type=float, default=0.0,
+                    help="tolerance-driven boundary iteration (n_iter sweeps at most)")
     ap.add_argument("--flux", action="store_true",
                     help="time the solve with the flux vector F and -div F (flux plan)")
     ap.add_argument("--errors", action="store_true",
@@ -456,7 +458,7 @@ def main():
     print(f"# inputs generated in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
-    plan = rts.Plan(pd, prec)
+    plan = rts.Plan(pd, prec, tol=args.tol)
     ins = plan.device_inputs(pd)
     outs = plan.new_outputs(pd)
     if args.rows:
@@ -522,6 +524,7 @@ def main():
                        f"{p.nrays} rays S4, n_iter {p.n_iter}, seeded stratified atmosphere",
            "grid": [p.nx, p.ny, p.nz], "bands": p.nbands, "rays": p.nrays, "n_iter": p.n_iter,
            "schedule": plan.schedule(), "autotuned": tuned, "sweep_ms": round(sweep_ms, 4),
+           "tol": args.tol,
            "call_ms": round(call_ms, 4), "executed_updates_per_s": executed / (ms * 1e-3)}
     out = {"metric": "cell-ray-band updates/sec (288^3 4-band+grey 24-ray RTS)",
            "value": nominal / (ms * 1e-3), "unit": "cell-ray-band updates/s", "n_gpus": 1,

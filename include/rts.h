@@ -88,8 +88,18 @@ typedef struct {
   double i_bot;           /* intensity for RTS_BOT_FIXED */
   int32_t n_iter;         /* >= 1: sweeps of rays whose dominant axis is x or y */
   int32_t prec;           /* rts_precision */
-  int32_t flux;           /* 0 or 1: the workspace also holds three flux partials per sweep
-                             task, so that rts_solve / rts_solve_batched can write F and QF */
+  int32_t flux;           /* 0 or 1: the workspace also holds flux partials per sweep task,
+                             so that rts_solve / rts_solve_batched can write F and QF */
+  double tol;             /* >= 0.  0: n_iter sweeps.  > 0: tolerance-driven boundary iteration
+                             (the paper iterates boundary intensities until their error is
+                             within a prescribed tolerance): the rays sharing an x or y dominant
+                             axis and its direction sweep together until the largest change of
+                             their outflow-plane intensities between successive sweeps is at
+                             most tol times the largest outflow-plane intensity (the first sweep
+                             compares with the initial ghost, I = S), n_iter sweeps at most.
+                             Needs such a group to be one sweep task (at most four rays, one per
+                             in-plane sign pattern, as S4): else RTS_E_UNSUPPORTED at
+                             rts_plan_create.  rts_adjoint rejects it (RTS_E_UNSUPPORTED). */
 } rts_desc;
 
 typedef struct {
@@ -164,7 +174,7 @@ int rts_solve_batched(void* plan, int32_t nbox, const rts_inputs* in, const rts_
  * and lap in the workspace, then sweeps the transposed recursion downwind to
  * upwind in one persistent launch (strips of two rows exchanging edge rows,
  * like the forward sweep), recomputing the exp and interpolation weights from
- * the stored upwind D.  Returns RTS_E_UNSUPPORTED if the strips of one task
+ * the stored upwind D.  Returns RTS_E_UNSUPPORTED if a box has tol > 0, or if the strips of one task
  * cannot all be resident.  Seeds may be NULL (zero).  dS and dchi are
  * overwritten; chi = kappa * rho, so dL/dkappa_b = rho dL/dchi_b and
  * dL/drho = sum_b kappa_b dL/dchi_b.  Per-task partials are summed in a

@@ -33,6 +33,8 @@ size_t sweep_lds_bytes(int threads);
 template <class Real, int H, bool UNI>
 const void* sweep_fn();
 template <class Real, int H, bool UNI>
+const void* sweep_fn_ext(int ext);
+template <class Real, int H, bool UNI>
 hipError_t launch_sweep_h(const SweepArgs&, int, int, hipStream_t);
 template <class Real>
 hipError_t launch_reduce(const char*, const Task*, const BoxGeo&, const BoxPtrs&, hipStream_t);
@@ -160,6 +162,7 @@ int validate_desc(const rts_desc& d) {
   if (d.top != RTS_TOP_ZERO && d.top != RTS_TOP_THERMAL) return RTS_E_ARG;
   if (d.prec != RTS_FP64 && d.prec != RTS_FP32) return RTS_E_ARG;
   if (d.flux != 0 && d.flux != 1) return RTS_E_ARG;
+  if (!finite(d.tol) || d.tol < 0) return RTS_E_ARG;
   if (!finite(d.i_bot)) return RTS_E_ARG;
   for (int r = 0; r < d.nrays; ++r) {
     const double* m = d.mu + 3 * r;
@@ -313,6 +316,14 @@ void build_layout(Plan& P) {
     T.xbuf_off = (int64_t)(off / sizeof(uint64_t));
     off = align_up(off + (size_t)T.strips * 2 * 2 * kMaxRaysPerTask * T.n_cols * words * sizeof(uint64_t));
   }
+  for (Task& T : P.tasks) {  // tolerance-driven laps: per-lap maxima and arrival counts
+    T.tol = T.z_planes ? 0.0 : P.boxes[T.box].d.tol;
+    T.tolw_off = -1;
+    if (T.tol > 0) {
+      T.tolw_off = (int64_t)(off / sizeof(uint64_t));
+      off = align_up(off + (size_t)T.laps * 3 * sizeof(uint64_t));
+    }
+  }
   P.off_tasks = off;
   off = align_up(off + sizeof(Task) * P.tasks.size());
   P.off_queue = off;
@@ -341,6 +352,11 @@ void build_layout(Plan& P) {
     T.part_off = (int64_t)(off / esz);
     off = align_up(off + (size_t)B.N * esz);
     T.n_cells = B.N;
+    T.gbuf_off = -1;
+    if (T.tol > 0) {  // the previous last plane of the strips' rows, every slot
+      T.gbuf_off = (int64_t)(off / esz);
+      off = align_up(off + (size_t)T.n_rows * T.n_cols * kMaxRaysPerTask * esz);
+    }
     T.flux_off = -1;
     if (B.d.flux) {  // flux partials along cols, rows and, unless uni, the plane axis
       T.flux_off = (int64_t)(off / esz);
@@ -451,9 +467,18 @@ int resident_blocks(const void* fn, int threads, size_t lds, int* out) {
 
 template <class Real, int H>
 int occupancy_h(Plan& P) {
-  const void* fn = P.uni ? sweep_fn<Real, H, true>() : sweep_fn<Real, H, false>();
-  int rc = resident_blocks(fn, P.threads, sweep_lds_bytes<Real, H>(P.threads), &P.occupancy_blocks);
-  if (rc) return rc;
+  // the smallest residency of the plain and the extended sweeps (flux partials,
+  // tolerance laps: more registers and a little static LDS)
+  const void* fns[3] = {P.uni ? sweep_fn<Real, H, true>() : sweep_fn<Real, H, false>(),
+                        P.uni ? sweep_fn_ext<Real, H, true>(1) : sweep_fn_ext<Real, H, false>(1),
+                        P.uni ? sweep_fn_ext<Real, H, true>(2) : sweep_fn_ext<Real, H, false>(2)};
+  P.occupancy_blocks = 1 << 30;
+  for (const void* f : fns) {
+    int nb = 0;
+    int rc = resident_blocks(f, P.threads, sweep_lds_bytes<Real, H>(P.threads), &nb);
+    if (rc) return rc;
+    P.occupancy_blocks = std::min(P.occupancy_blocks, nb);
+  }
   return resident_blocks(reverse_fn<Real>(P.threads), reverse_threads(P.threads),
                          reverse_lds_bytes<Real>(P.threads), &P.rev_blocks);
 }
@@ -555,6 +580,9 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
   a.flux = 0;
   if (out)
     for (size_t b = 0; b < P.boxes.size(); ++b) a.flux |= out[b].F != nullptr;
+  a.ext = a.flux ? 1 : 0;
+  for (const Task& T : P.tasks)
+    if (T.tol > 0) a.ext = 2;
   // Every strip of a task must be resident together (neighbouring strips wait
   // on each other), so the grid never drops below the largest task's strip
   // count; tickets are claimed in order, hence with that many resident
@@ -860,6 +888,15 @@ int rts_plan_create(const rts_desc* descs, int32_t nbox, void** out) {
           tl.push_back(a);
         }
       }
+      // with a tolerance the rays of a group stop together: one sweep task each
+      if (B.d.tol > 0)
+        for (auto& k : keys)
+          if (k.first != 2 && grp[k].size() > 1) {
+            g_last_hip = "tol > 0 needs at most four rays per dominant axis and direction, "
+                         "one per in-plane sign pattern";
+            delete P;
+            return RTS_E_UNSUPPORTED;
+          }
       for (auto& k : keys)
         for (auto& a : grp[k]) B.groups.push_back(a);
       B.tasks_per_band = (int)B.groups.size();
@@ -934,6 +971,11 @@ int rts_adjoint(void* plan, int32_t nbox, const rts_inputs* in, const rts_seeds*
   if (nbox != (int)P->boxes.size()) return RTS_E_ARG;
   for (int b = 0; b < nbox; ++b)
     if (!in[b].kappa || !in[b].rho || !in[b].S || !d[b].dS || !d[b].dchi) return RTS_E_ARG;
+  for (int b = 0; b < nbox; ++b)
+    if (P->boxes[b].d.tol > 0) {  // the reverse sweep replays a fixed number of laps
+      g_last_hip = "rts_adjoint needs a fixed sweep count (tol = 0)";
+      return RTS_E_UNSUPPORTED;
+    }
   if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 || ws_bytes < P->total_adj)
     return RTS_E_WORKSPACE;
   try {

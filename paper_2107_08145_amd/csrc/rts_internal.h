@@ -47,6 +47,11 @@ struct Task {
                            // component is mu_axis times the partial sum, not stored
   int32_t frame[3];        // grid axis (0 x, 1 y, 2 z) of cols, rows and the plane axis
   int32_t pad2;
+  double tol;              // > 0: laps stop when the last plane changes by <= tol of its largest
+                           // intensity (laps is then the largest count); 0: always laps
+  int64_t gbuf_off;        // tol: element offset of the previous last plane D [row][col][slot]
+  int64_t tolw_off;        // tol: 64-bit word offset of [laps][3] (max change, max intensity,
+                           // strips arrived), zeroed by every call
   int64_t n_cells;         // cells of the box
   int64_t xbuf_off;        // 64-bit-word offset of the neighbour exchange buffer
   int64_t it_off;          // element offset of this band's I_top block in the box I_top
@@ -131,6 +136,8 @@ struct SweepArgs {
   int64_t timeout_ticks;   // s_memrealtime ticks before a wait gives up
   int32_t store_d;         // also store D of every plane (forward pass of the adjoint)
   int32_t flux;            // also write the flux partials sum_r w_r mu_r D_r
+  int32_t ext;             // launch the extended sweep (flux partials and/or tolerance laps)
+  int32_t pad;
   BoxPtrs box[kMaxBoxes];
 };
 

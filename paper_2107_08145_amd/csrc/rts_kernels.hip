@@ -272,7 +272,94 @@ struct LRow {
 // then the interior rows) and, after a barrier, a write phase that stores the
 // new plane; a second barrier ends the step.  Addresses of global data are a
 // uniform row pointer plus the thread's column.
-template <class Real, int H, bool UNI, bool FULL, bool FLUX>
+// End of a lap of a tolerance-driven sweep (called by every thread of the
+// strip, after the lap's last plane is in LDS: D and S of this thread's column
+// are read from there, so the call takes no register arrays and stays out of
+// the step's register allocation): compares this strip's rows of the plane
+// with the stored previous one (the ghost the lap started from) and stores
+// the new one; the
+// workgroup's maxima of |change| and |D + S| go to the task's words of this
+// lap with device-scope atomic max (non-negative doubles order like their
+// bits), then thread 0 counts the strip in and waits until every strip of the
+// task has (bounded by the watchdog).  Returns the task's common decision:
+// stop after this lap (within tolerance, or the last lap).
+// (Task fields come as scalars: `used` has bit r set for a used slot r.)
+template <class Real, int H>
+__device__ __noinline__ bool lap_end_stop(char* ws, int64_t timeout_ticks, double tol, int laps,
+                                          int strips, int64_t gbuf_off, int64_t tolw_off,
+                                          int used, int W, int lap, int hr, bool act, int c,
+                                          int r0, const Real* lc) {
+  using ST = Strip<Real, H>;
+  constexpr int R = kMaxRaysPerTask;
+  __shared__ double sh_red[2][kMaxCols / 64];
+  __shared__ int sh_stop;
+  double dmax = 0.0, smax = 0.0;
+  if (act) {
+    Real* gb = gptr(reinterpret_cast<Real*>(ws) + gbuf_off);
+    for (int i = 0; i < hr; ++i) {
+      for (int r = 0; r < R; ++r) {
+        if (!((used >> r) & 1)) continue;  // unused slot
+        const Real d = lc[ST::qd(i, r)];
+        Real& g = gb[((int64_t)(r0 + i) * W + c) * R + r];
+        dmax = fmax(dmax, (double)fabs(d - g));
+        smax = fmax(smax, (double)fabs(d + lc[ST::qs(i + 1)]));
+        g = d;
+      }
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    dmax = fmax(dmax, __shfl_xor(dmax, o));
+    smax = fmax(smax, __shfl_xor(smax, o));
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh_red[0][wv] = dmax;
+    sh_red[1][wv] = smax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (int)(blockDim.x + 63) / 64;
+    for (int w = 1; w < nw; ++w) {
+      dmax = fmax(dmax, sh_red[0][w]);
+      smax = fmax(smax, sh_red[1][w]);
+    }
+    unsigned long long* tw =
+        gptr(reinterpret_cast<unsigned long long*>(ws) + tolw_off) + 3 * lap;
+    int* status = gptr(reinterpret_cast<int*>(ws));
+    atomicMax(&tw[0], (unsigned long long)__double_as_longlong(dmax));
+    atomicMax(&tw[1], (unsigned long long)__double_as_longlong(smax));
+    __hip_atomic_fetch_add((RTS_GLOBAL unsigned long long*)(uintptr_t)&tw[2], 1ull,
+                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    auto arrived = [&]() {
+      return __hip_atomic_load((const RTS_GLOBAL unsigned long long*)(uintptr_t)&tw[2],
+                               __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    bool ok = true;
+    if (arrived() < (unsigned long long)strips) {
+      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+      while (arrived() < (unsigned long long)strips) {
+        __builtin_amdgcn_s_sleep(2);
+        if (ld_dev(status) != 0) { ok = false; break; }
+        if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > timeout_ticks) {
+          st_dev(status, 1);
+          ok = false;
+          break;
+        }
+      }
+    }
+    const double gd = __longlong_as_double((long long)__hip_atomic_load(
+        (const RTS_GLOBAL unsigned long long*)(uintptr_t)&tw[0], __ATOMIC_ACQUIRE,
+        __HIP_MEMORY_SCOPE_AGENT));
+    const double gs = __longlong_as_double((long long)__hip_atomic_load(
+        (const RTS_GLOBAL unsigned long long*)(uintptr_t)&tw[1], __ATOMIC_ACQUIRE,
+        __HIP_MEMORY_SCOPE_AGENT));
+    sh_stop = !ok || gd <= tol * gs || lap + 1 >= laps;
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(sh_stop) != 0;
+}
+
+template <class Real, int H, bool UNI, bool FULL, int EXT>
 __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const int strip,
                                           Real* lds) {
   using ST = Strip<Real, H>;
@@ -327,7 +414,9 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
   const int q0 = T.sa > 0 ? 0 : na - 1;
   const int q_last = T.sa > 0 ? na - 1 : 0;
   const int nsteps = zp ? na - 1 : T.laps * na;
-  const int out_from = zp ? 0 : (T.laps - 1) * na;
+  // tolerance-driven laps: outputs written every lap (the last lap run keeps them)
+  const bool tolmode = EXT == 2 && !zp && T.tol > 0;
+  const int out_from = zp || tolmode ? 0 : (T.laps - 1) * na;
   auto plane_of = [&](int t) {
     return t < 0 ? (zp ? q0 : q_last) : (zp ? q0 + T.sa * (t + 1) : q0 + T.sa * (t % na));
   };
@@ -376,7 +465,7 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
       }
       *lane_at(urow(P, qo + (r0 + i) * rs), ub) = sum;
     }
-    if (FLUX && T.flux_off >= 0) {  // (a box without flux partials writes none)
+    if (EXT >= 1 && A.flux && T.flux_off >= 0) {  // (a box without flux partials writes none)
       // flux partials sum_r (w mu_k)_r D_r along k = cols, rows (and the plane
       // axis unless uni), in the layout of the partial sum.  With uni the
       // slots share |w mu_k| and the signs follow the slot order (cols: + for
@@ -461,6 +550,15 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
     store_plane(D0);
     if (zp) write_out(q0, D0);
     if (zp) store_d(0, D0);
+    if (tolmode && act) {  // the initial ghost plane's D of this strip's rows
+      Real* gb = gptr(reinterpret_cast<Real*>(A.ws) + T.gbuf_off);
+#pragma unroll
+      for (int i = 0; i < H; ++i) {
+        if (!FULL && i >= hr) break;
+#pragma unroll
+        for (int r = 0; r < R; ++r) gb[((int64_t)(r0 + i) * W + c) * R + r] = D0[i][r];
+      }
+    }
     if (nsteps > 0) load_plane(plane_of(0));
     lds_barrier();
   }
@@ -662,6 +760,20 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
     store_plane(Dn);
     if (t >= out_from) write_out(q, Dn);
     store_d(zp ? t + 1 : t, Dn);
+    if (tolmode && (t % na) == na - 1) {
+      // end of a lap: the change of this strip's part of the last plane (the
+      // next ghost) and its largest intensity, folded into the task's words;
+      // once every strip of the task has arrived all read the same maxima and
+      // stop together when the change is within tolerance
+      int used = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) used |= (T.ray[r].ray >= 0) << r;
+      if (lap_end_stop<Real, H>(A.ws, A.timeout_ticks, T.tol, T.laps, T.strips, T.gbuf_off,
+                                T.tolw_off, used, W, t / na, hr, act, c, r0, lc)) {
+        lds_barrier();
+        break;
+      }
+    }
     if (t + 1 < nsteps) {
       load_plane(plane_of(t + 1));
       halo_issue(t + 1);
@@ -670,9 +782,10 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
   }
 }
 
-// FLUX: also write the flux partials (a separate instantiation, so that the
-// solve without them keeps its register allocation)
-template <class Real, int H, bool UNI, bool FLUX>
+// EXT: 0 the plain sweep; 1 also the flux partials (A.flux); 2 also
+// tolerance-driven laps (T.tol > 0).  Separate instantiations, so that each
+// keeps its own register allocation.
+template <class Real, int H, bool UNI, int EXT>
 __global__ __launch_bounds__(1024) void rts_sweep(SweepArgs A) {
   extern __shared__ char smem_raw[];
   Real* lds = reinterpret_cast<Real*>(smem_raw);
@@ -689,8 +802,8 @@ __global__ __launch_bounds__(1024) void rts_sweep(SweepArgs A) {
     while (qi + 1 < A.ntasks && queue[2 * (qi + 1)] <= tk) ++qi;
     CTask& T = ((CTask*)(uintptr_t)A.tasks)[queue[2 * qi + 1]];
     const int strip = tk - queue[2 * qi];
-    if ((strip + 1) * T.rows_per_strip <= T.n_rows) run_strip<Real, H, UNI, true, FLUX>(A, T, strip, lds);
-    else run_strip<Real, H, UNI, false, FLUX>(A, T, strip, lds);
+    if ((strip + 1) * T.rows_per_strip <= T.n_rows) run_strip<Real, H, UNI, true, EXT>(A, T, strip, lds);
+    else run_strip<Real, H, UNI, false, EXT>(A, T, strip, lds);
   }
 }
 
@@ -1655,16 +1768,22 @@ size_t sweep_lds_bytes(int threads) {
 
 template <class Real, int H, bool UNI>
 const void* sweep_fn() {
-  return reinterpret_cast<const void*>(&rts_sweep<Real, H, UNI, false>);
+  return reinterpret_cast<const void*>(&rts_sweep<Real, H, UNI, 0>);
+}
+
+template <class Real, int H, bool UNI>
+const void* sweep_fn_ext(int ext) {
+  return ext == 2 ? reinterpret_cast<const void*>(&rts_sweep<Real, H, UNI, 2>)
+                  : reinterpret_cast<const void*>(&rts_sweep<Real, H, UNI, 1>);
 }
 
 template <class Real, int H, bool UNI>
 hipError_t launch_sweep_h(const SweepArgs& a, int grid, int threads, hipStream_t st) {
-  // (the flux variant has the same LDS and register bounds)
-  if (a.flux)
-    rts_sweep<Real, H, UNI, true><<<dim3(grid), dim3(threads), sweep_lds_bytes<Real, H>(threads), st>>>(a);
-  else
-    rts_sweep<Real, H, UNI, false><<<dim3(grid), dim3(threads), sweep_lds_bytes<Real, H>(threads), st>>>(a);
+  // (the occupancy estimate takes the smallest of the three variants)
+  const size_t lds = sweep_lds_bytes<Real, H>(threads);
+  if (a.ext == 2) rts_sweep<Real, H, UNI, 2><<<dim3(grid), dim3(threads), lds, st>>>(a);
+  else if (a.ext == 1) rts_sweep<Real, H, UNI, 1><<<dim3(grid), dim3(threads), lds, st>>>(a);
+  else rts_sweep<Real, H, UNI, 0><<<dim3(grid), dim3(threads), lds, st>>>(a);
   return hipGetLastError();
 }
 
@@ -1777,7 +1896,9 @@ RTS_ADJ_INST(double)
   template hipError_t launch_sweep_h<Real, H, false>(const SweepArgs&, int, int, hipStream_t); \
   template size_t sweep_lds_bytes<Real, H>(int);                                            \
   template const void* sweep_fn<Real, H, true>();                                           \
-  template const void* sweep_fn<Real, H, false>();
+  template const void* sweep_fn<Real, H, false>();                                          \
+  template const void* sweep_fn_ext<Real, H, true>(int);                                    \
+  template const void* sweep_fn_ext<Real, H, false>(int);
 RTS_INST(float, 2)
 RTS_INST(float, 4)
 RTS_INST(float, 6)

@@ -46,7 +46,7 @@ class Desc(ctypes.Structure):
                 ("mu", ctypes.POINTER(ctypes.c_double)), ("w", ctypes.POINTER(ctypes.c_double)),
                 ("qweight", ctypes.POINTER(ctypes.c_double)), ("bot", ctypes.c_int32),
                 ("top", ctypes.c_int32), ("i_bot", ctypes.c_double), ("n_iter", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("flux", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("flux", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class Inputs(ctypes.Structure):
@@ -152,8 +152,9 @@ def _stream_ptr(stream=None):
 class Plan:
     """A librts plan for one or more boxes (paper_2107_08145_amd.inputs.Problem)."""
 
-    def __init__(self, problems, prec: int = RTS_FP64, flux=False):
-        """flux: bool, or one bool per box (desc.flux: room for the flux vector)."""
+    def __init__(self, problems, prec: int = RTS_FP64, flux=False, tol: float = 0.0):
+        """flux: bool, or one bool per box (desc.flux: room for the flux vector);
+        tol: desc.tol of every box (0: n_iter sweeps; > 0: tolerance-driven)."""
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
         flags = list(flux) if isinstance(flux, (list, tuple)) else [flux] * len(problems)
@@ -174,6 +175,7 @@ class Plan:
             d.qweight = qw.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             d.bot, d.top, d.i_bot, d.n_iter, d.prec = p.bot, p.top, p.i_bot, p.n_iter, prec
             d.flux = 1 if flags[i] else 0
+            d.tol = float(tol)
         h = ctypes.c_void_p()
         _check(lib().rts_plan_create(descs, len(problems), ctypes.byref(h)), "rts_plan_create")
         self.handle = h
@@ -294,11 +296,12 @@ class Plan:
                "rts_check_status")
 
 
-def solve(p, prec: int = RTS_FP64, plan: Plan | None = None, flux: bool = False):
+def solve(p, prec: int = RTS_FP64, plan: Plan | None = None, flux: bool = False,
+          tol: float = 0.0):
     """Forward solve of one problem on the current GPU; returns numpy (Q, J, I_top), or
-    (Q, J, I_top, F, QF) with flux."""
+    (Q, J, I_top, F, QF) with flux; tol > 0: tolerance-driven boundary iteration."""
     import torch
-    plan = plan or Plan(p, prec, flux=flux)
+    plan = plan or Plan(p, prec, flux=flux, tol=tol)
     ins = plan.device_inputs(p)
     outs = plan.new_outputs(p, want_flux=flux)
     plan.solve_into([ins], [outs])

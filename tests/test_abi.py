@@ -240,3 +240,27 @@ def test_flux_plan_workspace_and_argument_errors():
         dd.flux = flag
         assert L.rts_plan_create(descs, 1, ctypes.byref(h)) == want
     L.rts_plan_destroy(h)
+
+
+def test_tolerance_plan_checks():
+    p = inputs.workload("grey32", size=16)
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(rts.RTSError) as e:
+            rts.Plan(p, rts.RTS_FP64, tol=bad)
+        assert e.value.status == rts.RTS_E_ARG
+    pl = rts.Plan(p, rts.RTS_FP64, tol=1e-6)       # S4: one task per dominant axis and direction
+    # two rays with the same dominant axis, direction and in-plane signs need two tasks
+    q = inputs.workload("grey32", size=16)
+    q.mu = np.concatenate([q.mu, q.mu[:1]])
+    q.w = np.concatenate([q.w, q.w[:1]]) / (1 + q.w[0])
+    rts.Plan(q, rts.RTS_FP64)                       # fine without a tolerance
+    with pytest.raises(rts.RTSError) as e:
+        rts.Plan(q, rts.RTS_FP64, tol=1e-6)
+    assert e.value.status == rts.RTS_E_UNSUPPORTED
+    # the adjoint replays a fixed sweep count: rejected before any HIP call
+    L = rts.lib()
+    ci = rts.Inputs(256, 256, 256)
+    cs = rts.Seeds(None, None, None)
+    cg = rts.Grads(256, 256)
+    assert L.rts_adjoint(pl.handle, 1, ctypes.byref(ci), ctypes.byref(cs), ctypes.byref(cg),
+                         ctypes.c_void_p(256), 1 << 40, None) == rts.RTS_E_UNSUPPORTED

@@ -1,0 +1,118 @@
+"""GPU tolerance-driven boundary iteration (rts_desc.tol > 0) against the FP64
+CPU oracle's solve_tol: the rays sharing an x or y dominant axis and its
+direction sweep together until the largest change of their outflow planes is
+within tol of their largest outflow intensity (n_iter sweeps at most).
+
+The stop decision compares floating-point maxima, so each case uses a tol
+whose oracle sweep counts do not change between 0.9 tol and 1.1 tol: the
+GPU's FP32 or differently rounded FP64 maxima then take the same decisions.
+Bars: FP64 as in test_gpu_parity (per cell |dQ| <= 1e-9 |Q| + 4 pi chi S
+1e-13, J and I_top 1e-13 of max), FP32 2e-5 of max|Q| and 2e-6 of max J and
+I_top; a different sweep count would differ by about tol (>= 1e-4 here).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2107_08145_amd import inputs, rts
+
+pytestmark = pytest.mark.gpu
+
+
+def _thin(nx, ny, nz, seed, **kw):
+    # optically thin horizontally: the periodic iteration needs several sweeps
+    return inputs.random_problem(nx, ny, nz, seed, lo=0.02, hi=0.5, **kw)
+
+
+def _robust_tol(p, cands, n_iter):
+    for tol in cands:
+        s = [oracle.solve_tol(p, t, threads=8)[-1] for t in (tol, 0.9 * tol, 1.1 * tol)]
+        if all(np.array_equal(s[0], x) for x in s[1:]) and 1 < s[0].max() < n_iter:
+            return tol, s[0]
+    raise AssertionError("no tolerance with stable sweep counts")
+
+
+def _check64(p, got, ref):
+    Qg, Jg, Ig = got[:3]
+    Qo, Jo, Io = ref[:3]
+    chi = oracle.chi_of(p)
+    floor = 4 * math.pi * (np.abs(chi) * np.abs(p.S)).max(axis=0) * 1e-13
+    assert np.all(np.abs(Qg - Qo) <= 1e-9 * np.abs(Qo) + floor), np.abs(Qg - Qo).max()
+    assert np.abs(Jg - Jo).max() <= 1e-13 * np.abs(Jo).max()
+    assert np.abs(Ig - Io).max() <= 1e-13 * np.abs(Io).max()
+
+
+def _check32(got, ref):
+    eq = np.abs(got[0] - ref[0]).max() / np.abs(ref[0]).max()
+    ej = np.abs(got[1] - ref[1]).max() / np.abs(ref[1]).max()
+    ei = np.abs(got[2] - ref[2]).max() / np.abs(ref[2]).max()
+    assert eq <= 2e-5 and ej <= 2e-6 and ei <= 2e-6, (eq, ej, ei)
+    return eq, ej, ei
+
+
+@pytest.mark.parametrize("shape,seed", [((20, 17, 11), 1), ((33, 14, 9), 2), ((16, 21, 2), 3)])
+def test_tol_fp64_matches_oracle(shape, seed):
+    p = _thin(*shape, seed=seed, bands=2, n_iter=10)
+    tol, sw = _robust_tol(p, [1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6], 10)
+    print("case tol fp64", shape, tol, sw.max(), flush=True)
+    got = rts.solve(p, rts.RTS_FP64, tol=tol)
+    _check64(p, got, oracle.solve_tol(p, tol, threads=8))
+
+
+def test_tol_fp32_matches_oracle_with_flux():
+    p = _thin(26, 24, 13, seed=4, bands=2, n_iter=8)
+    p32 = p.astype(np.float32)
+    p64 = p32.astype(np.float64)
+    tol, sw = _robust_tol(p64, [1e-3, 3e-4, 1e-4], 8)
+    print("case tol fp32 + flux", tol, sw.max(), flush=True)
+    got = rts.solve(p32, rts.RTS_FP32, tol=tol, flux=True)
+    ref = oracle.solve_tol(p64, tol, threads=8, flux=True)
+    eq, ej, ei = _check32(got, ref)
+    scale = 4 * math.pi * np.abs(ref[1]).max()
+    assert np.abs(got[3] - ref[3]).max() <= 2e-6 * scale
+    print(f"tol fp32: Q {eq:.2e} J {ej:.2e} I_top {ei:.2e}")
+
+
+def test_tol_limits_equal_fixed_sweeps():
+    # a huge tol stops after one sweep; a tol that is never met runs n_iter
+    p = _thin(18, 15, 10, seed=5, n_iter=4)
+    one = p.astype(p.S.dtype)
+    one.n_iter = 1
+    print("case tol limits", flush=True)
+    for a, b in zip(rts.solve(p, rts.RTS_FP64, tol=1e30), rts.solve(one, rts.RTS_FP64)):
+        assert np.array_equal(a, b)
+    for a, b in zip(rts.solve(p, rts.RTS_FP64, tol=1e-300), rts.solve(p, rts.RTS_FP64)):
+        assert np.array_equal(a, b)
+
+
+def test_tol_batched_and_graph_replays():
+    import torch
+    ps = [_thin(24, 18, 12, seed=6, bands=2, n_iter=8).astype(np.float32),
+          _thin(17, 26, 11, seed=7, bands=2, n_iter=8).astype(np.float32)]
+    tol = 3e-4
+    refs = [oracle.solve_tol(p.astype(np.float64), tol, threads=8) for p in ps]
+    for p in ps:   # stable decisions for this tol
+        q = p.astype(np.float64)
+        s = [oracle.solve_tol(q, t, threads=8)[-1] for t in (tol, 0.9 * tol, 1.1 * tol)]
+        assert all(np.array_equal(s[0], x) for x in s[1:])
+    pl = rts.Plan(ps, rts.RTS_FP32, tol=tol)
+    ins = [pl.device_inputs(p) for p in ps]
+    outs = [pl.new_outputs(p) for p in ps]
+    first = None
+    for use_graph in (0, 1):
+        pl.set_schedule(use_graph=use_graph)
+        for rep in range(3):
+            print("case tol batched", use_graph, rep, flush=True)
+            pl.solve_into(ins, outs, batched=True)
+            pl.check_status()
+            torch.cuda.synchronize()
+            got = [[t.double().cpu().numpy() for t in o] for o in outs]
+            for g, ref in zip(got, refs):
+                _check32(g, ref)
+            if first is None:
+                first = got
+            for g, f in zip(got, first):
+                for a, b in zip(g, f):
+                    assert np.array_equal(a, b), (use_graph, rep)
