@@ -238,6 +238,12 @@ def bench_adjoint(args):
     adj_ms = _time_calls(lambda: plan.adjoint_into([ins], [(gQ, None, gI)], [(dS, dchi)]),
                          args.steps, args.warmup)
     plan.check_status()
+    # a training step: the forward keeps D (rts_solve_for_adjoint), the backward
+    # only sweeps in reverse (rts_adjoint_from_solve)
+    keep_ms = _time_calls(lambda: plan.solve_for_adjoint_into([ins], [outs]), args.steps, args.warmup)
+    back_ms = _time_calls(lambda: plan.adjoint_from_solve_into([ins], [(gQ, None, gI)], [(dS, dchi)]),
+                          args.steps, args.warmup)
+    plan.check_status()
     nominal = p.ncells * p.nrays * p.nbands
     out = {"metric": "adjoint time / forward time (RTS, reverse-mode dL/dS and dL/dchi)",
            "value": adj_ms / fwd_ms, "unit": "ratio", "n_gpus": 1, "steps": args.steps,
@@ -246,6 +252,9 @@ def bench_adjoint(args):
            "data": "synthetic",
            "adjoint_updates_per_s": nominal / (adj_ms * 1e-3),
            "workspace_bytes": plan.workspace_bytes(rts.RTS_OP_ADJOINT),
+           "training_step": {"forward_keeping_d_ms": round(keep_ms, 4), "backward_ms": round(back_ms, 4),
+                             "backward_over_forward": round(back_ms / fwd_ms, 3),
+                             "step_over_forward": round((keep_ms + back_ms) / fwd_ms, 3)},
            "config": {"workload": f"{name}: {p.nx}x{p.ny}x{p.nz}, {p.nbands} band(s), {p.nrays} rays, "
                                   f"n_iter {p.n_iter}; L = sum (I_top - I_target)^2 + sum g Q"}}
     print(json.dumps(out), flush=True)

@@ -182,6 +182,23 @@ int rts_solve_batched(void* plan, int32_t nbox, const rts_inputs* in, const rts_
 int rts_adjoint(void* plan, int32_t nbox, const rts_inputs* in, const rts_seeds* g,
                 const rts_grads* d, void* ws, size_t ws_bytes, void* hip_stream);
 
+/* The forward solve of all boxes (as rts_solve_batched, never from a graph)
+ * that also keeps D of every plane and lap in the workspace, which must hold
+ * rts_workspace_bytes(RTS_OP_ADJOINT) bytes, for a later
+ * rts_adjoint_from_solve: the forward pass of a training step keeps what its
+ * backward pass needs, as an autograd tape keeps activations.  Same errors as
+ * rts_adjoint. */
+int rts_solve_for_adjoint(void* plan, int32_t nbox, const rts_inputs* in, const rts_outputs* out,
+                          void* ws, size_t ws_bytes, void* hip_stream);
+
+/* rts_adjoint without its forward pass: the reverse sweep and the gradient
+ * reduction read the D kept by the last rts_solve_for_adjoint on this
+ * workspace, which the caller must leave untouched in between (no other call
+ * of this plan on it) with the same inputs; the results are bitwise those of
+ * rts_adjoint.  Seeds, gradients and errors as in rts_adjoint. */
+int rts_adjoint_from_solve(void* plan, int32_t nbox, const rts_inputs* in, const rts_seeds* g,
+                           const rts_grads* d, void* ws, size_t ws_bytes, void* hip_stream);
+
 /* Autotuner: runs the forward solve of all boxes (as rts_solve_batched, not
  * replayed from a graph) under every candidate schedule -- rows per strip
  * 2/4/6/8 (FP32) or 2/4 (FP64), queue order 0/1 -- `reps` timed calls each

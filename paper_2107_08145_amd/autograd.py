@@ -1,10 +1,12 @@
 """torch.autograd binding of the librts forward solve and its adjoint.
 
-`rts_apply(kappa, rho, S, plan)` returns (Q, J, I_top) of one box and, when
-any input requires a gradient, records a node whose backward is one
-`rts_adjoint` call: it re-runs the forward sweep storing D of every plane,
-sweeps the transposed recursion plane by plane in reverse, and returns
-dL/dS and dL/dchi, chi = kappa rho.  The chain rule to the caller's inputs is
+`rts_apply(kappa, rho, S, plan)` returns (Q, J, I_top) of one box.  When any
+input requires a gradient the forward is `rts_solve_for_adjoint` on a private
+adjoint workspace (it keeps D of every plane, as a tape keeps activations)
+and the backward is `rts_adjoint_from_solve` on that workspace: the
+transposed recursion swept in reverse, giving dL/dS and dL/dchi,
+chi = kappa rho.  Each call owns its workspace, so several graphs may be in
+flight.  The chain rule to the caller's inputs is
 dL/dkappa_b = rho dL/dchi_b and dL/drho = sum_b kappa_b dL/dchi_b.
 
 Argument marshalling only: every step runs in librts (no CPU fallback).
@@ -27,7 +29,12 @@ class RTSFunction(torch.autograd.Function):
         dt = plan.dtype
         ins = (_dev(kappa, dt), _dev(rho, dt), _dev(S, dt))
         Q, J, It = plan.new_outputs(p)
-        plan.solve_into([ins], [(Q, J, It)])
+        if any(ctx.needs_input_grad[:3]):
+            ws_t, w, nbytes = plan.adjoint_workspace()
+            plan.solve_for_adjoint_into([ins], [(Q, J, It)], ws=(w, nbytes))
+            ctx.ws = (ws_t, w, nbytes)
+        else:
+            plan.solve_into([ins], [(Q, J, It)])
         ctx.plan = plan
         ctx.save_for_backward(*ins)
         return Q, J, It
@@ -40,7 +47,9 @@ class RTSFunction(torch.autograd.Function):
         dS = torch.empty_like(S)
         dchi = torch.empty_like(S)
         seeds = (_dev(gQ, torch.float64), _dev(gJ, dt), _dev(gIt, dt))
-        plan.adjoint_into([(kappa, rho, S)], [seeds], [(dS, dchi)])
+        ws_t, w, nbytes = ctx.ws
+        plan.adjoint_from_solve_into([(kappa, rho, S)], [seeds], [(dS, dchi)], ws=(w, nbytes))
+        del ctx.ws
         dkappa = dchi * rho.unsqueeze(0) if ctx.needs_input_grad[0] else None
         drho = (dchi * kappa).sum(0) if ctx.needs_input_grad[1] else None
         return dkappa, drho, (dS if ctx.needs_input_grad[2] else None), None

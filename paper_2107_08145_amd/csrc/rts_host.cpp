@@ -546,10 +546,11 @@ BoxGeo box_geo(const Plan& P, size_t b) {
 }
 
 // With out == nullptr (the forward pass of the adjoint) the sweep also stores
-// D of every plane, writes no I_top and the reduce is skipped.
+// D of every plane, writes no I_top and the reduce is skipped; with store the
+// sweep stores D as well as writing the outputs (rts_solve_for_adjoint).
 template <class Real>
 int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char* ws,
-                    hipStream_t st, hipEvent_t* ev) {
+                    hipStream_t st, hipEvent_t* ev, bool store = false) {
   // header and exchange buffers to zero
   RTS_HIP(launch_zero(reinterpret_cast<int*>(ws),
                       (int64_t)((P.off_tasks) / sizeof(int32_t)), st));
@@ -576,7 +577,7 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
                              out[b].F, out[b].QF}
                    : BoxPtrs{in[b].kappa, in[b].rho, in[b].S, nullptr, nullptr, nullptr, nullptr,
                              nullptr};
-  a.store_d = out ? 0 : 1;
+  a.store_d = out && !store ? 0 : 1;
   a.flux = 0;
   if (out)
     for (size_t b = 0; b < P.boxes.size(); ++b) a.flux |= out[b].F != nullptr;
@@ -605,11 +606,17 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
 
 // Enqueue one adjoint: the forward sweep storing D, the seeds, one reverse
 // launch per unrolled plane (every task of every box), the gradient reduce.
+// Without run_forward the stored D of an earlier rts_solve_for_adjoint on this
+// workspace is used; only the header (reverse ticket, status) is cleared.
 template <class Real>
 int enqueue_adjoint(Plan& P, const rts_inputs* in, const rts_seeds* g, const rts_grads* d,
-                    char* ws, hipStream_t st) {
-  int rc = enqueue_forward<Real>(P, in, nullptr, ws, st, nullptr);
-  if (rc) return rc;
+                    char* ws, hipStream_t st, bool run_forward = true) {
+  if (run_forward) {
+    int rc = enqueue_forward<Real>(P, in, nullptr, ws, st, nullptr);
+    if (rc) return rc;
+  } else {
+    RTS_HIP(launch_zero(reinterpret_cast<int*>(ws), (int64_t)(sizeof(WsHeader) / sizeof(int32_t)), st));
+  }
   RTS_HIP(launch_zero(reinterpret_cast<int*>(ws + P.off_grads),
                       (int64_t)((P.off_grads_end - P.off_grads) / sizeof(int32_t)), st));
   for (size_t b = 0; b < P.boxes.size(); ++b) {
@@ -959,6 +966,62 @@ int rts_solve_batched(void* plan, int32_t nbox, const rts_inputs* in, const rts_
   if (!plan) return RTS_E_ARG;
   try {
     return solve_impl(static_cast<Plan*>(plan), nbox, in, out, ws, ws_bytes, hip_stream, true);
+  } catch (...) {
+    return RTS_E_HIP;
+  }
+}
+
+namespace {
+// Argument, tolerance and residency checks shared by the adjoint entry points.
+int adjoint_checks(Plan* P, int32_t nbox, const rts_inputs* in, void* ws, size_t ws_bytes) {
+  if (nbox != (int)P->boxes.size() || !in) return RTS_E_ARG;
+  for (int b = 0; b < nbox; ++b)
+    if (!in[b].kappa || !in[b].rho || !in[b].S) return RTS_E_ARG;
+  for (int b = 0; b < nbox; ++b)
+    if (P->boxes[b].d.tol > 0) {  // the reverse sweep replays a fixed number of laps
+      g_last_hip = "the adjoint needs a fixed sweep count (tol = 0)";
+      return RTS_E_UNSUPPORTED;
+    }
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 || ws_bytes < P->total_adj)
+    return RTS_E_WORKSPACE;
+  int rc = prepare(P);
+  if (rc) return rc;
+  if (P->rev_blocks < 1 || P->rev_blocks * P->cus < P->rev_max_strips) {
+    g_last_hip = "the strips of one reverse sweep task cannot all be resident";
+    return RTS_E_UNSUPPORTED;
+  }
+  return RTS_OK;
+}
+}  // namespace
+
+int rts_solve_for_adjoint(void* plan, int32_t nbox, const rts_inputs* in, const rts_outputs* out,
+                          void* ws, size_t ws_bytes, void* hip_stream) {
+  if (!plan || !in || !out) return RTS_E_ARG;
+  Plan* P = static_cast<Plan*>(plan);
+  try {
+    int rc = check_call(P, nbox, in, out, ws, ws_bytes);
+    if (rc) return rc;
+    if ((rc = adjoint_checks(P, nbox, in, ws, ws_bytes))) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    return P->prec == RTS_FP32 ? enqueue_forward<float>(*P, in, out, (char*)ws, st, nullptr, true)
+                               : enqueue_forward<double>(*P, in, out, (char*)ws, st, nullptr, true);
+  } catch (...) {
+    return RTS_E_HIP;
+  }
+}
+
+int rts_adjoint_from_solve(void* plan, int32_t nbox, const rts_inputs* in, const rts_seeds* g,
+                           const rts_grads* d, void* ws, size_t ws_bytes, void* hip_stream) {
+  if (!plan || !in || !g || !d) return RTS_E_ARG;
+  Plan* P = static_cast<Plan*>(plan);
+  for (int b = 0; b < nbox && b < (int)P->boxes.size(); ++b)
+    if (!d[b].dS || !d[b].dchi) return RTS_E_ARG;
+  try {
+    int rc = adjoint_checks(P, nbox, in, ws, ws_bytes);
+    if (rc) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    return P->prec == RTS_FP32 ? enqueue_adjoint<float>(*P, in, g, d, (char*)ws, st, false)
+                               : enqueue_adjoint<double>(*P, in, g, d, (char*)ws, st, false);
   } catch (...) {
     return RTS_E_HIP;
   }

@@ -31,7 +31,8 @@ RTS_OP_AUTOTUNE = 2
 
 # every symbol declared in include/rts.h
 SYMBOLS = ("rts_plan_create", "rts_workspace_bytes", "rts_solve", "rts_solve_batched",
-           "rts_adjoint", "rts_plan_autotune", "rts_check_status", "rts_plan_get_schedule", "rts_plan_set_schedule",
+           "rts_adjoint", "rts_solve_for_adjoint", "rts_adjoint_from_solve", "rts_plan_autotune",
+           "rts_check_status", "rts_plan_get_schedule", "rts_plan_set_schedule",
            "rts_plan_enable_timing", "rts_plan_last_timing",
            "rts_plan_destroy", "rts_status_string", "rts_version")
 
@@ -112,6 +113,9 @@ def lib():
                                         vp, sz, vp]
         L.rts_adjoint.argtypes = [vp, i32, ctypes.POINTER(Inputs), ctypes.POINTER(Seeds),
                                   ctypes.POINTER(Grads), vp, sz, vp]
+        L.rts_adjoint_from_solve.argtypes = L.rts_adjoint.argtypes
+        L.rts_solve_for_adjoint.argtypes = [vp, i32, ctypes.POINTER(Inputs),
+                                            ctypes.POINTER(Outputs), vp, sz, vp]
         L.rts_plan_autotune.argtypes = [vp, i32, ctypes.POINTER(Inputs), ctypes.POINTER(Outputs),
                                          vp, sz, vp, i32, ctypes.POINTER(Schedule)]
         L.rts_check_status.argtypes = [vp, vp, vp]
@@ -127,7 +131,8 @@ def lib():
         L.rts_version.argtypes = []
         L.rts_version.restype = ctypes.c_char_p
         for f in ("rts_plan_create", "rts_workspace_bytes", "rts_solve", "rts_solve_batched",
-                  "rts_adjoint", "rts_plan_autotune", "rts_check_status", "rts_plan_get_schedule",
+                  "rts_adjoint", "rts_solve_for_adjoint", "rts_adjoint_from_solve",
+                  "rts_plan_autotune", "rts_check_status", "rts_plan_get_schedule",
                   "rts_plan_set_schedule", "rts_plan_enable_timing", "rts_plan_last_timing"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -273,6 +278,39 @@ class Plan:
                                        _stream_ptr(stream), reps, ctypes.byref(sch)),
                "rts_plan_autotune")
         return {k: getattr(sch, k) for k, _ in Schedule._fields_}
+
+    def adjoint_workspace(self):
+        """A private adjoint workspace: (tensor, aligned pointer, bytes)."""
+        import torch
+        need = self.workspace_bytes(RTS_OP_ADJOINT)
+        t = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+        off = (-t.data_ptr()) % 256
+        return t, t.data_ptr() + off, t.numel() - off
+
+    def solve_for_adjoint_into(self, ins, outs, ws=None, stream=None):
+        """rts_solve_for_adjoint: the forward solve that also keeps D of every plane for
+        adjoint_from_solve_into; ws = (pointer, bytes) of an adjoint workspace (default: the
+        plan's own)."""
+        n = len(ins)
+        ci, co = _marshal(ins, outs)
+        w, nbytes = ws if ws is not None else self.workspace(RTS_OP_ADJOINT)
+        _check(lib().rts_solve_for_adjoint(self.handle, n, ci, co, ctypes.c_void_p(w), nbytes,
+                                           _stream_ptr(stream)), "rts_solve_for_adjoint")
+
+    def adjoint_from_solve_into(self, ins, seeds, grads, ws=None, stream=None):
+        """rts_adjoint_from_solve on the workspace of the last solve_for_adjoint_into."""
+        n = len(ins)
+        ci = (Inputs * n)()
+        cs = (Seeds * n)()
+        cg = (Grads * n)()
+        ptr = (lambda t: t.data_ptr() if t is not None else None)
+        for i, ((k, r, s), (gq, gj, gi), (ds, dc)) in enumerate(zip(ins, seeds, grads)):
+            ci[i] = Inputs(k.data_ptr(), r.data_ptr(), s.data_ptr())
+            cs[i] = Seeds(ptr(gq), ptr(gj), ptr(gi))
+            cg[i] = Grads(ds.data_ptr(), dc.data_ptr())
+        w, nbytes = ws if ws is not None else self.workspace(RTS_OP_ADJOINT)
+        _check(lib().rts_adjoint_from_solve(self.handle, n, ci, cs, cg, ctypes.c_void_p(w), nbytes,
+                                            _stream_ptr(stream)), "rts_adjoint_from_solve")
 
     def adjoint_into(self, ins, seeds, grads, stream=None):
         """Enqueue an adjoint.  ins: [(kappa, rho, S)]; seeds: [(gQ, gJ, gItop)] (any may be

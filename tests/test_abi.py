@@ -264,3 +264,29 @@ def test_tolerance_plan_checks():
     cg = rts.Grads(256, 256)
     assert L.rts_adjoint(pl.handle, 1, ctypes.byref(ci), ctypes.byref(cs), ctypes.byref(cg),
                          ctypes.c_void_p(256), 1 << 40, None) == rts.RTS_E_UNSUPPORTED
+
+
+def test_kept_forward_and_backward_argument_errors():
+    p = inputs.workload("grey32", size=16)
+    pl = rts.Plan(p, rts.RTS_FP32)
+    L = rts.lib()
+    ci = rts.Inputs(256, 256, 256)
+    co = rts.Outputs(256, None, None)
+    cs = rts.Seeds(None, None, None)
+    cg = rts.Grads(256, 256)
+    n_solve = pl.workspace_bytes(rts.RTS_OP_SOLVE)
+    # the kept forward needs the adjoint workspace; both check before any HIP call
+    assert L.rts_solve_for_adjoint(pl.handle, 1, ctypes.byref(ci), ctypes.byref(co),
+                                   ctypes.c_void_p(256), n_solve, None) == rts.RTS_E_WORKSPACE
+    assert L.rts_solve_for_adjoint(pl.handle, 2, ctypes.byref(ci), ctypes.byref(co),
+                                   ctypes.c_void_p(256), 1 << 40, None) == rts.RTS_E_ARG
+    assert L.rts_adjoint_from_solve(pl.handle, 1, ctypes.byref(ci), ctypes.byref(cs),
+                                    ctypes.byref(cg), ctypes.c_void_p(256), n_solve,
+                                    None) == rts.RTS_E_WORKSPACE
+    bad = rts.Grads(None, 256)
+    assert L.rts_adjoint_from_solve(pl.handle, 1, ctypes.byref(ci), ctypes.byref(cs),
+                                    ctypes.byref(bad), ctypes.c_void_p(256), 1 << 40,
+                                    None) == rts.RTS_E_ARG
+    tol = rts.Plan(p, rts.RTS_FP32, tol=1e-4)
+    assert L.rts_solve_for_adjoint(tol.handle, 1, ctypes.byref(ci), ctypes.byref(co),
+                                   ctypes.c_void_p(256), 1 << 40, None) == rts.RTS_E_UNSUPPORTED
