@@ -14,6 +14,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -768,9 +769,25 @@ std::string tune_key(const Plan& P, int device) {
   return k;
 }
 
+// The process-wide cache of tuned schedules (plans of several threads share it).
+std::mutex& tune_mutex() {
+  static std::mutex m;
+  return m;
+}
 std::map<std::string, rts_schedule>& tune_cache() {
   static std::map<std::string, rts_schedule> m;
   return m;
+}
+bool tune_lookup(const std::string& key, rts_schedule* s) {
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  auto hit = tune_cache().find(key);
+  if (hit == tune_cache().end()) return false;
+  *s = hit->second;
+  return true;
+}
+void tune_store(const std::string& key, const rts_schedule& s) {
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  tune_cache()[key] = s;
 }
 
 void set_sched(Plan* P, const rts_schedule& s) {
@@ -794,9 +811,9 @@ int autotune_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* ou
   if ((rc = dev_init(*P))) return rc;
   const std::string key = tune_key(*P, P->device);
   *tried = 0;
-  auto hit = tune_cache().find(key);
-  if (hit != tune_cache().end()) {
-    set_sched(P, hit->second);
+  rts_schedule cached;
+  if (tune_lookup(key, &cached)) {
+    set_sched(P, cached);
     return RTS_OK;
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -840,7 +857,7 @@ int autotune_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* ou
   (void)hipEventDestroy(e1);
   if (status == RTS_OK && *tried == 0) status = RTS_E_WORKSPACE;
   set_sched(P, status == RTS_OK ? best : orig);
-  if (status == RTS_OK) tune_cache()[key] = best;
+  if (status == RTS_OK) tune_store(key, best);
   return status;
 }
 
@@ -1031,23 +1048,11 @@ int rts_adjoint(void* plan, int32_t nbox, const rts_inputs* in, const rts_seeds*
                 const rts_grads* d, void* ws, size_t ws_bytes, void* hip_stream) {
   if (!plan || !in || !g || !d) return RTS_E_ARG;
   Plan* P = static_cast<Plan*>(plan);
-  if (nbox != (int)P->boxes.size()) return RTS_E_ARG;
-  for (int b = 0; b < nbox; ++b)
-    if (!in[b].kappa || !in[b].rho || !in[b].S || !d[b].dS || !d[b].dchi) return RTS_E_ARG;
-  for (int b = 0; b < nbox; ++b)
-    if (P->boxes[b].d.tol > 0) {  // the reverse sweep replays a fixed number of laps
-      g_last_hip = "rts_adjoint needs a fixed sweep count (tol = 0)";
-      return RTS_E_UNSUPPORTED;
-    }
-  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 || ws_bytes < P->total_adj)
-    return RTS_E_WORKSPACE;
+  for (int b = 0; b < nbox && b < (int)P->boxes.size(); ++b)
+    if (!d[b].dS || !d[b].dchi) return RTS_E_ARG;
   try {
-    int rc = prepare(P);
+    int rc = adjoint_checks(P, nbox, in, ws, ws_bytes);
     if (rc) return rc;
-    if (P->rev_blocks < 1 || P->rev_blocks * P->cus < P->rev_max_strips) {
-      g_last_hip = "the strips of one reverse sweep task cannot all be resident";
-      return RTS_E_UNSUPPORTED;
-    }
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     return P->prec == RTS_FP32 ? enqueue_adjoint<float>(*P, in, g, d, (char*)ws, st)
                                : enqueue_adjoint<double>(*P, in, g, d, (char*)ws, st);
