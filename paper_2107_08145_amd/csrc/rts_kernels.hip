@@ -1017,9 +1017,19 @@ __global__ __launch_bounds__(256) void rts_reduce_v4(const char* __restrict__ ws
       }
     }
   };
+  // f[ax] += sc * v for a uniform grid axis ax: every axis gets sc or an
+  // exact zero times v (no dynamic index into the register array)
+  auto add_to = [&](int ax, const double (&v)[4], double sc) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const double w = ax == m ? sc : 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) f[m][i] += w * v[i];
+    }
+  };
   for (int b = 0; b < G.nbands; ++b) {
     double acc[4] = {0, 0, 0, 0};
-    double fa[3][4] = {};
+    const double qfb = 4.0 * 3.14159265358979323846 * G.qweight[b];
     for (int k = 0; k < G.tasks_per_band; ++k) {
       const Task& T = tasks[G.task0 + b * G.tasks_per_band + k];
       const float* part = gptr(reinterpret_cast<const float*>(ws) + T.part_off);
@@ -1029,21 +1039,18 @@ __global__ __launch_bounds__(256) void rts_reduce_v4(const char* __restrict__ ws
       }
       // flux components along (cols, rows, plane axis) of the task, mapped to x, y, z;
       // with uni the plane-axis one is mu_axis times the partial sum
-      double v[3][4] = {};
-      add_part(part, T.transposed, v[2]);
-      for (int i = 0; i < 4; ++i) acc[i] += v[2][i];
+      double v[4] = {0, 0, 0, 0};
+      add_part(part, T.transposed, v);
+      for (int i = 0; i < 4; ++i) acc[i] += v[i];
+      if (T.uni) add_to(T.frame[2], v, qfb * (T.ray[0].wm[2] / T.ray[0].w));
       const float* fp = gptr(reinterpret_cast<const float*>(ws) + T.flux_off);
-      add_part(fp, T.transposed, v[0]);
-      add_part(fp + N, T.transposed, v[1]);
-      if (T.uni) {
-        const double mua = T.ray[0].wm[2] / T.ray[0].w;
-        for (int i = 0; i < 4; ++i) v[2][i] *= mua;
-      } else {
-        for (int i = 0; i < 4; ++i) v[2][i] = 0.0;
-        add_part(fp + 2 * N, T.transposed, v[2]);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        if (m == 2 && T.uni) break;
+        for (int i = 0; i < 4; ++i) v[i] = 0.0;
+        add_part(fp + m * N, T.transposed, v);
+        add_to(T.frame[m], v, qfb);
       }
-      for (int m = 0; m < 3; ++m)
-        for (int i = 0; i < 4; ++i) fa[T.frame[m]][i] += v[m][i];
     }
     if (in) {
       const double qf = 4.0 * 3.14159265358979323846 * G.qweight[b];
@@ -1060,7 +1067,7 @@ __global__ __launch_bounds__(256) void rts_reduce_v4(const char* __restrict__ ws
       if (FLUX) {
         const double sv[4] = {(double)s4.x, (double)s4.y, (double)s4.z, (double)s4.w};
         for (int m = 0; m < 3; ++m)
-          for (int i = 0; i < 4; ++i) f[m][i] += qf * (fa[m][i] + sv[i] * G.msum[m]);
+          for (int i = 0; i < 4; ++i) f[m][i] += qf * (sv[i] * G.msum[m]);
       }
     }
   }
