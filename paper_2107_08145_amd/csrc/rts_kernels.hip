@@ -1489,7 +1489,6 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
 #pragma unroll
     for (int i = 1; i < H - 1; ++i)
       if (i < top) do_row(i);
-    if (k + 1 < K) halo_issue(k + 1);
     lds_barrier();  // every thread has read the downwind state and the upwind plane
 #pragma unroll
     for (int i = 0; i < H; ++i)
@@ -1498,6 +1497,10 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
 #pragma unroll
         for (int m = 0; m < 3; ++m)
           lc[ST::qw(i, slot(s), m)] = (FULL || i < hr) ? nst[i][s][m] : Real(0);
+    // the neighbours publish their edge rows of this step at about the same
+    // time as this strip (two-row strips have no interior rows in between):
+    // their words are loaded last, so that they are fresh more often
+    if (k + 1 < K) halo_issue(k + 1);
   };
   StepIn s0, s1;
   load_step(0, s0);
