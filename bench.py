@@ -35,10 +35,11 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (published; needs packed FP32 instructions)
 PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector (published)
 # The sweep is bound by vector ALU issue (counters: VALU busy, HBM well below
-# its peak).  This build issues no packed FP32 instructions, so its FP32 ALU
+# its peak).  The kernels issue no packed FP32 instructions, so their FP32 ALU
 # peak is 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz = 78.6 TFLOP/s.
 PEAK_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-FLOPS_PER_UPDATE = 32          # algorithmic FP operations of one D-form update
+FLOPS_PER_UPDATE = 32          # algorithmic FP operations of one D-form update: three bilinear
+                               # interpolations 3 x 7, dtau 2, exp 1, c 2, the update 4, the sum 2
 
 
 def sweep_model(p, plan_sched_tasks, esz):
@@ -443,8 +444,8 @@ def main():
             print(f"{avg_us:12.1f} us  x{k:4d}  {tot_ms:10.3f} ms  {n[:110]}")
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the solver has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -55,7 +55,7 @@ extern "C" {
 /* status codes */
 #define RTS_OK 0
 #define RTS_E_ARG (-1)         /* invalid argument: null pointer, bad size, mu_z == 0, ... */
-#define RTS_E_UNSUPPORTED (-2) /* valid but not supported by this build (e.g. nx > 1024)  */
+#define RTS_E_UNSUPPORTED (-2) /* valid but not supported by the library (e.g. nx > 1024) */
 #define RTS_E_WORKSPACE (-3)   /* workspace null, misaligned or too small                  */
 #define RTS_E_HIP (-4)         /* a HIP runtime call failed                                */
 #define RTS_E_DEADLOCK (-5)    /* the sweep's neighbour wait timed out (device status)     */

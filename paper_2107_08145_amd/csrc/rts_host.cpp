@@ -1151,7 +1151,7 @@ const char* rts_status_string(int status) {
   switch (status) {
     case RTS_OK: return "RTS_OK";
     case RTS_E_ARG: return "RTS_E_ARG: invalid argument";
-    case RTS_E_UNSUPPORTED: return "RTS_E_UNSUPPORTED: not supported by this build";
+    case RTS_E_UNSUPPORTED: return "RTS_E_UNSUPPORTED: not supported by the library";
     case RTS_E_WORKSPACE: return "RTS_E_WORKSPACE: workspace null, misaligned or too small";
     case RTS_E_HIP: {
       static thread_local std::string s;
