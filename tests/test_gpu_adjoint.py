@@ -214,19 +214,21 @@ def test_autograd_chain_rule():
         assert np.abs(g - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("prec", [rts.RTS_FP64, rts.RTS_FP32])
-def test_solve_for_adjoint_and_adjoint_from_solve_are_bitwise(prec):
-    # the forward that keeps D gives rts_solve's outputs, and the adjoint that
-    # reads it gives rts_adjoint's gradients, bit for bit; a second call of
-    # the backward on the same kept forward gives them again
+@pytest.mark.parametrize("prec,flux", [(rts.RTS_FP64, False), (rts.RTS_FP32, False),
+                                       (rts.RTS_FP32, True)])
+def test_solve_for_adjoint_and_adjoint_from_solve_are_bitwise(prec, flux):
+    # the forward that keeps D gives rts_solve's outputs (with the flux vector
+    # too), and the adjoint that reads it gives rts_adjoint's gradients, bit
+    # for bit; a second call of the backward on the same kept forward gives
+    # them again
     import torch
     dt = np.float32 if prec == rts.RTS_FP32 else np.float64
     ps = [inputs.random_problem(30, 22, 15, seed=71, bands=2).astype(dt),
           inputs.random_problem(19, 27, 12, seed=72, bands=2).astype(dt)]
-    pl = rts.Plan(ps, prec)
+    pl = rts.Plan(ps, prec, flux=flux)
     ins = [pl.device_inputs(p) for p in ps]
-    outs_a = [pl.new_outputs(p) for p in ps]
-    outs_b = [pl.new_outputs(p) for p in ps]
+    outs_a = [pl.new_outputs(p, want_flux=flux) for p in ps]
+    outs_b = [pl.new_outputs(p, want_flux=flux) for p in ps]
     seeds, ga, gb = [], [], []
     for i, p in enumerate(ps):
         gQ, gJ, gI = _seeds(p, 80 + i)
@@ -237,7 +239,7 @@ def test_solve_for_adjoint_and_adjoint_from_solve_are_bitwise(prec):
                    torch.empty(p.S.shape, dtype=pl.dtype, device="cuda")))
         gb.append((torch.empty(p.S.shape, dtype=pl.dtype, device="cuda"),
                    torch.empty(p.S.shape, dtype=pl.dtype, device="cuda")))
-    print("case kept forward + adjoint", prec, flush=True)
+    print("case kept forward + adjoint", prec, flux, flush=True)
     pl.solve_into(ins, outs_a, batched=True)
     pl.adjoint_into(ins, seeds, ga)
     pl.solve_for_adjoint_into(ins, outs_b)
