@@ -290,3 +290,14 @@ def test_kept_forward_and_backward_argument_errors():
     tol = rts.Plan(p, rts.RTS_FP32, tol=1e-4)
     assert L.rts_solve_for_adjoint(tol.handle, 1, ctypes.byref(ci), ctypes.byref(co),
                                    ctypes.c_void_p(256), 1 << 40, None) == rts.RTS_E_UNSUPPORTED
+
+
+def test_bench_refuses_more_than_one_gpu_and_entry_points_exist():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+    sys.path.insert(0, ROOT)
+    import __graft_entry__ as g
+    assert callable(g.build) and callable(g.smoke)
