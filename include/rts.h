@@ -140,6 +140,10 @@ typedef struct {
                              the largest task (they must all be resident together) */
   int32_t order;          /* 0: longest sweeps first, 1: input order */
   int32_t use_graph;      /* 1: rts_solve_batched replays a captured hipGraph */
+  int32_t single_launch;  /* 0: one persistent sweep launch per workgroup width (the sweep
+                             tasks whose sweep planes round up to the same multiple of 64
+                             columns), widest first, in stream order; 1: every task in one
+                             launch as wide as the widest plane.  Results are identical. */
 } rts_schedule;
 
 /* Create a plan for `nbox` boxes (host only; validates every field; the

@@ -115,7 +115,7 @@ struct Plan {
   std::vector<Box> boxes;
   int prec = RTS_FP64;
   size_t esz = 8;
-  rts_schedule sched{4, 0, 0, 0};
+  rts_schedule sched{4, 0, 0, 0, 0};
   // layout (bytes)
   size_t off_flags = 0, off_tasks = 0, off_queue = 0, off_atasks = 0, off_rqueue = 0,
          off_data = 0, total = 0;
@@ -129,6 +129,18 @@ struct Plan {
   std::vector<int32_t> queue;
   int total_strips = 0;
   int max_strips = 1;  // strips of the largest task
+  // forward sweep launches: one per workgroup width (unless sched.single_launch),
+  // widest first; each owns a contiguous segment of the queue with its own tickets
+  struct WidthClass {
+    int width;       // padded columns that select the class (0: every task)
+    int threads;     // workgroup size: the padded columns of its widest task
+    int q0, nq;      // queue entries [q0, q0 + nq)
+    int strips;      // tickets of the launch
+    int max_strips;  // strips of its largest task
+    int blocks;      // resident workgroups per CU
+    bool uni;        // every task of the launch has four uniform slots
+  };
+  std::vector<WidthClass> wclasses;
   int threads = 64;
   bool uni = true;  // every task's four slots share f1, f2, ds and w
   // device-dependent state, filled on first use
@@ -282,26 +294,45 @@ void build_layout(Plan& P) {
     max_cols = std::max(max_cols, T.n_cols);
     P.tasks[t] = T;
   }
-  // queue order: longest sweeps (most plane steps x cells) first, stable
+  // Queue: tasks grouped by workgroup width (a workgroup has one thread per
+  // padded column of the widest task it may claim, so narrow tasks in a wide
+  // launch leave waves idle), widest first; inside a group the longest sweeps
+  // (most plane steps x cells) first, or input order; stable.
+  auto width_of = [&](const Task& T) {
+    return P.sched.single_launch ? 0 : (T.n_cols + 63) / 64 * 64;
+  };
   std::vector<int> q(P.tasks.size());
   for (size_t i = 0; i < q.size(); ++i) q[i] = (int)i;
-  if (P.sched.order == 0) {
-    std::stable_sort(q.begin(), q.end(), [&](int a, int b) {
-      const Task& A = P.tasks[a];
-      const Task& Bt = P.tasks[b];
-      const int64_t sa = (int64_t)A.laps * A.n_planes, sb = (int64_t)Bt.laps * Bt.n_planes;
-      if (sa != sb) return sa > sb;
-      return (int64_t)A.n_rows * A.n_cols > (int64_t)Bt.n_rows * Bt.n_cols;
-    });
-  }
+  std::stable_sort(q.begin(), q.end(), [&](int a, int b) {
+    const Task& A = P.tasks[a];
+    const Task& Bt = P.tasks[b];
+    if (width_of(A) != width_of(Bt)) return width_of(A) > width_of(Bt);
+    if (P.sched.order != 0) return false;
+    const int64_t sa = (int64_t)A.laps * A.n_planes, sb = (int64_t)Bt.laps * Bt.n_planes;
+    if (sa != sb) return sa > sb;
+    return (int64_t)A.n_rows * A.n_cols > (int64_t)Bt.n_rows * Bt.n_cols;
+  });
+  P.wclasses.clear();
   int ticket = 0;
-  for (int i : q) {
-    P.tasks[i].ticket0 = ticket;
+  P.total_strips = 0;
+  for (size_t k = 0; k < q.size(); ++k) {
+    Task& T = P.tasks[q[k]];
+    if (P.wclasses.empty() || P.wclasses.back().width != width_of(T)) {
+      P.wclasses.push_back(Plan::WidthClass{width_of(T), 64, (int)k, 0, 0, 1, 0, true});
+      ticket = 0;  // every launch counts its own tickets from 0
+    }
+    Plan::WidthClass& c = P.wclasses.back();
+    T.ticket0 = ticket;
     P.queue.push_back(ticket);
-    P.queue.push_back(i);
-    ticket += P.tasks[i].strips;
+    P.queue.push_back(q[k]);
+    ticket += T.strips;
+    P.total_strips += T.strips;
+    c.nq += 1;
+    c.strips = ticket;
+    c.max_strips = std::max(c.max_strips, (int)T.strips);
+    c.threads = std::max(c.threads, (T.n_cols + 63) / 64 * 64);
+    c.uni = c.uni && T.uni != 0;
   }
-  P.total_strips = ticket;
   P.max_strips = 1;
   for (const Task& T : P.tasks) P.max_strips = std::max(P.max_strips, (int)T.strips);
   P.threads = ((max_cols + 63) / 64) * 64;
@@ -468,17 +499,21 @@ int resident_blocks(const void* fn, int threads, size_t lds, int* out) {
 
 template <class Real, int H>
 int occupancy_h(Plan& P) {
-  // the smallest residency of the plain and the extended sweeps (flux partials,
-  // tolerance laps: more registers and a little static LDS)
-  const void* fns[3] = {P.uni ? sweep_fn<Real, H, true>() : sweep_fn<Real, H, false>(),
-                        P.uni ? sweep_fn_ext<Real, H, true>(1) : sweep_fn_ext<Real, H, false>(1),
-                        P.uni ? sweep_fn_ext<Real, H, true>(2) : sweep_fn_ext<Real, H, false>(2)};
+  // per launch, the smallest residency of the plain and the extended sweeps
+  // (flux partials, tolerance laps: more registers and a little static LDS)
   P.occupancy_blocks = 1 << 30;
-  for (const void* f : fns) {
-    int nb = 0;
-    int rc = resident_blocks(f, P.threads, sweep_lds_bytes<Real, H>(P.threads), &nb);
-    if (rc) return rc;
-    P.occupancy_blocks = std::min(P.occupancy_blocks, nb);
+  for (Plan::WidthClass& c : P.wclasses) {
+    const void* fns[3] = {c.uni ? sweep_fn<Real, H, true>() : sweep_fn<Real, H, false>(),
+                          c.uni ? sweep_fn_ext<Real, H, true>(1) : sweep_fn_ext<Real, H, false>(1),
+                          c.uni ? sweep_fn_ext<Real, H, true>(2) : sweep_fn_ext<Real, H, false>(2)};
+    c.blocks = 1 << 30;
+    for (const void* f : fns) {
+      int nb = 0;
+      int rc = resident_blocks(f, c.threads, sweep_lds_bytes<Real, H>(c.threads), &nb);
+      if (rc) return rc;
+      c.blocks = std::min(c.blocks, nb);
+    }
+    P.occupancy_blocks = std::min(P.occupancy_blocks, c.blocks);
   }
   return resident_blocks(reverse_fn<Real>(P.threads), reverse_threads(P.threads),
                          reverse_lds_bytes<Real>(P.threads), &P.rev_blocks);
@@ -496,19 +531,21 @@ int occupancy(Plan& P) {
 }
 
 template <class Real, bool UNI>
-hipError_t launch_sweep_u(Plan& P, const SweepArgs& a, int grid, hipStream_t st) {
+hipError_t launch_sweep_u(Plan& P, const SweepArgs& a, int grid, int threads, hipStream_t st) {
   switch (P.sched.rows_per_strip) {
-    case 2: return launch_sweep_h<Real, 2, UNI>(a, grid, P.threads, st);
-    case 4: return launch_sweep_h<Real, 4, UNI>(a, grid, P.threads, st);
-    case 6: if (sizeof(Real) == 4) return launch_sweep_h<float, 6, UNI>(a, grid, P.threads, st); break;
-    case 8: if (sizeof(Real) == 4) return launch_sweep_h<float, 8, UNI>(a, grid, P.threads, st); break;
+    case 2: return launch_sweep_h<Real, 2, UNI>(a, grid, threads, st);
+    case 4: return launch_sweep_h<Real, 4, UNI>(a, grid, threads, st);
+    case 6: if (sizeof(Real) == 4) return launch_sweep_h<float, 6, UNI>(a, grid, threads, st); break;
+    case 8: if (sizeof(Real) == 4) return launch_sweep_h<float, 8, UNI>(a, grid, threads, st); break;
   }
   return hipErrorInvalidValue;
 }
 
 template <class Real>
-hipError_t launch_sweep(Plan& P, const SweepArgs& a, int grid, hipStream_t st) {
-  return P.uni ? launch_sweep_u<Real, true>(P, a, grid, st) : launch_sweep_u<Real, false>(P, a, grid, st);
+hipError_t launch_sweep(Plan& P, const Plan::WidthClass& c, const SweepArgs& a, int grid,
+                        hipStream_t st) {
+  return c.uni ? launch_sweep_u<Real, true>(P, a, grid, c.threads, st)
+               : launch_sweep_u<Real, false>(P, a, grid, c.threads, st);
 }
 
 int ensure_pinned(Plan& P) {
@@ -569,9 +606,6 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
   std::memset(&a, 0, sizeof(a));
   a.ws = ws;
   a.tasks = reinterpret_cast<const Task*>(ws + P.off_tasks);
-  a.queue = reinterpret_cast<const int32_t*>(ws + P.off_queue);
-  a.ntasks = (int)P.tasks.size();
-  a.total_strips = P.total_strips;
   a.timeout_ticks = P.timeout_ticks;
   for (size_t b = 0; b < P.boxes.size(); ++b)
     a.box[b] = out ? BoxPtrs{in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top,
@@ -585,15 +619,24 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
   a.ext = a.flux ? 1 : 0;
   for (const Task& T : P.tasks)
     if (T.tol > 0) a.ext = 2;
-  // Every strip of a task must be resident together (neighbouring strips wait
-  // on each other), so the grid never drops below the largest task's strip
+  // One persistent launch per workgroup width, in stream order.  Every strip
+  // of a task must be resident together (neighbouring strips wait on each
+  // other), so a launch's grid never drops below its largest task's strip
   // count; tickets are claimed in order, hence with that many resident
   // workgroups the tasks being worked on always make progress.
-  int grid = P.occupancy_blocks * P.cus;
-  if (P.sched.max_workgroups > 0) grid = std::min(grid, std::max((int)P.sched.max_workgroups, P.max_strips));
-  grid = std::max(1, std::min(grid, P.total_strips));
   if (ev) RTS_HIP(hipEventRecord(ev[1], st));
-  RTS_HIP(launch_sweep<Real>(P, a, grid, st));
+  for (size_t k = 0; k < P.wclasses.size(); ++k) {
+    const Plan::WidthClass& c = P.wclasses[k];
+    a.queue = reinterpret_cast<const int32_t*>(ws + P.off_queue) + 2 * c.q0;
+    a.ntasks = c.nq;
+    a.total_strips = c.strips;
+    a.wclass = (int)k;
+    int grid = c.blocks * P.cus;
+    if (P.sched.max_workgroups > 0)
+      grid = std::min(grid, std::max((int)P.sched.max_workgroups, c.max_strips));
+    grid = std::max(1, std::min(grid, c.strips));
+    RTS_HIP(launch_sweep<Real>(P, c, a, grid, st));
+  }
   if (ev) RTS_HIP(hipEventRecord(ev[2], st));
   if (!out) return RTS_OK;
   for (size_t b = 0; b < P.boxes.size(); ++b) {
@@ -677,10 +720,12 @@ int prepare(Plan* P) {
   if (P->occupancy_blocks == 0) {
     rc = P->prec == RTS_FP32 ? occupancy<float>(*P) : occupancy<double>(*P);
     if (rc) return rc;
-    if (P->occupancy_blocks < 1 || P->occupancy_blocks * P->cus < P->max_strips) {
-      g_last_hip = "the strips of one sweep task cannot all be resident; use more rows per strip";
-      return RTS_E_UNSUPPORTED;
-    }
+    for (const Plan::WidthClass& c : P->wclasses)
+      if (c.blocks < 1 || c.blocks * P->cus < c.max_strips) {
+        P->occupancy_blocks = 0;
+        g_last_hip = "the strips of one sweep task cannot all be resident; use more rows per strip";
+        return RTS_E_UNSUPPORTED;
+      }
   }
   return ensure_pinned(*P);
 }
@@ -753,7 +798,8 @@ std::vector<rts_schedule> tune_candidates(const Plan& P) {
   const int* hs = P.prec == RTS_FP32 ? hs32 : hs64;
   const int nh = P.prec == RTS_FP32 ? 4 : 2;
   for (int i = 0; i < nh; ++i)
-    for (int order = 0; order < 2; ++order) c.push_back(rts_schedule{hs[i], 0, order, P.sched.use_graph});
+    for (int order = 0; order < 2; ++order)
+      c.push_back(rts_schedule{hs[i], 0, order, P.sched.use_graph, P.sched.single_launch});
   return c;
 }
 
@@ -1097,7 +1143,9 @@ int rts_plan_set_schedule(void* plan, const rts_schedule* s) {
   Plan* P = static_cast<Plan*>(plan);
   const int h = s->rows_per_strip;
   const bool ok = P->prec == RTS_FP32 ? (h == 2 || h == 4 || h == 6 || h == 8) : (h == 2 || h == 4);
-  if (!ok || s->max_workgroups < 0 || (s->order != 0 && s->order != 1)) return RTS_E_ARG;
+  if (!ok || s->max_workgroups < 0 || (s->order != 0 && s->order != 1) ||
+      (s->single_launch != 0 && s->single_launch != 1))
+    return RTS_E_ARG;
   try {
     set_sched(P, *s);
   } catch (...) {

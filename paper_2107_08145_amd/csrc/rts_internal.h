@@ -119,13 +119,18 @@ struct BoxGeo {
   double dx, dy, dz;       // grid spacing (flux divergence)
 };
 
+// Forward sweep launches of one call: one per workgroup width (padded columns).
+constexpr int kMaxWidths = kMaxCols / 64;
+
 // Workspace header (first 256 bytes).
 struct WsHeader {
-  int32_t status;          // 0, or 1 after a neighbour-wait timeout
-  int32_t ticket;          // work-queue counter of the forward sweep
-  int32_t ticket_rev;      // work-queue counter of the reverse sweep
-  int32_t pad[61];
+  int32_t status;               // 0, or 1 after a neighbour-wait timeout
+  int32_t ticket_rev;           // work-queue counter of the reverse sweep
+  int32_t pad0[2];
+  int32_t ticket[kMaxWidths];   // work-queue counter of each forward sweep launch
+  int32_t pad[44];
 };
+static_assert(sizeof(WsHeader) == 256, "workspace header is 256 bytes");
 
 struct SweepArgs {
   char* ws;                // workspace base
@@ -137,7 +142,7 @@ struct SweepArgs {
   int32_t store_d;         // also store D of every plane (forward pass of the adjoint)
   int32_t flux;            // also write the flux partials sum_r w_r mu_r D_r
   int32_t ext;             // launch the extended sweep (flux partials and/or tolerance laps)
-  int32_t pad;
+  int32_t wclass;          // ticket counter of this launch (WsHeader::ticket)
   BoxPtrs box[kMaxBoxes];
 };
 

@@ -792,7 +792,7 @@ __global__ __launch_bounds__(1024) void rts_sweep(SweepArgs A) {
   __shared__ int sh_ticket;
   WsHeader* hdr = reinterpret_cast<WsHeader*>(A.ws);
   for (;;) {
-    if (threadIdx.x == 0) sh_ticket = atomicAdd(&hdr->ticket, 1);
+    if (threadIdx.x == 0) sh_ticket = atomicAdd(&hdr->ticket[A.wclass], 1);
     __syncthreads();
     const int tk = __builtin_amdgcn_readfirstlane(sh_ticket);
     __syncthreads();

@@ -86,7 +86,8 @@ class Grads(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("rows_per_strip", ctypes.c_int32), ("max_workgroups", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("single_launch", ctypes.c_int32)]
 
 
 class RTSError(RuntimeError):

@@ -109,6 +109,11 @@ def test_workspace_and_schedule():
     assert pl.schedule()["rows_per_strip"] == 8
     with pytest.raises(rts.RTSError):
         pl.set_schedule(rows_per_strip=3)
+    assert s["single_launch"] == 0            # one sweep launch per workgroup width
+    pl.set_schedule(single_launch=1)
+    assert pl.schedule()["single_launch"] == 1
+    with pytest.raises(rts.RTSError):
+        pl.set_schedule(single_launch=2)
     p64 = rts.Plan(p, rts.RTS_FP64)
     with pytest.raises(rts.RTSError):
         p64.set_schedule(rows_per_strip=8)  # fp64 strips hold at most 4 rows

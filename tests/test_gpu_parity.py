@@ -167,6 +167,47 @@ def test_batched_equals_single():
                     assert np.array_equal(a.double().cpu().numpy(), b), (use_graph, rep)
 
 
+@pytest.mark.parametrize("extra", ["plain", "flux", "tol"])
+def test_width_launches_equal_single_launch(extra):
+    # sweep planes of 64 to 256 padded columns (nx != ny: one box has two
+    # widths): one launch per width and one launch at the widest width give
+    # the same bits, eagerly and in graph replays, and match the oracle
+    import torch
+    ps = [_rand_problem(130, 40, 20, seed=51, bands=2), _rand_problem(70, 200, 15, seed=52),
+          _rand_problem(20, 17, 9, seed=53, bands=3)]
+    if extra == "tol":
+        ps = [inputs.random_problem(p.nx, p.ny, p.nz, seed=60 + i, lo=0.02, hi=0.5, n_iter=6,
+                                    bands=p.nbands) for i, p in enumerate(ps)]
+    ps = [p.astype(np.float32) for p in ps]
+    flux = extra == "flux"
+    tol = 1e30 if extra == "tol" else 0.0     # the first sweep meets it: one sweep each
+    pl = rts.Plan(ps, rts.RTS_FP32, flux=flux, tol=tol)
+    ins = [pl.device_inputs(p) for p in ps]
+    res = {}
+    for single in (0, 1):
+        for use_graph in (0, 1):
+            pl.set_schedule(single_launch=single, use_graph=use_graph)
+            outs = [pl.new_outputs(p, want_flux=flux) for p in ps]
+            for rep in range(2):
+                print("case width launches", extra, single, use_graph, rep, flush=True)
+                pl.solve_into(ins, outs, batched=True)
+                pl.check_status()
+                torch.cuda.synchronize()
+                res[(single, use_graph, rep)] = [[t.double().cpu().numpy() for t in o]
+                                                 for o in outs]
+    first = res[(0, 0, 0)]
+    for k, got in res.items():
+        for g, f in zip(got, first):
+            for a, b in zip(g, f):
+                assert np.array_equal(a, b), k
+    for p, g in zip(ps, first):
+        q = p.astype(np.float64)
+        if extra == "tol":
+            q.n_iter = 1
+        ref = oracle.flux(q, threads=8) if flux else oracle.solve(q, threads=8)
+        _check32(p, g[:3], ref[:3])
+
+
 def test_autotune_keeps_results():
     p = _rand_problem(70, 40, 37, seed=4).astype(np.float32)
     ref = rts.solve(p, rts.RTS_FP32)
