@@ -124,7 +124,7 @@ struct Plan {
   size_t off_grads = 0, off_grads_end = 0, total_adj = 0;
   std::vector<AdjTask> atasks;
   std::vector<int32_t> rqueue;
-  int rev_total_strips = 0, rev_max_strips = 1, rev_blocks = 0;
+  int rev_blocks = 0;
   std::vector<Task> tasks;
   std::vector<int32_t> queue;
   int total_strips = 0;
@@ -141,6 +141,7 @@ struct Plan {
     bool uni;        // every task of the launch has four uniform slots
   };
   std::vector<WidthClass> wclasses;
+  std::vector<WidthClass> rclasses;  // the same for the reverse sweep (threads: padded columns)
   int threads = 64;
   bool uni = true;  // every task's four slots share f1, f2, ds and w
   // device-dependent state, filled on first use
@@ -417,8 +418,9 @@ void build_layout(Plan& P) {
   }
   for (size_t t = 0; t < P.tasks.size(); ++t) {
     const Box& B = P.boxes[P.tasks[t].box];
-    // one partial per thread of a column of the reverse sweep
-    const int np = reverse_parts(P.threads);
+    // one partial per thread of a column of the task's reverse launch
+    const int np = reverse_parts(P.sched.single_launch ? P.threads
+                                                       : (P.tasks[t].n_cols + 63) / 64 * 64);
     P.atasks[t].nparts = np;
     P.atasks[t].gs_off = (int64_t)(off / esz);
     off = align_up(off + np * (size_t)B.N * esz);
@@ -437,20 +439,34 @@ void build_layout(Plan& P) {
     const Box& B = P.boxes[T.box];
     P.atasks[t].seed_off = (T.transposed ? B.seedT_off : B.seed_off) + (int64_t)T.band * B.N;
   }
-  // reverse queue: longest sweeps first
+  // reverse queue: grouped by width as the forward one, longest sweeps first
+  auto rwidth = [&](int t) {
+    return P.sched.single_launch ? 0 : (P.tasks[t].n_cols + 63) / 64 * 64;
+  };
   std::vector<int> rq(P.tasks.size());
   for (size_t i = 0; i < rq.size(); ++i) rq[i] = (int)i;
   std::stable_sort(rq.begin(), rq.end(), [&](int a, int b) {
+    if (rwidth(a) != rwidth(b)) return rwidth(a) > rwidth(b);
     return P.tasks[a].n_unrolled - P.atasks[a].u_init > P.tasks[b].n_unrolled - P.atasks[b].u_init;
   });
   P.rqueue.clear();
-  P.rev_total_strips = 0;
-  P.rev_max_strips = 1;
-  for (int i : rq) {
-    P.rqueue.push_back(P.rev_total_strips);
+  P.rclasses.clear();
+  int rticket = 0;
+  for (size_t k = 0; k < rq.size(); ++k) {
+    const int i = rq[k];
+    if (P.rclasses.empty() || P.rclasses.back().width != rwidth(i)) {
+      P.rclasses.push_back(Plan::WidthClass{rwidth(i), 64, (int)k, 0, 0, 1, 0, true});
+      rticket = 0;
+    }
+    Plan::WidthClass& c = P.rclasses.back();
+    P.rqueue.push_back(rticket);
     P.rqueue.push_back(i);
-    P.rev_total_strips += P.atasks[i].strips;
-    P.rev_max_strips = std::max(P.rev_max_strips, (int)P.atasks[i].strips);
+    rticket += P.atasks[i].strips;
+    c.nq += 1;
+    c.strips = rticket;
+    c.max_strips = std::max(c.max_strips, (int)P.atasks[i].strips);
+    c.threads = P.sched.single_launch ? P.threads
+                                      : std::max(c.threads, (P.tasks[i].n_cols + 63) / 64 * 64);
   }
   P.rev_blocks = 0;
   P.uploaded_ws = nullptr;
@@ -515,8 +531,14 @@ int occupancy_h(Plan& P) {
     }
     P.occupancy_blocks = std::min(P.occupancy_blocks, c.blocks);
   }
-  return resident_blocks(reverse_fn<Real>(P.threads), reverse_threads(P.threads),
-                         reverse_lds_bytes<Real>(P.threads), &P.rev_blocks);
+  P.rev_blocks = 1 << 30;
+  for (Plan::WidthClass& c : P.rclasses) {
+    int rc = resident_blocks(reverse_fn<Real>(c.threads), reverse_threads(c.threads),
+                             reverse_lds_bytes<Real>(c.threads), &c.blocks);
+    if (rc) return rc;
+    P.rev_blocks = std::min(P.rev_blocks, c.blocks);
+  }
+  return RTS_OK;
 }
 
 template <class Real>
@@ -649,7 +671,7 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
 }
 
 // Enqueue one adjoint: the forward sweep storing D, the seeds, one reverse
-// launch per unrolled plane (every task of every box), the gradient reduce.
+// launch per workgroup width (every task of every box), the gradient reduce.
 // Without run_forward the stored D of an earlier rts_solve_for_adjoint on this
 // workspace is used; only the header (reverse ticket, status) is cleared.
 template <class Real>
@@ -680,16 +702,21 @@ int enqueue_adjoint(Plan& P, const rts_inputs* in, const rts_seeds* g, const rts
   a.ws = ws;
   a.tasks = reinterpret_cast<const Task*>(ws + P.off_tasks);
   a.atasks = reinterpret_cast<const AdjTask*>(ws + P.off_atasks);
-  a.queue = reinterpret_cast<const int32_t*>(ws + P.off_rqueue);
-  a.ntasks = (int)P.atasks.size();
-  a.total_strips = P.rev_total_strips;
   a.timeout_ticks = P.timeout_ticks;
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     a.gItop[b] = g[b].gItop;
     a.S[b] = in[b].S;
   }
-  const int grid = std::max(1, std::min(P.rev_blocks * P.cus, P.rev_total_strips));
-  RTS_HIP(launch_reverse<Real>(a, grid, P.threads, st));
+  // one persistent reverse launch per width, in stream order
+  for (size_t k = 0; k < P.rclasses.size(); ++k) {
+    const Plan::WidthClass& c = P.rclasses[k];
+    a.queue = reinterpret_cast<const int32_t*>(ws + P.off_rqueue) + 2 * c.q0;
+    a.ntasks = c.nq;
+    a.total_strips = c.strips;
+    a.wclass = (int)k;
+    const int grid = std::max(1, std::min(c.blocks * P.cus, c.strips));
+    RTS_HIP(launch_reverse<Real>(a, grid, c.threads, st));
+  }
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     const BoxGeo G = box_geo(P, b);
     RTS_HIP(launch_adj_reduce<Real>(ws, a.tasks, a.atasks, G, g[b].gQ, g[b].gJ, g[b].gItop,
@@ -1049,10 +1076,11 @@ int adjoint_checks(Plan* P, int32_t nbox, const rts_inputs* in, void* ws, size_t
     return RTS_E_WORKSPACE;
   int rc = prepare(P);
   if (rc) return rc;
-  if (P->rev_blocks < 1 || P->rev_blocks * P->cus < P->rev_max_strips) {
-    g_last_hip = "the strips of one reverse sweep task cannot all be resident";
-    return RTS_E_UNSUPPORTED;
-  }
+  for (const Plan::WidthClass& c : P->rclasses)
+    if (c.blocks < 1 || c.blocks * P->cus < c.max_strips) {
+      g_last_hip = "the strips of one reverse sweep task cannot all be resident";
+      return RTS_E_UNSUPPORTED;
+    }
   return RTS_OK;
 }
 }  // namespace

@@ -74,7 +74,7 @@ struct AdjTask {
   int32_t task;       // index into the Task table (AdjTask i belongs to Task i)
   int32_t u_init;     // last unrolled plane of the reverse: -1 (ghost plane) or 0
   int32_t strips;     // strips of kRevRows rows
-  int32_t nparts;     // gradient partials per quantity (threads per column of the reverse sweep)
+  int32_t nparts;     // gradient partials per quantity (threads per column of its reverse launch)
   int64_t xbuf_off;   // 64-bit word offset of the exchange buffer [strip][parity][edge][2][3][col][words]
   int64_t gs_off;     // Real offset of this task's dL/dS partial (task array layout)
   int64_t gc_off;     // Real offset of this task's dL/dchi partial (task array layout)
@@ -89,6 +89,8 @@ struct RevArgs {
   int32_t ntasks;
   int32_t total_strips;
   int64_t timeout_ticks;
+  int32_t wclass;                // ticket counter of this launch (WsHeader::ticket_rev)
+  int32_t pad;
   const void* gItop[kMaxBoxes];  // per box, [nbands][n_up][ny][nx] or null
   const void* S[kMaxBoxes];      // per box, [nbands][N]
 };
@@ -124,11 +126,11 @@ constexpr int kMaxWidths = kMaxCols / 64;
 
 // Workspace header (first 256 bytes).
 struct WsHeader {
-  int32_t status;               // 0, or 1 after a neighbour-wait timeout
-  int32_t ticket_rev;           // work-queue counter of the reverse sweep
-  int32_t pad0[2];
-  int32_t ticket[kMaxWidths];   // work-queue counter of each forward sweep launch
-  int32_t pad[44];
+  int32_t status;                 // 0, or 1 after a neighbour-wait timeout
+  int32_t pad0[3];
+  int32_t ticket[kMaxWidths];     // work-queue counter of each forward sweep launch
+  int32_t ticket_rev[kMaxWidths]; // work-queue counter of each reverse sweep launch
+  int32_t pad[28];
 };
 static_assert(sizeof(WsHeader) == 256, "workspace header is 256 bytes");
 

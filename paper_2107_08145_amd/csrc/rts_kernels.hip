@@ -1520,7 +1520,7 @@ void rts_reverse(RevArgs A) {
   WsHeader* hdr = reinterpret_cast<WsHeader*>(A.ws);
   constexpr int H = kRevRows;
   for (;;) {
-    if (threadIdx.x == 0) sh_ticket = atomicAdd(&hdr->ticket_rev, 1);
+    if (threadIdx.x == 0) sh_ticket = atomicAdd(&hdr->ticket_rev[A.wclass], 1);
     __syncthreads();
     const int tk = __builtin_amdgcn_readfirstlane(sh_ticket);
     __syncthreads();

@@ -193,6 +193,43 @@ def test_adjoint_batched_equals_single():
                 assert np.array_equal(a.double().cpu().numpy(), b), rep
 
 
+def test_adjoint_width_launches():
+    # planes of 64 to 320 padded columns: with one reverse launch per width
+    # a box's gradients are bitwise those of its own plan; one launch at the
+    # widest width (single_launch) sums the slots of the narrow tasks in
+    # another order and meets the same bar against the oracle
+    import torch
+    ps = [inputs.random_problem(300, 20, 9, seed=71, bands=2).astype(np.float32),
+          inputs.random_problem(40, 70, 12, seed=72).astype(np.float32)]
+    pl = rts.Plan(ps, rts.RTS_FP32)
+    ins = [pl.device_inputs(p) for p in ps]
+    seeds, grads, host, refs = [], [], [], []
+    for i, p in enumerate(ps):
+        gQ, gJ, gI = _seeds(p, 80 + i)
+        gJ, gI = gJ.astype(np.float32), gI.astype(np.float32)
+        host.append((gQ, gJ, gI))
+        refs.append(oracle.adjoint(p.astype(np.float64), gQ, gJ.astype(np.float64),
+                                   gI.astype(np.float64), threads=8))
+        seeds.append((torch.as_tensor(gQ, device="cuda"), torch.as_tensor(gJ, device="cuda"),
+                      torch.as_tensor(gI, device="cuda")))
+        grads.append((torch.empty(p.S.shape, dtype=torch.float32, device="cuda"),
+                      torch.empty(p.S.shape, dtype=torch.float32, device="cuda")))
+    for single in (0, 1):
+        pl.set_schedule(single_launch=single)
+        print("case adjoint width launches", single, flush=True)
+        pl.adjoint_into(ins, seeds, grads)
+        pl.check_status()
+        torch.cuda.synchronize()
+        for p, h, g, ref in zip(ps, host, grads, refs):
+            got = [t.double().cpu().numpy() for t in g]
+            e = _cmp(got, ref, 2e-4)
+            print(f"adjoint width launches single={single} {p.nx}x{p.ny}: {e:.2e}")
+            if single == 0:
+                alone = rts.adjoint(p, rts.RTS_FP32, *h)
+                for a, b in zip(got, alone):
+                    assert np.array_equal(a, b)
+
+
 def test_autograd_chain_rule():
     import torch
     from paper_2107_08145_amd.autograd import rts_apply
