@@ -143,7 +143,10 @@ typedef struct {
   int32_t single_launch;  /* 0: one persistent sweep launch per workgroup width (the sweep
                              tasks whose sweep planes round up to the same multiple of 64
                              columns), widest first, in stream order; 1: every task in one
-                             launch as wide as the widest plane.  Results are identical. */
+                             launch as wide as the widest plane.  Forward results are
+                             identical; adjoint gradients differ by rounding only (a task's
+                             slot contributions are summed over as many partials as its
+                             reverse launch has threads per column). */
 } rts_schedule;
 
 /* Create a plan for `nbox` boxes (host only; validates every field; the
@@ -205,7 +208,8 @@ int rts_adjoint_from_solve(void* plan, int32_t nbox, const rts_inputs* in, const
 
 /* Autotuner: runs the forward solve of all boxes (as rts_solve_batched, not
  * replayed from a graph) under every candidate schedule -- rows per strip
- * 2/4/6/8 (FP32) or 2/4 (FP64), queue order 0/1 -- `reps` timed calls each
+ * 2/4/6/8 (FP32) or 2/4 (FP64), queue order 0/1, and single_launch 0/1 when
+ * the sweep planes of the plan have more than one padded width -- `reps` timed calls each
  * after one warm-up call, timed with HIP events on `hip_stream`, and keeps
  * the fastest in the plan (written to *chosen if not NULL).  Candidates whose
  * workspace exceeds ws_bytes, or whose strips cannot all be resident, are

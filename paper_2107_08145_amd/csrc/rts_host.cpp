@@ -818,15 +818,21 @@ int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
 }
 
 // Schedules the autotuner tries: every strip height of the precision, both
-// queue orders.
+// queue orders and, when the sweep planes have more than one padded width,
+// both launch forms (one launch per width, one at the widest).
 std::vector<rts_schedule> tune_candidates(const Plan& P) {
   std::vector<rts_schedule> c;
   const int hs32[] = {2, 4, 6, 8}, hs64[] = {2, 4};
   const int* hs = P.prec == RTS_FP32 ? hs32 : hs64;
   const int nh = P.prec == RTS_FP32 ? 4 : 2;
-  for (int i = 0; i < nh; ++i)
-    for (int order = 0; order < 2; ++order)
-      c.push_back(rts_schedule{hs[i], 0, order, P.sched.use_graph, P.sched.single_launch});
+  bool mixed = false;
+  for (const Task& T : P.tasks)
+    mixed = mixed || (T.n_cols + 63) / 64 != (P.tasks[0].n_cols + 63) / 64;
+  const int sl0 = mixed ? 0 : P.sched.single_launch, sl1 = mixed ? 1 : P.sched.single_launch;
+  for (int sl = sl0; sl <= sl1; ++sl)
+    for (int i = 0; i < nh; ++i)
+      for (int order = 0; order < 2; ++order)
+        c.push_back(rts_schedule{hs[i], 0, order, P.sched.use_graph, sl});
   return c;
 }
 

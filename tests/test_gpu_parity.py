@@ -217,6 +217,7 @@ def test_autotune_keeps_results():
     chosen = pl.autotune([ins], [outs], reps=2)
     print("autotune chose", chosen, flush=True)
     assert chosen["rows_per_strip"] in (2, 4, 6, 8) and chosen["order"] in (0, 1)
+    assert chosen["single_launch"] in (0, 1)    # planes of 128 and 64 columns: both tried
     assert pl.schedule() == chosen
     got = rts.solve(p, rts.RTS_FP32, plan=pl)
     for a, b in zip(ref, got):
