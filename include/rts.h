@@ -229,8 +229,9 @@ int rts_plan_get_schedule(void* plan, rts_schedule* s);
 int rts_plan_set_schedule(void* plan, const rts_schedule* s);
 
 /* Device-side timing.  While enabled, each rts_solve / rts_solve_batched call
- * (not graph replays) records HIP events on its stream around the sweep kernel
- * and around the whole call (up to 512 calls).  rts_plan_last_timing waits for
+ * (not graph replays) records HIP events on its stream around the sweep
+ * launches (one per workgroup width, see rts_schedule.single_launch) and
+ * around the whole call (up to 512 calls).  rts_plan_last_timing waits for
  * the last recorded call and returns the mean sweep-kernel and whole-call
  * durations in ms over the calls recorded since timing was (re)enabled, or -1
  * if none.  Enabling resets the record. */

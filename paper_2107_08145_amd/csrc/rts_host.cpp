@@ -646,6 +646,7 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
   // other), so a launch's grid never drops below its largest task's strip
   // count; tickets are claimed in order, hence with that many resident
   // workgroups the tasks being worked on always make progress.
+  if (P.wclasses.size() > (size_t)kMaxWidths) return RTS_E_UNSUPPORTED;  // (widths <= kMaxCols)
   if (ev) RTS_HIP(hipEventRecord(ev[1], st));
   for (size_t k = 0; k < P.wclasses.size(); ++k) {
     const Plan::WidthClass& c = P.wclasses[k];
@@ -708,6 +709,7 @@ int enqueue_adjoint(Plan& P, const rts_inputs* in, const rts_seeds* g, const rts
     a.S[b] = in[b].S;
   }
   // one persistent reverse launch per width, in stream order
+  if (P.rclasses.size() > (size_t)kMaxWidths) return RTS_E_UNSUPPORTED;
   for (size_t k = 0; k < P.rclasses.size(); ++k) {
     const Plan::WidthClass& c = P.rclasses[k];
     a.queue = reinterpret_cast<const int32_t*>(ws + P.off_rqueue) + 2 * c.q0;
