@@ -49,6 +49,31 @@ def test_full_size_fp32(name):
     assert eq <= 1e-5 and ej <= 2e-6 and ei <= 2e-6
 
 
+def test_full_size_boxes6_batched_fp32():
+    # the six uneven boxes in one autotuned, graph-replayed rts_solve_batched
+    # call (one persistent sweep launch per workgroup width), box by box
+    import torch
+    ps = [p.astype(np.float32) for p in inputs.workload("boxes6")]
+    pl = rts.Plan(ps, rts.RTS_FP32)
+    ins = [pl.device_inputs(p) for p in ps]
+    outs = [pl.new_outputs(p) for p in ps]
+    pl.autotune(ins, outs, reps=1)
+    pl.set_schedule(use_graph=1)
+    for rep in range(2):
+        print("case full size boxes6 batched", rep, pl.schedule(), flush=True)
+        pl.solve_into(ins, outs, batched=True)
+        pl.check_status()
+        torch.cuda.synchronize()
+    got = [tuple(t.double().cpu().numpy() for t in o) for o in outs]
+    del outs, ins, pl
+    torch.cuda.empty_cache()
+    for p, g in zip(ps, got):
+        ref = oracle.solve(p.astype(np.float64), threads=THREADS)
+        eq, ej, ei = _errs(g, ref)
+        print(f"boxes6 {p.nx}x{p.ny}x{p.nz}: Q {eq:.2e} J {ej:.2e} I_top {ei:.2e}", flush=True)
+        assert eq <= 1e-5 and ej <= 2e-6 and ei <= 2e-6
+
+
 def test_full_size_grey288_fp64():
     p = inputs.workload("grey288")
     print("case full size fp64 grey288", flush=True)
