@@ -343,6 +343,14 @@ def bench_batched(args):
     ms = _time_calls(lambda: plan.solve_into(ins, outs, batched=True), args.steps, args.warmup)
     plan.check_status()
     print(f"# batched forward {ms:.3f} ms", file=sys.stderr, flush=True)
+    # the other launch form at the same strip height, for comparison
+    chosen = plan.schedule()
+    plan.set_schedule(single_launch=1 - chosen["single_launch"])
+    other_ms = _time_calls(lambda: plan.solve_into(ins, outs, batched=True), args.steps, 1)
+    plan.check_status()
+    plan.set_schedule(**chosen)
+    print(f"# with single_launch={1 - chosen['single_launch']}: {other_ms:.3f} ms", file=sys.stderr,
+          flush=True)
     nominal = sum(p.ncells * p.nrays * p.nbands for p in ps)
     out = {"metric": "cell-ray-band updates/sec (six uneven boxes, 4-band+grey, 24 rays, batched)",
            "value": nominal / (ms * 1e-3), "unit": "cell-ray-band updates/s", "n_gpus": 1,
@@ -350,7 +358,9 @@ def bench_batched(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32" if prec == rts.RTS_FP32 else "f64", "data": "synthetic",
            "config": {"workload": "boxes6: " + ", ".join(f"{p.nx}x{p.ny}x{p.nz}" for p in ps),
-                      "schedule": plan.schedule()}}
+                      "schedule": chosen},
+           "other_launch_form": {"single_launch": 1 - chosen["single_launch"],
+                                 "ms_per_step": round(other_ms, 4)}}
     if args.adjoint:
         # one rts_adjoint call over the boxes whose reverse sweep fits: the
         # 576^2 planes of the first box need more LDS per strip than a CU has
