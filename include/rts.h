@@ -165,9 +165,10 @@ int rts_solve(void* plan, const rts_inputs* in, const rts_outputs* out, void* ws
               size_t ws_bytes, void* hip_stream);
 
 /* Forward solve of all `nbox` boxes (nbox must equal the plan's box count):
- * every band, ray and box in one persistent sweep launch fed by a device-side
- * work queue; captured once into a hipGraph and replayed when the schedule's
- * use_graph is set. */
+ * every band, ray and box in one call, the sweep tasks of each workgroup width
+ * in one persistent launch fed by a device-side work queue (one launch in all
+ * with rts_schedule.single_launch); captured once into a hipGraph and replayed
+ * when the schedule's use_graph is set. */
 int rts_solve_batched(void* plan, int32_t nbox, const rts_inputs* in, const rts_outputs* out,
                       void* ws, size_t ws_bytes, void* hip_stream);
 
@@ -179,8 +180,8 @@ int rts_solve_batched(void* plan, int32_t nbox, const rts_inputs* in, const rts_
  * "Summary of the Radiation Transport Solver" section as implemented by
  * rts_solve): the call re-runs the forward sweep, storing D of every plane
  * and lap in the workspace, then sweeps the transposed recursion downwind to
- * upwind in one persistent launch (strips of two rows exchanging edge rows,
- * like the forward sweep), recomputing the exp and interpolation weights from
+ * upwind in one persistent launch per workgroup width (strips of two rows
+ * exchanging edge rows, like the forward sweep), recomputing the exp and interpolation weights from
  * the stored upwind D.  Returns RTS_E_UNSUPPORTED if a box has tol > 0, or if the strips of one task
  * cannot all be resident.  Seeds may be NULL (zero).  dS and dchi are
  * overwritten; chi = kappa * rho, so dL/dkappa_b = rho dL/dchi_b and
