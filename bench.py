@@ -123,14 +123,20 @@ def _pmc_rows(d, counter):
     return rows
 
 
-def trace_summary(d):
-    """Per-kernel calls and mean duration from a rocprofv3 --kernel-trace database."""
+def trace_summary(d, by_workgroup=False):
+    """Per-kernel calls and mean duration from a rocprofv3 --kernel-trace database
+    (per kernel and workgroup size with by_workgroup)."""
     import sqlite3
     out = []
     for f in _db_files(d):
         c = sqlite3.connect(f)
-        q = ("select name, count(*), avg(duration), sum(duration) from kernels "
-             "group by name order by sum(duration) desc")
+        if by_workgroup:
+            q = ("select name || ' [workgroup ' || workgroup_x || ']', count(*), avg(duration), "
+                 "sum(duration) from kernels group by name, workgroup_x "
+                 "order by sum(duration) desc")
+        else:
+            q = ("select name, count(*), avg(duration), sum(duration) from kernels "
+                 "group by name order by sum(duration) desc")
         out += [(n, k, a / 1e3, s / 1e6) for n, k, a, s in c.execute(q).fetchall()]
     return out
 
@@ -340,17 +346,22 @@ def bench_batched(args):
     else:
         plan.autotune(ins, outs, reps=1)
     plan.set_schedule(use_graph=1)
+    if args.launch_form != "auto":
+        plan.set_schedule(single_launch=int(args.launch_form == "single"))
     ms = _time_calls(lambda: plan.solve_into(ins, outs, batched=True), args.steps, args.warmup)
     plan.check_status()
     print(f"# batched forward {ms:.3f} ms", file=sys.stderr, flush=True)
-    # the other launch form at the same strip height, for comparison
     chosen = plan.schedule()
-    plan.set_schedule(single_launch=1 - chosen["single_launch"])
-    other_ms = _time_calls(lambda: plan.solve_into(ins, outs, batched=True), args.steps, 1)
-    plan.check_status()
-    plan.set_schedule(**chosen)
-    print(f"# with single_launch={1 - chosen['single_launch']}: {other_ms:.3f} ms", file=sys.stderr,
-          flush=True)
+    other = None
+    if args.launch_form == "auto":
+        # the other launch form at the same strip height, for comparison
+        plan.set_schedule(single_launch=1 - chosen["single_launch"])
+        other_ms = _time_calls(lambda: plan.solve_into(ins, outs, batched=True), args.steps, 1)
+        plan.check_status()
+        plan.set_schedule(**chosen)
+        other = {"single_launch": 1 - chosen["single_launch"], "ms_per_step": round(other_ms, 4)}
+        print(f"# with single_launch={other['single_launch']}: {other_ms:.3f} ms",
+              file=sys.stderr, flush=True)
     nominal = sum(p.ncells * p.nrays * p.nbands for p in ps)
     out = {"metric": "cell-ray-band updates/sec (six uneven boxes, 4-band+grey, 24 rays, batched)",
            "value": nominal / (ms * 1e-3), "unit": "cell-ray-band updates/s", "n_gpus": 1,
@@ -358,9 +369,9 @@ def bench_batched(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32" if prec == rts.RTS_FP32 else "f64", "data": "synthetic",
            "config": {"workload": "boxes6: " + ", ".join(f"{p.nx}x{p.ny}x{p.nz}" for p in ps),
-                      "schedule": chosen},
-           "other_launch_form": {"single_launch": 1 - chosen["single_launch"],
-                                 "ms_per_step": round(other_ms, 4)}}
+                      "schedule": chosen}}
+    if other:
+        out["other_launch_form"] = other
     if args.adjoint:
         # one rts_adjoint call over the boxes whose reverse sweep fits: the
         # 576^2 planes of the first box need more LDS per strip than a CU has
@@ -440,6 +451,11 @@ def main():
                     help="run only a plain 1 GiB device copy (scales rocprofv3 byte counters)")
     ap.add_argument("--trace-summary", metavar="TRACE_DIR",
                     help="print per-kernel mean durations of a rocprofv3 --kernel-trace run")
+    ap.add_argument("--by-workgroup", action="store_true",
+                    help="with --trace-summary: one line per kernel and workgroup size")
+    ap.add_argument("--launch-form", choices=("auto", "per-width", "single"), default="auto",
+                    help="boxes6: sweep launches per workgroup width or one launch (auto: the "
+                         "plan's choice, and the other form timed beside it)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs into profiles/")
     args = ap.parse_args()
@@ -450,7 +466,9 @@ def main():
         pmc_summary(args.workload, args.rows, *args.pmc_summary)
         return
     if args.trace_summary:
-        for n, k, avg_us, tot_ms in trace_summary(args.trace_summary):
+        for n, k, avg_us, tot_ms in trace_summary(args.trace_summary, args.by_workgroup):
+            if args.by_workgroup and "(" in n:   # drop the argument list
+                n = n.split("(")[0] + " " + n[n.rfind("[workgroup"):]
             print(f"{avg_us:12.1f} us  x{k:4d}  {tot_ms:10.3f} ms  {n[:110]}")
         return
     if args.gpus != 1:
