@@ -306,3 +306,23 @@ def test_bench_refuses_more_than_one_gpu_and_entry_points_exist():
     sys.path.insert(0, ROOT)
     import __graft_entry__ as g
     assert callable(g.build) and callable(g.smoke)
+
+
+def test_bench_trace_summary_groups_by_workgroup(tmp_path):
+    # a kernel-trace database of the shape rocprofv3 writes: one table of
+    # dispatches with the kernel name, duration (ns) and workgroup size
+    import sqlite3
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    c = sqlite3.connect(tmp_path / "trace_results.db")
+    c.execute("create table kernels (name text, duration integer, workgroup_x integer)")
+    rows = [("k(A)", 3000, 576), ("k(A)", 5000, 576), ("k(A)", 1000, 64), ("z(B)", 2000, 256)]
+    c.executemany("insert into kernels values (?, ?, ?)", rows)
+    c.commit()
+    c.close()
+    plain = {n: (k, a) for n, k, a, _ in bench.trace_summary(str(tmp_path))}
+    assert plain == {"k(A)": (3, 3.0), "z(B)": (1, 2.0)}
+    by = {n: (k, a) for n, k, a, _ in bench.trace_summary(str(tmp_path), by_workgroup=True)}
+    assert by == {"k(A) [workgroup 576]": (2, 4.0), "k(A) [workgroup 64]": (1, 1.0),
+                  "z(B) [workgroup 256]": (1, 2.0)}
