@@ -9,11 +9,16 @@ rts_solve: chi preparation, every sweep of every band and ray, and the final
 reduction, with inputs already resident in HBM.
 
 Prints one JSON line.  `value` is nominal cell-ray-band updates per second
-(N * rays * bands per step).  `roofline` describes the sweep kernel, timed
-with HIP events on its own stream inside the timed region.  `cpu_baseline`
-times the FP64 oracle on the whole workload on this host's cores (about 15 s
-with 16 threads).  The schedule (rows per strip, queue order) is picked by
-the library's autotuner before the warm-up unless --rows is given.
+(N * rays * bands per step); the timed calls are replays of one captured
+hipGraph of the whole call (--no-graph: eager calls).  `roofline` describes
+the sweep kernel, timed with HIP events on its stream inside the timed region
+(event-record nodes of the replayed graph), against the published FP32 vector
+peak.  `adjoint` is the adjoint / forward time on the 128^3 adjoint workload
+with the training-step split.  `cpu_baseline` times the FP64 oracle on the
+whole workload on this host's cores (at most 16 threads; about 15 s) and,
+single-threaded, on a bounded sample of it.  The schedule (rows per strip,
+queue order) is picked by the library's autotuner before the warm-up unless
+--rows is given.
 
 Other modes: --adjoint (adjoint/forward time on the 128^3 adjoint workload),
 --workload boxes6 (six uneven boxes in one batched, graph-replayed call).
@@ -183,22 +188,72 @@ def pmc_summary(workload, rows, fetch_dir, write_dir, cfetch_dir, cwrite_dir):
     print(json.dumps(out))
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(p_full):
-    """The FP64 oracle on the whole workload (every band, ray and boundary
-    iteration, the same synthetic inputs) on this host's cores."""
+    """The FP64 oracle on this host's cores: all cores (at most 16, the host
+    share of one GPU) on the whole workload (every band, ray and boundary
+    iteration, the same synthetic inputs), and one thread on a bounded sample
+    of it (the grey band on the bottom third of the layers)."""
     import oracle
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     threads = max(1, min(16, cores))
     q = p_full.astype(np.float64)
     oracle._load()
     t0 = time.perf_counter()
-    oracle.solve(q, threads=threads)
+    ref = oracle.solve(q, threads=threads)
     dt = time.perf_counter() - t0
     nominal = q.ncells * q.nrays * q.nbands
-    return {"value": nominal / dt, "unit": "cell-ray-band updates/s", "cores": threads,
+    # single-thread sample: band nbands-1 (grey) of layers 0 .. nz/3
+    from paper_2107_08145_amd import inputs
+    nz1 = max(2, q.nz // 3)
+    b = q.nbands - 1
+    s1 = inputs.Problem(q.nx, q.ny, nz1, q.dx, q.dy, q.dz, q.mu, q.w,
+                        np.ascontiguousarray(q.kappa[b:b + 1, :nz1]),
+                        np.ascontiguousarray(q.rho[:nz1]),
+                        np.ascontiguousarray(q.S[b:b + 1, :nz1]), np.ones(1),
+                        q.bot, q.top, q.i_bot, q.n_iter)
+    t0 = time.perf_counter()
+    oracle.solve(s1, threads=1)
+    dt1 = time.perf_counter() - t0
+    nominal1 = s1.ncells * s1.nrays * s1.nbands
+    return ref, {"value": nominal / dt, "unit": "cell-ray-band updates/s", "cores": threads,
             "kind": "oracle", "seconds": round(dt, 2),
             "sample": f"FP64 oracle, the whole workload: {q.nx}x{q.ny}x{q.nz}, {q.nbands} bands, "
-                      f"{q.nrays} rays, n_iter {q.n_iter} (OpenMP over the cells of a plane)"}
+                      f"{q.nrays} rays, n_iter {q.n_iter} (OpenMP over the cells of a plane)",
+            "nproc": os.cpu_count(), "affinity_cores": cores, "cpu_model": _cpu_model(),
+            "single_thread": {"value": nominal1 / dt1, "unit": "cell-ray-band updates/s",
+                              "cores": 1, "seconds": round(dt1, 2),
+                              "sample": f"FP64 oracle, one thread: the grey band on layers "
+                                        f"0..{nz1 - 1} ({q.nx}x{q.ny}x{nz1}, {q.nrays} rays, "
+                                        f"n_iter {q.n_iter})"}}
+
+
+def error_report(got, ref):
+    """Errors of (Q, J, I_top) against the FP64 oracle: the paper's per-value
+    validation rule (relative 1e-5 or absolute 1e-7, the latter taken of the
+    array's largest magnitude: arbitrary units), its failing values, the
+    normwise max|d|/max|ref| and the largest relative error over the values
+    with |ref| >= 1e-3 max|ref|."""
+    rep = {}
+    for name, g, r in zip(("Q", "J", "I_top"), got, ref):
+        d = np.abs(g - r)
+        a = np.abs(r)
+        m = a.max()
+        ok = (d <= 1e-5 * a) | (d <= 1e-7 * m)
+        big = a >= 1e-3 * m
+        rep[name] = {"per_value_failures": int((~ok).sum()), "values": int(ok.size),
+                     "normwise": float(d.max() / m),
+                     "max_rel_over_1e-3_max": float((d[big] / a[big]).max())}
+    return rep
 
 
 def _time_calls(fn, steps, warmup):
@@ -214,18 +269,19 @@ def _time_calls(fn, steps, warmup):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
-def bench_adjoint(args):
-    """Adjoint vs forward on the adjoint workload (128^3 grey unless --workload/--size).
+def adjoint_measure(name, size, prec_name, steps, warmup):
+    """Adjoint vs forward on the adjoint workload (128^3 grey by default).
 
     Loss: L = sum over the top layer and upward rays of (I_top - I_target)^2 +
     sum(g Q), I_target from the same solver on a 5 % perturbed S.  One adjoint
     call re-runs the forward sweep (storing D of every plane) and the reverse
-    sweep; the forward reference is one rts_solve."""
+    sweep; the forward reference is one rts_solve.  Also the training-step
+    split: a forward that keeps D (rts_solve_for_adjoint) and a backward that
+    only sweeps in reverse (rts_adjoint_from_solve)."""
     import torch
     from paper_2107_08145_amd import inputs, rts
-    name = args.workload if args.workload != "bands288" else "adjoint128"
-    p = inputs.workload(name, size=args.size)
-    prec = rts.RTS_FP32 if args.prec == "fp32" else rts.RTS_FP64
+    p = inputs.workload(name, size=size)
+    prec = rts.RTS_FP32 if prec_name == "fp32" else rts.RTS_FP64
     pd = p.astype(np.float32 if prec == rts.RTS_FP32 else np.float64)
     s_target, g = inputs.adjoint_seeds(p, 4000)
     torch.cuda.set_device(0)
@@ -241,29 +297,36 @@ def bench_adjoint(args):
     gQ = torch.as_tensor(g, device="cuda", dtype=torch.float64)
     dS = torch.empty_like(ins[2])
     dchi = torch.empty_like(ins[2])
-    fwd_ms = _time_calls(lambda: plan.solve_into([ins], [outs]), args.steps, args.warmup)
+    fwd_ms = _time_calls(lambda: plan.solve_into([ins], [outs]), steps, warmup)
     adj_ms = _time_calls(lambda: plan.adjoint_into([ins], [(gQ, None, gI)], [(dS, dchi)]),
-                         args.steps, args.warmup)
+                         steps, warmup)
     plan.check_status()
-    # a training step: the forward keeps D (rts_solve_for_adjoint), the backward
-    # only sweeps in reverse (rts_adjoint_from_solve)
-    keep_ms = _time_calls(lambda: plan.solve_for_adjoint_into([ins], [outs]), args.steps, args.warmup)
+    keep_ms = _time_calls(lambda: plan.solve_for_adjoint_into([ins], [outs]), steps, warmup)
     back_ms = _time_calls(lambda: plan.adjoint_from_solve_into([ins], [(gQ, None, gI)], [(dS, dchi)]),
-                          args.steps, args.warmup)
+                          steps, warmup)
     plan.check_status()
     nominal = p.ncells * p.nrays * p.nbands
+    return {"ratio": round(adj_ms / fwd_ms, 4), "adjoint_ms": round(adj_ms, 4),
+            "forward_ms": round(fwd_ms, 4), "dtype": "f32" if prec == rts.RTS_FP32 else "f64",
+            "adjoint_updates_per_s": nominal / (adj_ms * 1e-3),
+            "workspace_bytes": plan.workspace_bytes(rts.RTS_OP_ADJOINT),
+            "training_step": {"forward_keeping_d_ms": round(keep_ms, 4), "backward_ms": round(back_ms, 4),
+                              "backward_over_forward": round(back_ms / fwd_ms, 3),
+                              "step_over_forward": round((keep_ms + back_ms) / fwd_ms, 3)},
+            "workload": f"{name}: {p.nx}x{p.ny}x{p.nz}, {p.nbands} band(s), {p.nrays} rays, "
+                        f"n_iter {p.n_iter}; L = sum (I_top - I_target)^2 + sum g Q"}
+
+
+def bench_adjoint(args):
+    name = args.workload if args.workload != "bands288" else "adjoint128"
+    a = adjoint_measure(name, args.size, args.prec, args.steps, args.warmup)
     out = {"metric": "adjoint time / forward time (RTS, reverse-mode dL/dS and dL/dchi)",
-           "value": adj_ms / fwd_ms, "unit": "ratio", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(adj_ms, 4), "forward_ms": round(fwd_ms, 4),
-           "higher_is_better": False, "dtype": "f32" if prec == rts.RTS_FP32 else "f64",
-           "data": "synthetic",
-           "adjoint_updates_per_s": nominal / (adj_ms * 1e-3),
-           "workspace_bytes": plan.workspace_bytes(rts.RTS_OP_ADJOINT),
-           "training_step": {"forward_keeping_d_ms": round(keep_ms, 4), "backward_ms": round(back_ms, 4),
-                             "backward_over_forward": round(back_ms / fwd_ms, 3),
-                             "step_over_forward": round((keep_ms + back_ms) / fwd_ms, 3)},
-           "config": {"workload": f"{name}: {p.nx}x{p.ny}x{p.nz}, {p.nbands} band(s), {p.nrays} rays, "
-                                  f"n_iter {p.n_iter}; L = sum (I_top - I_target)^2 + sum g Q"}}
+           "value": a["ratio"], "unit": "ratio", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": a["adjoint_ms"], "forward_ms": a["forward_ms"],
+           "higher_is_better": False, "dtype": a["dtype"], "data": "synthetic",
+           "adjoint_updates_per_s": a["adjoint_updates_per_s"],
+           "workspace_bytes": a["workspace_bytes"], "training_step": a["training_step"],
+           "config": {"workload": a["workload"]}}
     print(json.dumps(out), flush=True)
 
 
@@ -419,9 +482,7 @@ def bench_batched(args):
         for p, pd, o in zip(ps, pds, outs):
             ref = oracle.solve(pd.astype(np.float64), threads=16)
             got = [t.double().cpu().numpy() for t in o]
-            errs.append({"box": f"{p.nx}x{p.ny}x{p.nz}"} |
-                        {k: float(np.abs(g - r).max() / np.abs(r).max())
-                         for k, g, r in zip(("Q", "J", "I_top"), got, ref)})
+            errs.append({"box": f"{p.nx}x{p.ny}x{p.nz}"} | error_report(got, ref))
             print(f"# box {errs[-1]}", file=sys.stderr, flush=True)
         out["errors_vs_oracle"] = errs
     print(json.dumps(out), flush=True)
@@ -447,6 +508,10 @@ def main():
     ap.add_argument("--rows", type=int, default=0,
                     help="rows per strip (0: chosen by the library's autotuner)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="default workload: skip the adjoint / forward measurement")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager calls instead of graph replays")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (scales rocprofv3 byte counters)")
     ap.add_argument("--trace-summary", metavar="TRACE_DIR",
@@ -508,7 +573,13 @@ def main():
         tuned = True
         print(f"# autotuned in {time.perf_counter() - t_tune:.1f}s: {plan.schedule()}",
               file=sys.stderr, flush=True)
+    # the whole call (prep, every sweep launch, reduce) replayed from one
+    # captured hipGraph; timed calls record HIP events through event-record
+    # nodes of the graph around the sweep launches and the call
+    if not args.no_graph:
+        plan.set_schedule(use_graph=1)
     torch.cuda.synchronize()
+    plan.enable_timing(True)   # (the timed graph is captured during the warm-up)
     for _ in range(args.warmup):
         plan.solve_into([ins], [outs])
     plan.check_status()
@@ -534,15 +605,17 @@ def main():
     sw_s = sweep_ms * 1e-3
     gbs = alg_bytes / sw_s / 1e9
     tflops = executed * FLOPS_PER_UPDATE / sw_s / 1e12
-    peak_alu = PEAK_FP32_NONPACKED_TFLOPS if prec == rts.RTS_FP32 else PEAK_FP64_TFLOPS
+    peak_alu = PEAK_FP32_TFLOPS if prec == rts.RTS_FP32 else PEAK_FP64_TFLOPS
     traffic = (traffic_from_profile(args.workload, plan.schedule()["rows_per_strip"])
                if args.size is None else None)
     if tflops / peak_alu >= gbs / PEAK_HBM_GBS:
         roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": round(peak_alu, 1),
                 "unit": "TFLOP/s", "frac": round(tflops / peak_alu, 4)}
         if prec == rts.RTS_FP32:
-            roof["peak_packed_fp32"] = PEAK_FP32_TFLOPS
-            roof["frac_of_packed_peak"] = round(tflops / PEAK_FP32_TFLOPS, 4)
+            # the kernels issue no packed FP32 instructions: their own issue
+            # rate is half the published vector peak
+            roof["peak_nonpacked_fp32"] = round(PEAK_FP32_NONPACKED_TFLOPS, 1)
+            roof["frac_of_nonpacked_peak"] = round(tflops / PEAK_FP32_NONPACKED_TFLOPS, 4)
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(gbs / PEAK_HBM_GBS, 4)}
@@ -562,7 +635,7 @@ def main():
                        f"{p.nrays} rays S4, n_iter {p.n_iter}, seeded stratified atmosphere",
            "grid": [p.nx, p.ny, p.nz], "bands": p.nbands, "rays": p.nrays, "n_iter": p.n_iter,
            "schedule": plan.schedule(), "autotuned": tuned, "sweep_ms": round(sweep_ms, 4),
-           "tol": args.tol,
+           "tol": args.tol, "graph_replay": not args.no_graph,
            "call_ms": round(call_ms, 4), "executed_updates_per_s": executed / (ms * 1e-3)}
     out = {"metric": "cell-ray-band updates/sec (288^3 4-band+grey 24-ray RTS)",
            "value": nominal / (ms * 1e-3), "unit": "cell-ray-band updates/s", "n_gpus": 1,
@@ -570,9 +643,17 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32" if prec == rts.RTS_FP32 else "f64", "data": "synthetic",
            "config": cfg, "roofline": roof}
+    if not args.no_adjoint and args.size is None:
+        # adjoint / forward time on the 128^3 adjoint workload, same precision
+        print("# adjoint (adjoint128)...", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_measure("adjoint128", None, args.prec, args.steps, args.warmup)
     if not args.no_cpu and args.size is None:
         print("# cpu baseline (oracle)...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(p)
+        # the oracle on the inputs the GPU solved (FP32-rounded in an FP32
+        # plan); its result also gives the errors of the timed calls' outputs
+        got = [o.double().cpu().numpy() for o in outs]
+        ref, out["cpu_baseline"] = cpu_baseline(pd)
+        out["errors_vs_oracle"] = error_report(got, ref)
     print(json.dumps(out), flush=True)
 
 

@@ -139,7 +139,9 @@ typedef struct {
   int32_t max_workgroups; /* 0 = as many as are co-resident; never fewer than the strips of
                              the largest task (they must all be resident together) */
   int32_t order;          /* 0: longest sweeps first, 1: input order */
-  int32_t use_graph;      /* 1: rts_solve_batched replays a captured hipGraph */
+  int32_t use_graph;      /* 1: rts_solve and rts_solve_batched replay a captured hipGraph of
+                             the whole call (re-captured when a pointer, the layout or the
+                             timing switch changes) */
   int32_t single_launch;  /* 0: one persistent sweep launch per workgroup width (the sweep
                              tasks whose sweep planes round up to the same multiple of 64
                              columns), widest first, in stream order; 1: every task in one
@@ -230,9 +232,10 @@ int rts_plan_get_schedule(void* plan, rts_schedule* s);
 int rts_plan_set_schedule(void* plan, const rts_schedule* s);
 
 /* Device-side timing.  While enabled, each rts_solve / rts_solve_batched call
- * (not graph replays) records HIP events on its stream around the sweep
- * launches (one per workgroup width, see rts_schedule.single_launch) and
- * around the whole call (up to 512 calls).  rts_plan_last_timing waits for
+ * records HIP events on its stream around the sweep launches (one per
+ * workgroup width, see rts_schedule.single_launch) and around the whole call
+ * (up to 512 calls); a graph replay does so through event-record nodes of the
+ * captured graph, re-pointed to the call's events before each replay.  rts_plan_last_timing waits for
  * the last recorded call and returns the mean sweep-kernel and whole-call
  * durations in ms over the calls recorded since timing was (re)enabled, or -1
  * if none.  Enabling resets the record. */

@@ -32,9 +32,13 @@ class RTSFunction(torch.autograd.Function):
         if any(ctx.needs_input_grad[:3]):
             ws_t, w, nbytes = plan.adjoint_workspace()
             plan.solve_for_adjoint_into([ins], [(Q, J, It)], ws=(w, nbytes))
+            # the status word of the private workspace (a neighbour-wait
+            # timeout leaves partial outputs): checked before anything reads them
+            plan.check_status(ws=w)
             ctx.ws = (ws_t, w, nbytes)
         else:
             plan.solve_into([ins], [(Q, J, It)])
+            plan.check_status()
         ctx.plan = plan
         ctx.save_for_backward(*ins)
         return Q, J, It
@@ -49,6 +53,7 @@ class RTSFunction(torch.autograd.Function):
         seeds = (_dev(gQ, torch.float64), _dev(gJ, dt), _dev(gIt, dt))
         ws_t, w, nbytes = ctx.ws
         plan.adjoint_from_solve_into([(kappa, rho, S)], [seeds], [(dS, dchi)], ws=(w, nbytes))
+        plan.check_status(ws=w)
         del ctx.ws
         dkappa = dchi * rho.unsqueeze(0) if ctx.needs_input_grad[0] else None
         drho = (dchi * kappa).sum(0) if ctx.needs_input_grad[1] else None

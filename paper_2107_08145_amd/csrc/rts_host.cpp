@@ -53,7 +53,8 @@ hipError_t launch_adj_seed(const void*, const void*, const double*, const void*,
                            double, int, int, int, hipStream_t);
 template <class Real>
 hipError_t launch_adj_reduce(const char*, const Task*, const AdjTask*, const BoxGeo&,
-                             const double*, const void*, const void*, void*, void*, hipStream_t);
+                             const double*, const void*, const void*, const void*, void*, void*,
+                             hipStream_t);
 }  // namespace rts
 
 using namespace rts;
@@ -151,10 +152,12 @@ struct Plan {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   std::vector<void*> old_pinned;
-  const void* uploaded_ws = nullptr;
   // graph cache
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;           // the captured graph of gexec
+  hipEvent_t cap_ev[4] = {};            // events recorded at capture (timed graphs)
+  hipGraphNode_t ev_nodes[4] = {};      // their event-record nodes
   std::vector<const void*> gkey;
   // timing: events of up to kMaxTimed calls (call start, sweep start, sweep end, call end)
   bool timing = false;
@@ -469,11 +472,11 @@ void build_layout(Plan& P) {
                                       : std::max(c.threads, (P.tasks[i].n_cols + 63) / 64 * 64);
   }
   P.rev_blocks = 0;
-  P.uploaded_ws = nullptr;
-  if (P.gexec) {
-    (void)hipGraphExecDestroy(P.gexec);
-    P.gexec = nullptr;
-  }
+  if (P.gexec) (void)hipGraphExecDestroy(P.gexec);
+  if (P.graph) (void)hipGraphDestroy(P.graph);
+  P.gexec = nullptr;
+  P.graph = nullptr;
+  for (auto& n : P.ev_nodes) n = nullptr;
 }
 
 int dev_init(Plan& P) {
@@ -588,6 +591,11 @@ int ensure_pinned(Plan& P) {
   return RTS_OK;
 }
 
+hipError_t upload_tables(const Plan& P, char* ws, hipStream_t st) {
+  return hipMemcpyAsync(ws + P.off_tasks, P.pinned, P.off_data - P.off_tasks,
+                        hipMemcpyHostToDevice, st);
+}
+
 // Enqueue one forward solve of all boxes of the plan.
 BoxGeo box_geo(const Plan& P, size_t b) {
   const Box& B = P.boxes[b];
@@ -602,6 +610,18 @@ BoxGeo box_geo(const Plan& P, size_t b) {
   for (int r = 0; r < B.d.nrays; ++r)
     for (int m = 0; m < 3; ++m) G.msum[m] += B.w[r] * B.mu[3 * r + m];
   G.dx = B.d.g.dx; G.dy = B.d.g.dy; G.dz = B.d.g.dz;
+  G.chi_off = B.chi_off;
+  G.chiT_off = B.chiT_off;
+  G.sT_off = B.sT_off;
+  // sum_r w_r - 1, compensated (Neumaier), so that weights summing to 1 give
+  // an exact 0 whenever their rounded sum is exact
+  double s = 0.0, comp = 0.0;
+  for (int r = 0; r < B.d.nrays; ++r) {
+    const double t = s + B.w[r];
+    comp += std::fabs(s) >= std::fabs(B.w[r]) ? (s - t) + B.w[r] : (B.w[r] - t) + s;
+    s = t;
+  }
+  G.wsum1 = (s - 1.0) + comp;
   return G;
 }
 
@@ -610,15 +630,16 @@ BoxGeo box_geo(const Plan& P, size_t b) {
 // sweep stores D as well as writing the outputs (rts_solve_for_adjoint).
 template <class Real>
 int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char* ws,
-                    hipStream_t st, hipEvent_t* ev, bool store = false) {
+                    hipStream_t st, hipEvent_t* ev, bool store = false, bool ev_ext = false) {
+  // (under graph capture the sweep's events become event-record nodes)
+  const unsigned ev_flags = ev_ext ? hipEventRecordExternal : hipEventRecordDefault;
   // header and exchange buffers to zero
   RTS_HIP(launch_zero(reinterpret_cast<int*>(ws),
                       (int64_t)((P.off_tasks) / sizeof(int32_t)), st));
-  if (P.uploaded_ws != ws) {
-    RTS_HIP(hipMemcpyAsync(ws + P.off_tasks, P.pinned, P.off_data - P.off_tasks,
-                           hipMemcpyHostToDevice, st));
-    P.uploaded_ws = ws;
-  }
+  // The task table and queues go up with every call: the same workspace
+  // address does not mean the same device bytes (a caller's allocator may have
+  // handed the block to other work in between).  They are tens of KB.
+  RTS_HIP(upload_tables(P, ws, st));
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     const Box& B = P.boxes[b];
     RTS_HIP(launch_prep<Real>(in[b].kappa, in[b].rho, in[b].S, ws, B.chi_off, B.chiT_off,
@@ -647,7 +668,7 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
   // count; tickets are claimed in order, hence with that many resident
   // workgroups the tasks being worked on always make progress.
   if (P.wclasses.size() > (size_t)kMaxWidths) return RTS_E_UNSUPPORTED;  // (widths <= kMaxCols)
-  if (ev) RTS_HIP(hipEventRecord(ev[1], st));
+  if (ev) RTS_HIP(hipEventRecordWithFlags(ev[1], st, ev_flags));
   for (size_t k = 0; k < P.wclasses.size(); ++k) {
     const Plan::WidthClass& c = P.wclasses[k];
     a.queue = reinterpret_cast<const int32_t*>(ws + P.off_queue) + 2 * c.q0;
@@ -660,7 +681,7 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
     grid = std::max(1, std::min(grid, c.strips));
     RTS_HIP(launch_sweep<Real>(P, c, a, grid, st));
   }
-  if (ev) RTS_HIP(hipEventRecord(ev[2], st));
+  if (ev) RTS_HIP(hipEventRecordWithFlags(ev[2], st, ev_flags));
   if (!out) return RTS_OK;
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     const BoxGeo G = box_geo(P, b);
@@ -683,6 +704,7 @@ int enqueue_adjoint(Plan& P, const rts_inputs* in, const rts_seeds* g, const rts
     if (rc) return rc;
   } else {
     RTS_HIP(launch_zero(reinterpret_cast<int*>(ws), (int64_t)(sizeof(WsHeader) / sizeof(int32_t)), st));
+    RTS_HIP(upload_tables(P, ws, st));
   }
   RTS_HIP(launch_zero(reinterpret_cast<int*>(ws + P.off_grads),
                       (int64_t)((P.off_grads_end - P.off_grads) / sizeof(int32_t)), st));
@@ -722,7 +744,7 @@ int enqueue_adjoint(Plan& P, const rts_inputs* in, const rts_seeds* g, const rts
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     const BoxGeo G = box_geo(P, b);
     RTS_HIP(launch_adj_reduce<Real>(ws, a.tasks, a.atasks, G, g[b].gQ, g[b].gJ, g[b].gItop,
-                                    d[b].dS, d[b].dchi, st));
+                                    in[b].S, d[b].dS, d[b].dchi, st));
   }
   return RTS_OK;
 }
@@ -759,6 +781,28 @@ int prepare(Plan* P) {
   return ensure_pinned(*P);
 }
 
+// One set of timing events (call start, sweep start, sweep end, call end) for
+// the next timed call, or nullptr once kMaxTimed calls are recorded.
+int next_events(Plan* P, hipEvent_t** out) {
+  *out = nullptr;
+  if (!P->timing || P->ev_used >= kMaxTimed) return RTS_OK;
+  if ((int)P->ev.size() <= P->ev_used) {
+    std::array<hipEvent_t, 4> e{};
+    for (int i = 0; i < 4; ++i) RTS_HIP(hipEventCreate(&e[i]));
+    P->ev.push_back(e);
+  }
+  *out = P->ev[P->ev_used].data();
+  return RTS_OK;
+}
+
+void drop_graph(Plan* P) {
+  if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  P->gexec = nullptr;
+  P->graph = nullptr;
+  for (auto& n : P->ev_nodes) n = nullptr;
+}
+
 int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, void* ws,
                size_t ws_bytes, void* stream, bool allow_graph) {
   int rc = check_call(P, nbox, in, out, ws, ws_bytes);
@@ -767,16 +811,9 @@ int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const bool graph = allow_graph && P->sched.use_graph;
   hipEvent_t* ev = nullptr;
-  if (P->timing && !graph && P->ev_used < kMaxTimed) {
-    if ((int)P->ev.size() <= P->ev_used) {
-      std::array<hipEvent_t, 4> e{};
-      for (int i = 0; i < 4; ++i) RTS_HIP(hipEventCreate(&e[i]));
-      P->ev.push_back(e);
-    }
-    ev = P->ev[P->ev_used].data();
-    RTS_HIP(hipEventRecord(ev[0], st));
-  }
+  if ((rc = next_events(P, &ev))) return rc;
   if (!graph) {
+    if (ev) RTS_HIP(hipEventRecord(ev[0], st));
     rc = P->prec == RTS_FP32 ? enqueue_forward<float>(*P, in, out, (char*)ws, st, ev)
                              : enqueue_forward<double>(*P, in, out, (char*)ws, st, ev);
     if (rc) return rc;
@@ -786,23 +823,32 @@ int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
     }
     return RTS_OK;
   }
-  // graph path: key on every pointer the captured work uses
-  std::vector<const void*> key{ws};
+  // graph path: key on every pointer the captured work uses, and on timing
+  // (a timed graph holds event-record nodes around the call and the sweeps)
+  const bool timed = ev != nullptr;
+  std::vector<const void*> key{ws, reinterpret_cast<const void*>(uintptr_t(timed ? 1 : 0))};
   for (int b = 0; b < nbox; ++b) {
     key.insert(key.end(), {in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top,
                            out[b].F, out[b].QF});
   }
   if (!P->gexec || key != P->gkey) {
-    if (P->gexec) {
-      (void)hipGraphExecDestroy(P->gexec);
-      P->gexec = nullptr;
-    }
+    drop_graph(P);
     if (!P->cap_stream) RTS_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
-    // make sure the task table is resident before capture (the capture re-uploads it)
-    P->uploaded_ws = nullptr;
+    if (timed && !P->cap_ev[0])
+      for (auto& e : P->cap_ev) RTS_HIP(hipEventCreate(&e));
     RTS_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
-    rc = P->prec == RTS_FP32 ? enqueue_forward<float>(*P, in, out, (char*)ws, P->cap_stream, nullptr)
-                             : enqueue_forward<double>(*P, in, out, (char*)ws, P->cap_stream, nullptr);
+    // event-record nodes (external events: their timestamps are kept), whose
+    // events are re-pointed before each timed replay
+    hipError_t e0 = timed ? hipEventRecordWithFlags(P->cap_ev[0], P->cap_stream, hipEventRecordExternal)
+                          : hipSuccess;
+    rc = e0 != hipSuccess ? hip_fail(e0, "hipEventRecordWithFlags")
+         : P->prec == RTS_FP32
+             ? enqueue_forward<float>(*P, in, out, (char*)ws, P->cap_stream, timed ? P->cap_ev : nullptr, false, true)
+             : enqueue_forward<double>(*P, in, out, (char*)ws, P->cap_stream, timed ? P->cap_ev : nullptr, false, true);
+    if (!rc && timed) {
+      e0 = hipEventRecordWithFlags(P->cap_ev[3], P->cap_stream, hipEventRecordExternal);
+      if (e0 != hipSuccess) rc = hip_fail(e0, "hipEventRecordWithFlags");
+    }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
     if (rc) {
@@ -810,12 +856,42 @@ int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
       return rc;
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    if (timed) {  // the event-record nodes, by the event each records
+      size_t n = 0;
+      RTS_HIP(hipGraphGetNodes(g, nullptr, &n));
+      std::vector<hipGraphNode_t> nodes(n);
+      RTS_HIP(hipGraphGetNodes(g, nodes.data(), &n));
+      for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType ty;
+        RTS_HIP(hipGraphNodeGetType(nd, &ty));
+        if (ty != hipGraphNodeTypeEventRecord) continue;
+        hipEvent_t ee = nullptr;
+        RTS_HIP(hipGraphEventRecordNodeGetEvent(nd, &ee));
+        for (int i = 0; i < 4; ++i)
+          if (ee == P->cap_ev[i]) P->ev_nodes[i] = nd;
+      }
+      for (auto nd : P->ev_nodes)
+        if (!nd) {
+          (void)hipGraphDestroy(g);
+          for (auto& x : P->ev_nodes) x = nullptr;
+          g_last_hip = "timed graph capture: an event-record node is missing";
+          return RTS_E_HIP;
+        }
+    }
     e = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    P->graph = g;  // kept: its nodes address the exec's event-record nodes
     P->gkey = key;
   }
+  if (timed) {
+    for (int i = 0; i < 4; ++i)
+      RTS_HIP(hipGraphExecEventRecordNodeSetEvent(P->gexec, P->ev_nodes[i], ev[i]));
+  }
   RTS_HIP(hipGraphLaunch(P->gexec, st));
+  if (timed) ++P->ev_used;
   return RTS_OK;
 }
 
@@ -1053,7 +1129,7 @@ int rts_solve(void* plan, const rts_inputs* in, const rts_outputs* out, void* ws
   Plan* P = static_cast<Plan*>(plan);
   if (P->boxes.size() != 1) return RTS_E_ARG;
   try {
-    return solve_impl(P, 1, in, out, ws, ws_bytes, hip_stream, false);
+    return solve_impl(P, 1, in, out, ws, ws_bytes, hip_stream, true);
   } catch (...) {
     return RTS_E_HIP;
   }
@@ -1222,6 +1298,9 @@ void rts_plan_destroy(void* plan) {
   if (!plan) return;
   Plan* P = static_cast<Plan*>(plan);
   if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  for (auto& e : P->cap_ev)
+    if (e) (void)hipEventDestroy(e);
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   for (auto& a : P->ev)
     for (auto& e : a)

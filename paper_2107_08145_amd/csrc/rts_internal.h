@@ -119,6 +119,8 @@ struct BoxGeo {
   double qweight[16];
   double msum[3];          // sum_r w_r mu_r (the flux of an isotropic unit intensity / 4 pi)
   double dx, dy, dz;       // grid spacing (flux divergence)
+  double wsum1;            // sum_r w_r - 1: J_b = (1 + wsum1) S_b + sum_r w_r D_r (0 for
+                           // normalised weights, then the term vanishes exactly)
 };
 
 // Forward sweep launches of one call: one per workgroup width (padded columns).

@@ -957,8 +957,10 @@ __global__ __launch_bounds__(256) void rts_reduce(const char* __restrict__ ws,
       if (x < nx && y < ny) {
         const int64_t p = ((int64_t)z * ny + y) * nx + x;
         const double chi = (double)kap[b * N + p] * (double)rho[p];
-        q[i] += qf * chi * acc[i];
-        if (J) J[b * N + p] = (Real)((double)S[b * N + p] + acc[i]);
+        const double sv = (double)S[b * N + p];
+        const double dj = acc[i] + G.wsum1 * sv;  // J - S
+        q[i] += qf * chi * dj;
+        if (J) J[b * N + p] = (Real)(sv + dj);
       }
     }
   }
@@ -1056,14 +1058,17 @@ __global__ __launch_bounds__(256) void rts_reduce_v4(const char* __restrict__ ws
       const double qf = 4.0 * 3.14159265358979323846 * G.qweight[b];
       const float4 k4 = *reinterpret_cast<const float4*>(kap + b * N + p);
       const float4 s4 = *reinterpret_cast<const float4*>(S + b * N + p);
-      q[0] += qf * ((double)k4.x * (double)r4.x) * acc[0];
-      q[1] += qf * ((double)k4.y * (double)r4.y) * acc[1];
-      q[2] += qf * ((double)k4.z * (double)r4.z) * acc[2];
-      q[3] += qf * ((double)k4.w * (double)r4.w) * acc[3];
+      // J - S = sum of the partials + (sum_r w_r - 1) S
+      const double dj[4] = {acc[0] + G.wsum1 * (double)s4.x, acc[1] + G.wsum1 * (double)s4.y,
+                            acc[2] + G.wsum1 * (double)s4.z, acc[3] + G.wsum1 * (double)s4.w};
+      q[0] += qf * ((double)k4.x * (double)r4.x) * dj[0];
+      q[1] += qf * ((double)k4.y * (double)r4.y) * dj[1];
+      q[2] += qf * ((double)k4.z * (double)r4.z) * dj[2];
+      q[3] += qf * ((double)k4.w * (double)r4.w) * dj[3];
       if (J)
         *reinterpret_cast<float4*>(J + b * N + p) =
-            make_float4((float)((double)s4.x + acc[0]), (float)((double)s4.y + acc[1]),
-                        (float)((double)s4.z + acc[2]), (float)((double)s4.w + acc[3]));
+            make_float4((float)((double)s4.x + dj[0]), (float)((double)s4.y + dj[1]),
+                        (float)((double)s4.z + dj[2]), (float)((double)s4.w + dj[3]));
       if (FLUX) {
         const double sv[4] = {(double)s4.x, (double)s4.y, (double)s4.z, (double)s4.w};
         for (int m = 0; m < 3; ++m)
@@ -1579,6 +1584,7 @@ __global__ __launch_bounds__(256) void rts_adj_reduce(const char* __restrict__ w
                                                      const double* __restrict__ gQ,
                                                      const Real* __restrict__ gJ,
                                                      const Real* __restrict__ gItop,
+                                                     const Real* __restrict__ S,
                                                      Real* __restrict__ dS, Real* __restrict__ dchi) {
   __shared__ double t0[32][33], t1[32][33], t2[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -1586,6 +1592,7 @@ __global__ __launch_bounds__(256) void rts_adj_reduce(const char* __restrict__ w
   const int nx = G.nx, ny = G.ny, nz = G.nz;
   const int64_t N = (int64_t)nx * ny * nz;
   const Real* w = reinterpret_cast<const Real*>(ws);
+  const Real* chi = w + G.chi_off;
   for (int b = 0; b < G.nbands; ++b) {
     double as[4] = {0, 0, 0, 0}, ac[4] = {0, 0, 0, 0}, aj[4] = {0, 0, 0, 0};
     for (int k = 0; k < G.tasks_per_band; ++k) {
@@ -1640,11 +1647,18 @@ __global__ __launch_bounds__(256) void rts_adj_reduce(const char* __restrict__ w
       if (x < nx && y < ny) {
         const int64_t p = ((int64_t)z * ny + y) * nx + x;
         double vs = as[i], vc = ac[i];
-        if (gJ) vs += (double)gJ[b * N + p];
+        // direct terms of J_b = (1 + wsum1) S_b + sum_r w_r D_r and
+        // Q = sum_b 4 pi qw_b chi_b (wsum1 S_b + sum_r w_r D_r)
+        const double sv = G.wsum1 != 0.0 ? (double)S[b * N + p] : 0.0;
+        const double cv = G.wsum1 != 0.0 ? (double)chi[b * N + p] : 0.0;
+        if (gJ) vs += (1.0 + G.wsum1) * (double)gJ[b * N + p];
         if (gItop && z == nz - 1)
           for (int r = 0; r < G.n_up; ++r)
             vs += (double)gItop[(((int64_t)b * G.n_up + r) * ny + y) * nx + x];
-        if (gQ) vc += qf * aj[i] * gQ[p];
+        if (gQ) {
+          vc += qf * (aj[i] + G.wsum1 * sv) * gQ[p];
+          vs += qf * G.wsum1 * cv * gQ[p];
+        }
         dS[b * N + p] = (Real)vs;
         dchi[b * N + p] = (Real)vc;
       }
@@ -1660,6 +1674,7 @@ __global__ __launch_bounds__(256) void rts_adj_reduce_v4(const char* __restrict_
                                                         BoxGeo G, const double* __restrict__ gQ,
                                                         const float* __restrict__ gJ,
                                                         const float* __restrict__ gItop,
+                                                        const float* __restrict__ S,
                                                         float* __restrict__ dS,
                                                         float* __restrict__ dchi) {
   __shared__ double t0[32][33], t1[32][33], t2[32][33];
@@ -1722,9 +1737,20 @@ __global__ __launch_bounds__(256) void rts_adj_reduce_v4(const char* __restrict_
     if (in) {
       const double qf = 4.0 * 3.14159265358979323846 * G.qweight[b];
       double vs[4] = {as[0], as[1], as[2], as[3]}, vc[4] = {ac[0], ac[1], ac[2], ac[3]};
+      // direct terms of J_b = (1 + wsum1) S_b + sum_r w_r D_r and
+      // Q = sum_b 4 pi qw_b chi_b (wsum1 S_b + sum_r w_r D_r)
+      const double wj = 1.0 + G.wsum1;
+      double sv[4] = {0, 0, 0, 0}, cv[4] = {0, 0, 0, 0};
+      if (G.wsum1 != 0.0) {
+        const float4 s4 = *reinterpret_cast<const float4*>(S + b * N + p);
+        const float4 c4 = *reinterpret_cast<const float4*>(w + G.chi_off + b * N + p);
+        sv[0] = s4.x; sv[1] = s4.y; sv[2] = s4.z; sv[3] = s4.w;
+        cv[0] = c4.x; cv[1] = c4.y; cv[2] = c4.z; cv[3] = c4.w;
+      }
       if (gJ) {
         const float4 j = *reinterpret_cast<const float4*>(gJ + b * N + p);
-        vs[0] += (double)j.x; vs[1] += (double)j.y; vs[2] += (double)j.z; vs[3] += (double)j.w;
+        vs[0] += wj * (double)j.x; vs[1] += wj * (double)j.y;
+        vs[2] += wj * (double)j.z; vs[3] += wj * (double)j.w;
       }
       if (gItop && z == nz - 1)
         for (int r = 0; r < G.n_up; ++r) {
@@ -1734,8 +1760,11 @@ __global__ __launch_bounds__(256) void rts_adj_reduce_v4(const char* __restrict_
       if (gQ) {
         const double2 q01 = *reinterpret_cast<const double2*>(gQ + p);
         const double2 q23 = *reinterpret_cast<const double2*>(gQ + p + 2);
-        vc[0] += qf * aj[0] * q01.x; vc[1] += qf * aj[1] * q01.y;
-        vc[2] += qf * aj[2] * q23.x; vc[3] += qf * aj[3] * q23.y;
+        const double gq[4] = {q01.x, q01.y, q23.x, q23.y};
+        for (int e = 0; e < 4; ++e) {
+          vc[e] += qf * (aj[e] + G.wsum1 * sv[e]) * gq[e];
+          vs[e] += qf * G.wsum1 * cv[e] * gq[e];
+        }
       }
       *reinterpret_cast<float4*>(dS + b * N + p) =
           make_float4((float)vs[0], (float)vs[1], (float)vs[2], (float)vs[3]);
@@ -1865,16 +1894,18 @@ hipError_t launch_adj_seed(const void* kappa, const void* rho, const double* gQ,
 template <class Real>
 hipError_t launch_adj_reduce(const char* ws, const Task* tasks, const AdjTask* atasks,
                              const BoxGeo& g, const double* gQ, const void* gJ, const void* gItop,
-                             void* dS, void* dchi, hipStream_t st) {
+                             const void* S, void* dS, void* dchi, hipStream_t st) {
   dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, g.nz);
-  const uintptr_t al = (uintptr_t)gQ | (uintptr_t)gJ | (uintptr_t)gItop | (uintptr_t)dS |
-                       (uintptr_t)dchi;
+  const uintptr_t al = (uintptr_t)gQ | (uintptr_t)gJ | (uintptr_t)gItop | (uintptr_t)S |
+                       (uintptr_t)dS | (uintptr_t)dchi;
   if (sizeof(Real) == 4 && g.nx % 4 == 0 && al % 16 == 0)
     hipLaunchKernelGGL(rts_adj_reduce_v4, grid, dim3(256), 0, st, ws, tasks, atasks, g, gQ,
-                       (const float*)gJ, (const float*)gItop, (float*)dS, (float*)dchi);
+                       (const float*)gJ, (const float*)gItop, (const float*)S, (float*)dS,
+                       (float*)dchi);
   else
     hipLaunchKernelGGL(rts_adj_reduce<Real>, grid, dim3(256), 0, st, ws, tasks, atasks, g, gQ,
-                       (const Real*)gJ, (const Real*)gItop, (Real*)dS, (Real*)dchi);
+                       (const Real*)gJ, (const Real*)gItop, (const Real*)S, (Real*)dS,
+                       (Real*)dchi);
   return hipGetLastError();
 }
 
@@ -1897,7 +1928,7 @@ template hipError_t launch_reduce<double>(const char*, const Task*, const BoxGeo
                                             void*, void*, double, int, int, int, hipStream_t);  \
   template hipError_t launch_adj_reduce<Real>(const char*, const Task*, const AdjTask*,          \
                                               const BoxGeo&, const double*, const void*,         \
-                                              const void*, void*, void*, hipStream_t);
+                                              const void*, const void*, void*, void*, hipStream_t);
 RTS_ADJ_INST(float)
 RTS_ADJ_INST(double)
 #undef RTS_ADJ_INST

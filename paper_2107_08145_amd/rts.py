@@ -329,8 +329,14 @@ class Plan:
         _check(lib().rts_adjoint(self.handle, n, ci, cs, cg, ctypes.c_void_p(ws), nbytes,
                                  _stream_ptr(stream)), "rts_adjoint")
 
-    def check_status(self, stream=None):
-        ws, _ = self.workspace()
+    def check_status(self, stream=None, ws=None):
+        """rts_check_status: synchronise the stream and raise RTSError if the last call on the
+        workspace (default: the plan's own; else a pointer, or (pointer, bytes)) left an error
+        in its status word (RTS_E_DEADLOCK)."""
+        if ws is None:
+            ws, _ = self.workspace()
+        elif isinstance(ws, tuple):
+            ws = ws[0]
         _check(lib().rts_check_status(self.handle, ctypes.c_void_p(ws), _stream_ptr(stream)),
                "rts_check_status")
 

@@ -18,6 +18,7 @@ import pytest
 
 import oracle
 from paper_2107_08145_amd import inputs, rts
+from percell import assert_paper_rule
 
 pytestmark = pytest.mark.gpu
 
@@ -25,6 +26,9 @@ pytestmark = pytest.mark.gpu
 def _check(p, got, ref, rel):
     Qg, Jg, Ig, Fg, QFg = got
     Qo, Jo, Io, Fo, QFo = ref
+    if rel > 1e-10:  # FP32: the paper's per-value rule on Q, J and I_top
+        for name, g, o in (("Q", Qg, Qo), ("J", Jg, Jo), ("I_top", Ig, Io)):
+            assert_paper_rule(name, g, o)
     scale = 4 * math.pi * np.abs(Jo).max()
     ef = np.abs(Fg - Fo).max()
     eqf = np.abs(QFg - QFo).max()

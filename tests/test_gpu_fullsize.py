@@ -17,6 +17,7 @@ import pytest
 
 import oracle
 from paper_2107_08145_amd import inputs, rts
+from percell import assert_paper_rule
 
 pytestmark = pytest.mark.gpu
 THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
@@ -47,6 +48,8 @@ def test_full_size_fp32(name):
     eq, ej, ei = _errs(got, ref)
     print(f"{name} fp32 {sched}: Q {eq:.2e} J {ej:.2e} I_top {ei:.2e}", flush=True)
     assert eq <= 1e-5 and ej <= 2e-6 and ei <= 2e-6
+    for n, g, o in zip(("Q", "J", "I_top"), got, ref):
+        assert_paper_rule(f"{name} {n}", g, o)
 
 
 def test_full_size_boxes6_batched_fp32():
@@ -72,6 +75,8 @@ def test_full_size_boxes6_batched_fp32():
         eq, ej, ei = _errs(g, ref)
         print(f"boxes6 {p.nx}x{p.ny}x{p.nz}: Q {eq:.2e} J {ej:.2e} I_top {ei:.2e}", flush=True)
         assert eq <= 1e-5 and ej <= 2e-6 and ei <= 2e-6
+        for n, gg, o in zip(("Q", "J", "I_top"), g, ref):
+            assert_paper_rule(f"boxes6 {p.nx}x{p.ny}x{p.nz} {n}", gg, o)
 
 
 def test_full_size_grey288_fp64():
@@ -112,6 +117,8 @@ def test_full_size_bands288_flux_fp32():
     assert eqf <= (4 / p.dx + 4 / p.dy + 4 / p.dz) * 2e-6 * scale
     eq, ej, ei = _errs(got[:3], ref[:3])
     assert eq <= 1e-5 and ej <= 2e-6 and ei <= 2e-6
+    for n, g, o in zip(("Q", "J", "I_top"), got[:3], ref[:3]):
+        assert_paper_rule(f"bands288 flux {n}", g, o)
 
 
 def _adjoint128_seeds(p, prec):

@@ -18,6 +18,7 @@ import pytest
 
 import oracle
 from paper_2107_08145_amd import inputs, rts
+from percell import assert_paper_rule
 
 pytestmark = pytest.mark.gpu
 
@@ -37,12 +38,16 @@ def _check64(p, got, ref):
 
 
 def _check32(p32, got, ref, q_tol=2e-5, j_tol=2e-6):
+    # normwise bars, then the paper's per-value rule (relative 1e-5 or
+    # absolute 1e-7 of the largest value) on every cell of Q, J and I_top
     Qg, Jg, Ig = got
     Qo, Jo, Io = ref
     eq = np.abs(Qg - Qo).max() / np.abs(Qo).max()
     ej = np.abs(Jg - Jo).max() / np.abs(Jo).max()
     ei = np.abs(Ig - Io).max() / max(np.abs(Io).max(), 1e-300)
     assert eq <= q_tol and ej <= j_tol and ei <= j_tol, (eq, ej, ei)
+    for name, g, o in (("Q", Qg, Qo), ("J", Jg, Jo), ("I_top", Ig, Io)):
+        assert_paper_rule(name, g, o)
     return eq, ej, ei
 
 

@@ -17,6 +17,7 @@ import pytest
 
 import oracle
 from paper_2107_08145_amd import inputs, rts
+from percell import assert_paper_rule
 
 pytestmark = pytest.mark.gpu
 
@@ -45,10 +46,13 @@ def _check64(p, got, ref):
 
 
 def _check32(got, ref):
+    # normwise bars, then the paper's per-value rule on every cell
     eq = np.abs(got[0] - ref[0]).max() / np.abs(ref[0]).max()
     ej = np.abs(got[1] - ref[1]).max() / np.abs(ref[1]).max()
     ei = np.abs(got[2] - ref[2]).max() / np.abs(ref[2]).max()
     assert eq <= 2e-5 and ej <= 2e-6 and ei <= 2e-6, (eq, ej, ei)
+    for name, g, o in zip(("Q", "J", "I_top"), got[:3], ref[:3]):
+        assert_paper_rule(name, g, o)
     return eq, ej, ei
 
 

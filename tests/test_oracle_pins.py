@@ -183,6 +183,53 @@ def test_source_linear_in_tau_closed_form(oracle_mod, spacing):
         assert np.allclose(I, exp_[:, None, None], rtol=1e-13, atol=1e-14), r
 
 
+def test_band_sum_closed_form(oracle_mod):
+    # Two bands with band weights qw = (1, 0.5) and ray weights that do not sum
+    # to 1: every ray z-dominant (dx = dy = 3 dz), chi_b = kappa_b rho constant
+    # per band (rho varies with height, kappa_b = chi_b / rho), S_b = a_b + b_b
+    # tau_b.  The exact intensities of each band give J_b = sum_r w_r I_r,
+    # Q = sum_b qw_b 4 pi chi_b (J_b - S_b) and F_z = sum_b qw_b 4 pi
+    # sum_r w_r mu_z,r I_r in closed form: a wrong band offset, band weight,
+    # chi (kappa alone) or J normalisation fails here.
+    nx, ny, nz = 4, 5, 18
+    dz = 0.3
+    z = np.arange(nz) * dz
+    chis = (1.4, 0.35)
+    ab = ((0.8, 0.6), (2.0, 0.25))
+    qw = np.array([1.0, 0.5])
+    mu, w = inputs.s4_quadrature()
+    w = w * (0.9 + 0.6 * np.random.default_rng(11).random(24))   # sum w != 1
+    assert abs(w.sum() - 1) > 1e-2
+    rho = np.exp(-z / 3.0)[:, None, None] * np.ones((nz, ny, nx))
+    kappa = np.stack([c / rho for c in chis])
+    S = np.stack([(a + b * c * (z[-1] - z))[:, None, None] * np.ones((nz, ny, nx))
+                  for (a, b), c in zip(ab, chis)])
+    p = inputs.Problem(nx, ny, nz, 3 * dz, 3 * dz, dz, mu, w, kappa, rho, S, qw, 0, 0, 0.0, 3)
+    Q, J, It, F, _ = oracle_mod.flux(p)
+    Qx = np.zeros(nz)
+    Fz = np.zeros(nz)
+    for bnd, ((a, b), c) in enumerate(zip(ab, chis)):
+        tau = c * (z[-1] - z)
+        Jb = np.zeros(nz)
+        for r in range(24):
+            mz = abs(mu[r, 2])
+            if mu[r, 2] > 0:
+                I = a + b * tau + b * mz - b * mz * np.exp(-(tau[0] - tau) / mz)
+            else:
+                I = a * (1 - np.exp(-tau / mz)) + b * (tau - mz + mz * np.exp(-tau / mz))
+            Jb += w[r] * I
+            Fz += qw[bnd] * 4 * math.pi * w[r] * mu[r, 2] * I
+        assert np.allclose(J[bnd], Jb[:, None, None], rtol=1e-13, atol=0)
+        Qx += qw[bnd] * 4 * math.pi * c * (Jb - (a + b * tau))
+    scale = np.abs(Qx).max()
+    assert np.abs(Q - Qx[:, None, None]).max() <= 1e-12 * scale
+    assert np.allclose(F[2], Fz[:, None, None], rtol=1e-12, atol=1e-12 * np.abs(Fz).max())
+    # Q = sum_b 4 pi qw_b chi_b (J_b - S_b) also holds cell by cell for the solve
+    Q2, J2, _ = oracle_mod.solve(p)
+    assert np.array_equal(J2, J)
+    assert np.abs(Q2 - Qx[:, None, None]).max() <= 1e-12 * scale
+
+
 # ---------------------------------------------------------------------------
 # Brute force: the discrete scheme as one linear system over (sweep, cell),
 # built from physical coordinates (upwind point = cell centre - ds * mu) and
