@@ -75,9 +75,13 @@ def task_list(p):
 
 
 def kernel_hash():
+    """Hash of the device sources (every .hip / .hpp file and the shared structures)."""
+    d = os.path.join(ROOT, "paper_2107_08145_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("rts_kernels.hip", "rts_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2107_08145_amd", "csrc", f), "rb").read())
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")) or f == "rts_internal.h":
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 

@@ -24,7 +24,7 @@
 #include "rts_internal.h"
 
 namespace rts {
-// kernels (rts_kernels.hip)
+// kernels (rts_sweep.hpp, rts_reverse.hpp, rts_misc.hip)
 template <class Real>
 hipError_t launch_prep(const void*, const void*, const void*, void*, int64_t, int64_t, int64_t,
                        int, int, int, int, hipStream_t);

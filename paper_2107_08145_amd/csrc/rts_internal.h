@@ -1,5 +1,6 @@
 // Internal structures shared by the host planner (rts_host.cpp) and the gfx950
-// kernels (rts_kernels.hip).  Not part of the public ABI.
+// kernels (rts_device.hpp, rts_sweep.hpp, rts_reverse.hpp, rts_misc.hip).  Not
+// part of the public ABI.
 #pragma once
 #include <stdint.h>
 
