@@ -53,9 +53,10 @@ def _load():
         lib.oracle_complex_step.argtypes = head + [p, p, i, i64, d, p, p, p, i]
         lib.oracle_ray.argtypes = [i, i, i, d, d, d, p, i, i, d, i, p, p, p]
         lib.oracle_weights.argtypes = [d, p, p, p, p]
+        lib.oracle_solve_sub.argtypes = head + [p, d, p, p, p, p, p, p, p, p, i]
         for f in ("oracle_solve", "oracle_solve_chi", "oracle_adjoint",
                   "oracle_complex_step", "oracle_ray", "oracle_flux", "oracle_flux_divergence",
-                  "oracle_solve_tol"):
+                  "oracle_solve_tol", "oracle_solve_sub"):
             getattr(lib, f).restype = i
         lib.oracle_weights.restype = None
         _lib = lib
@@ -101,6 +102,32 @@ def solve(p, threads: int = 1, chi=None):
         raise ValueError("oracle rejected the problem")
     del keep
     return Q, J, It
+
+
+def solve_sub(p, sub, tol: float = 0.0, threads: int = 1, want_intensity: bool = False):
+    """Forward solve on sub = (mx, my, mz) subdomains with lagged exchange
+    between iterations (block Jacobi across subdomains, exact sweeps inside
+    one): p.n_iter iterations, or with tol > 0 until the largest intensity
+    change over all cells, rays and bands is at most tol of the largest
+    intensity.  Returns (Q, J, I_top, iterations), plus the final intensity of
+    every ray [B, R, nz, ny, nx] with want_intensity."""
+    lib = _load()
+    keep, head = _head(p)
+    B = p.nbands
+    Q = np.empty((p.nz, p.ny, p.nx))
+    J = np.empty((B, p.nz, p.ny, p.nx))
+    It = np.empty((B, p.n_up, p.ny, p.nx))
+    Ia = np.empty((B, p.nrays, p.nz, p.ny, p.nx)) if want_intensity else None
+    m = np.ascontiguousarray(sub, dtype=np.int32)
+    it = np.zeros(1, dtype=np.int32)
+    kap, rho, S = _f64(p.kappa), _f64(p.rho), _f64(p.S)
+    rc = lib.oracle_solve_sub(*head, _ptr(m), float(tol), _ptr(kap), _ptr(rho), _ptr(S), _ptr(Q),
+                              _ptr(J), _ptr(It), _ptr(Ia), _ptr(it), threads)
+    if rc:
+        raise ValueError("oracle rejected the problem")
+    del keep
+    out = (Q, J, It, int(it[0]))
+    return out + (Ia,) if want_intensity else out
 
 
 def flux(p, threads: int = 1):

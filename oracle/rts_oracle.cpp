@@ -50,6 +50,10 @@
 //     one-sided differences in the bottom and top layers).
 //   * Adjoint: the reverse-mode derivative of the above (downwind to upwind,
 //     last sweep first, ghost sensitivities carried into the previous sweep).
+//   * Subdomain decomposition (the paper's domain-decomposed RTS): blocks of
+//     the grid iterate with the intensities their upwind neighbours produced
+//     in the previous iteration (block Jacobi across blocks, exact sweeps
+//     inside a block), n_iter iterations or until a global tolerance.
 //
 // Build: g++ -O2 -std=c++17 -fPIC -shared -ffp-contract=off -fno-fast-math -fopenmp
 #include <algorithm>
@@ -542,6 +546,173 @@ void flux_divergence(const Desc& D, const double* F, double* QF) {
       }
 }
 
+// ---------------------------------------------------------------------------
+// Subdomain decomposition with lagged exchange.  The paper's radiation
+// transport runs on a 3D domain decomposition: each subdomain integrates its
+// rays from the boundary intensities its upwind neighbours produced in the
+// previous iteration, sends its own outflow intensities downstream, and the
+// iteration (integrate, write buffers, exchange, error with a global maximum)
+// repeats until the boundary intensities have converged.
+//
+// Here the grid is cut into sub[0] x sub[1] x sub[2] blocks along x, y and z
+// (block b of m along an axis of n cells holds cells [b n / m, (b + 1) n / m)).
+// Iteration k = 1, 2, ... of block s computes every cell of s that is not in
+// a boundary layer, in the ray's sweep order.  An upwind corner u of cell p
+// (in the previous plane along the dominant axis, with the periodic wrap) is
+// taken from iteration k when u lies in s and p is not in the first plane of
+// s along the ray (that plane's upwind plane belongs to the upstream block, or
+// is the block's own outflow plane across the periodic wrap); otherwise it is
+// taken from iteration k-1.  Iteration 0 is I = S off the boundary layers and
+// the boundary values on them (the initial ghost plane of the undivided
+// solve).  With one block this is exactly the undivided solve with n_iter
+// boundary iterations.  Every ray and band iterates in lock step; with tol > 0
+// the iteration stops after the first iteration k whose largest intensity
+// change over all cells, rays and bands, max |I_k - I_(k-1)|, is at most tol
+// times the largest |I_k| (n_iter iterations at most).
+
+struct Blocks {
+  int m[3];
+  int lo(int axis, int b, const Desc& D) const { return (int)((int64_t)b * D.n[axis] / m[axis]); }
+  int of(int axis, int v, const Desc& D) const {  // the block holding cell index v
+    int b = (int)((int64_t)v * m[axis] / D.n[axis]);
+    while (b + 1 < m[axis] && lo(axis, b + 1, D) <= v) ++b;
+    while (b > 0 && lo(axis, b, D) > v) --b;
+    return b;
+  }
+};
+
+// One iteration of one ray over every block: Icur from Iprev.  Returns the
+// largest |Icur - Iprev| and the largest |Icur| over the grid.
+std::pair<double, double> block_iteration(const Desc& D, const Ray& r, const Blocks& Bk,
+                                          const double* chi, const double* S,
+                                          const double* Iprev, double* Icur, int nt) {
+  const int na = D.n[r.axis], nA = D.n[r.ea], nB = D.n[r.eb];
+  const double b00 = (1 - r.fa) * (1 - r.fb), b10 = r.fa * (1 - r.fb);
+  const double b01 = (1 - r.fa) * r.fb, b11 = r.fa * r.fb;
+  auto cell = [&](int q, int a, int b) {
+    int c[3];
+    c[r.axis] = q; c[r.ea] = a; c[r.eb] = b;
+    return D.at(c[0], c[1], c[2]);
+  };
+  auto kz = [&](int q, int a, int b) {
+    int c[3];
+    c[r.axis] = q; c[r.ea] = a; c[r.eb] = b;
+    return c[2];
+  };
+  // boundary layers: set
+  for (int q = 0; q < na; ++q)
+    for (int a = 0; a < nA; ++a)
+      for (int b = 0; b < nB; ++b)
+        if (is_bc_layer(D, r, kz(q, a, b))) {
+          const int64_t p = cell(q, a, b);
+          Icur[p] = bc_value(D, r, S[p]);
+        }
+  for (int sq = 0; sq < Bk.m[r.axis]; ++sq)
+    for (int sa = 0; sa < Bk.m[r.ea]; ++sa)
+      for (int sb = 0; sb < Bk.m[r.eb]; ++sb) {
+        const int q0 = Bk.lo(r.axis, sq, D), q1 = Bk.lo(r.axis, sq + 1, D);
+        const int a0 = Bk.lo(r.ea, sa, D), a1e = Bk.lo(r.ea, sa + 1, D);
+        const int bb0 = Bk.lo(r.eb, sb, D), b1e = Bk.lo(r.eb, sb + 1, D);
+        const int first = r.sa > 0 ? q0 : q1 - 1;
+        for (int t = 0; t < q1 - q0; ++t) {
+          const int q = first + r.sa * t;
+          const int qu = wrap(q - r.sa, na);
+          const bool first_plane = t == 0;
+#pragma omp parallel for collapse(2) num_threads(nt) schedule(static)
+          for (int a = a0; a < a1e; ++a)
+            for (int b = bb0; b < b1e; ++b) {
+              if (is_bc_layer(D, r, kz(q, a, b))) continue;
+              const int64_t p = cell(q, a, b);
+              const int a1 = r.ea == 2 ? a - r.sea : wrap(a - r.sea, nA);
+              const int b1 = r.eb == 2 ? b - r.seb : wrap(b - r.seb, nB);
+              const int64_t u00 = cell(qu, a, b), u10 = cell(qu, a1, b);
+              const int64_t u01 = cell(qu, a, b1), u11 = cell(qu, a1, b1);
+              // current iteration only for corners of this block behind its first plane
+              const bool in_a = a1 >= a0 && a1 < a1e, in_b = b1 >= bb0 && b1 < b1e;
+              const double* s00 = first_plane ? Iprev : Icur;
+              const double* s10 = first_plane || !in_a ? Iprev : Icur;
+              const double* s01 = first_plane || !in_b ? Iprev : Icur;
+              const double* s11 = first_plane || !in_a || !in_b ? Iprev : Icur;
+              const double i00 = s00[u00], i10 = s10[u10], i01 = s01[u01], i11 = s11[u11];
+              const double iu = b00 * i00 + b10 * i10 + b01 * i01 + b11 * i11;
+              const double su = b00 * S[u00] + b10 * S[u10] + b01 * S[u01] + b11 * S[u11];
+              const double cu = b00 * chi[u00] + b10 * chi[u10] + b01 * chi[u01] + b11 * chi[u11];
+              const double x = 0.5 * r.ds * (chi[p] + cu);
+              const Wts<double> wt = weights(x);
+              Icur[p] = wt.e * iu + wt.w0 * S[p] + wt.w1 * su;
+            }
+        }
+      }
+  double diff = 0.0, scale = 0.0;
+  for (int64_t p = 0; p < D.cells(); ++p) {
+    diff = std::max(diff, std::fabs(Icur[p] - Iprev[p]));
+    scale = std::max(scale, std::fabs(Icur[p]));
+  }
+  return {diff, scale};
+}
+
+// The decomposed solve of every band and ray; Q, J, Itop as in forward().
+// Iall (optional) receives the final intensities [nb][nr][N]; the return
+// value is the number of iterations run (or -1).
+int forward_blocks(const Desc& D, const Blocks& Bk, const double* chi, const double* S,
+                   double* Q, double* J, double* Itop, double* Iall, int nt) {
+  const int64_t N = D.cells();
+  std::vector<Ray> rays(D.nr);
+  for (int r = 0; r < D.nr; ++r)
+    if (!make_ray(D, D.mu + 3 * r, rays[r])) return -1;
+  const size_t nf = (size_t)D.nb * D.nr;
+  std::vector<std::vector<double>> prev(nf, std::vector<double>(N)), cur(nf, std::vector<double>(N));
+  // iteration 0: I = S, boundary layers at their values
+  for (int b = 0; b < D.nb; ++b)
+    for (int r = 0; r < D.nr; ++r) {
+      std::vector<double>& I0 = prev[(size_t)b * D.nr + r];
+      for (int k = 0; k < D.n[2]; ++k)
+        for (int64_t p = (int64_t)k * D.n[0] * D.n[1]; p < (int64_t)(k + 1) * D.n[0] * D.n[1]; ++p)
+          I0[p] = is_bc_layer(D, rays[r], k) ? bc_value(D, rays[r], S[b * N + p]) : S[b * N + p];
+    }
+  int used = 0;
+  for (int it = 0; it < D.n_iter; ++it) {
+    double diff = 0.0, scale = 0.0;
+    for (int b = 0; b < D.nb; ++b)
+      for (int r = 0; r < D.nr; ++r) {
+        const size_t f = (size_t)b * D.nr + r;
+        const auto ds = block_iteration(D, rays[r], Bk, chi + b * N, S + b * N, prev[f].data(),
+                                        cur[f].data(), nt);
+        diff = std::max(diff, ds.first);
+        scale = std::max(scale, ds.second);
+      }
+    std::swap(prev, cur);  // prev holds iteration it + 1
+    used = it + 1;
+    if (D.tol > 0 && diff <= D.tol * scale) break;
+  }
+  // flux step from the last iteration run
+  const int64_t plane = (int64_t)D.n[0] * D.n[1];
+  int nup = 0;
+  for (int r = 0; r < D.nr; ++r) nup += rays[r].up;
+  for (int64_t p = 0; p < N; ++p) Q[p] = 0.0;
+  std::vector<double> Jb(N);
+  for (int b = 0; b < D.nb; ++b) {
+    for (int64_t p = 0; p < N; ++p) Jb[p] = 0.0;
+    int ru = 0;
+    for (int r = 0; r < D.nr; ++r) {
+      const std::vector<double>& I = prev[(size_t)b * D.nr + r];
+      for (int64_t p = 0; p < N; ++p) Jb[p] += D.w[r] * I[p];
+      if (Iall) std::copy(I.begin(), I.end(), Iall + ((size_t)b * D.nr + r) * N);
+      if (rays[r].up) {
+        if (Itop) {
+          double* dst = Itop + ((int64_t)b * nup + ru) * plane;
+          for (int64_t p = 0; p < plane; ++p) dst[p] = I[(int64_t)(D.n[2] - 1) * plane + p];
+        }
+        ++ru;
+      }
+    }
+    const double qf = 4.0 * kPi * D.qw[b];
+    for (int64_t p = 0; p < N; ++p) Q[p] += qf * chi[b * N + p] * (Jb[p] - S[b * N + p]);
+    if (J) std::memcpy(J + b * N, Jb.data(), sizeof(double) * N);
+  }
+  return used;
+}
+
 Desc make_desc(int nx, int ny, int nz, double dx, double dy, double dz, int nb, int nr,
                const double* mu, const double* w, const double* qw, int bot, int top,
                double ibot, int n_iter) {
@@ -655,6 +826,35 @@ int oracle_ray(int nx, int ny, int nz, double dx, double dy, double dz, const do
   Ray r;
   if (!make_ray(D, mu3, r)) return -1;
   solve_ray<double>(D, r, chi, S, I, nullptr, 1);
+  return 0;
+}
+
+// Forward solve on sub[0] x sub[1] x sub[2] subdomains with lagged exchange
+// between iterations (n_iter iterations, or tol > 0: until the largest
+// intensity change is at most tol of the largest intensity).  Q, J, Itop as in
+// oracle_solve (J, Itop may be null); Iall [nb][nr][N] receives the final
+// intensity of every ray if not null; *iters the iterations run.
+int oracle_solve_sub(int nx, int ny, int nz, double dx, double dy, double dz, int nb, int nr,
+                     const double* mu, const double* w, const double* qw, int bot, int top,
+                     double ibot, int n_iter, const int* sub, double tol, const double* kappa,
+                     const double* rho, const double* S, double* Q, double* J, double* Itop,
+                     double* Iall, int* iters, int nthreads) {
+  Desc D = make_desc(nx, ny, nz, dx, dy, dz, nb, nr, mu, w, qw, bot, top, ibot, n_iter);
+  if (!valid(D) || !(tol >= 0) || !std::isfinite(tol)) return -1;
+  Blocks Bk;
+  for (int a = 0; a < 3; ++a) {
+    if (sub[a] < 1 || sub[a] > D.n[a]) return -1;
+    Bk.m[a] = sub[a];
+  }
+  D.tol = tol;
+  const int64_t N = D.cells();
+  std::vector<double> chi((size_t)nb * N);
+  for (int b = 0; b < nb; ++b)
+    for (int64_t p = 0; p < N; ++p) chi[b * N + p] = kappa[b * N + p] * rho[p];
+  const int used = forward_blocks(D, Bk, chi.data(), S, Q, J, Itop, Iall,
+                                  nthreads > 0 ? nthreads : 1);
+  if (used < 0) return -1;
+  if (iters) *iters = used;
   return 0;
 }
 

@@ -354,6 +354,185 @@ def test_dense_linear_system(oracle_mod, case):
 
 
 # ---------------------------------------------------------------------------
+# Subdomain decomposition with lagged exchange: block Jacobi across blocks,
+# exact sweeps inside a block.  The brute force builds every iteration's
+# cells as one linear system from physical coordinates (upwind point = centre
+# - ds mu, corners by floor, weights from expm1) and decides per corner from
+# the blocks of the two cells whether it is this iteration's value (same
+# block, and the cell not in the block's first plane along the ray) or the
+# previous one's.
+
+
+def _block_lo(n, m, b):
+    return b * n // m
+
+
+def _block_of(n, m, v):
+    return max(b for b in range(m) if _block_lo(n, m, b) <= v)
+
+
+def _dense_blocks_ray(nx, ny, nz, d, m, chi, S, bot, top, i_bot, n_iter, sub):
+    n = (nx, ny, nz)
+    s = [d[a] / abs(m[a]) if m[a] != 0 else math.inf for a in range(3)]
+    ds = min(s)
+    axis = max(a for a in range(3) if s[a] == ds)
+    sgn = 1 if m[axis] > 0 else -1
+    N = nx * ny * nz
+
+    def flat(i, j, k):
+        return (k * ny + j) * nx + i
+
+    def bc(k):
+        if m[2] > 0 and k == 0:
+            return "bot"
+        if m[2] < 0 and k == nz - 1:
+            return "top"
+        return None
+
+    def bc_val(kind, p):
+        if kind == "bot":
+            return S.flat[p] if bot == 0 else i_bot
+        return 0.0 if top == 0 else S.flat[p]
+
+    def block(c):
+        return tuple(_block_of(n[a], sub[a], c[a]) for a in range(3))
+
+    U = n_iter * N
+    A = np.zeros((U, U))
+    rhs = np.zeros(U)
+    for it in range(n_iter):
+        for k in range(nz):
+            for j in range(ny):
+                for i in range(nx):
+                    p = flat(i, j, k)
+                    row = it * N + p
+                    A[row, row] = 1.0
+                    kind = bc(k)
+                    if kind:
+                        rhs[row] = bc_val(kind, p)
+                        continue
+                    bp = block((i, j, k))
+                    c_ax = (i, j, k)[axis]
+                    lo = _block_lo(n[axis], sub[axis], bp[axis])
+                    hi = _block_lo(n[axis], sub[axis], bp[axis] + 1) - 1
+                    first_plane = c_ax == (lo if sgn > 0 else hi)
+                    X = np.array([i * d[0], j * d[1], k * d[2]]) - ds * np.asarray(m)
+                    corners = [([], 1.0)]
+                    for a in range(3):
+                        t = X[a] / d[a]
+                        base = math.floor(t + 1e-9)
+                        fr = t - base
+                        if abs(fr) < 1e-9:
+                            fr = 0.0
+                        new = []
+                        for c, wgt in corners:
+                            new.append((c + [base], wgt * (1 - fr)))
+                            if fr > 0:
+                                new.append((c + [base + 1], wgt * fr))
+                        corners = new
+                    cu = su = 0.0
+                    terms = []
+                    for c, wgt in corners:
+                        ci, cj, ck = c
+                        assert 0 <= ck < nz
+                        cw = (ci % nx, cj % ny, ck)
+                        q = flat(*cw)
+                        cu += wgt * chi.flat[q]
+                        su += wgt * S.flat[q]
+                        terms.append((q, wgt, ck, block(cw) == bp and not first_plane))
+                    x = 0.5 * ds * (chi.flat[p] + cu)
+                    e, w0, w1 = _weights_expm1(x)
+                    rhs[row] = w0 * S.flat[p] + w1 * su
+                    for q, wgt, ck, current in terms:
+                        if current:
+                            A[row, it * N + q] -= e * wgt
+                        elif it == 0:     # iteration 0: I = S, boundary layers at their values
+                            kind_q = bc(ck)
+                            rhs[row] += e * wgt * (bc_val(kind_q, q) if kind_q else S.flat[q])
+                        else:
+                            A[row, (it - 1) * N + q] -= e * wgt
+    sol = np.linalg.solve(A, rhs)
+    return sol[(n_iter - 1) * N:].reshape(nz, ny, nx)
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_subdomains_dense_block_jacobi(oracle_mod, case):
+    nx, ny, nz = 4, 3, 5
+    d = [(1.0, 1.0, 1.0), (1.3, 0.8, 1.1), (1.0, 1.0, 1.0), (0.7, 1.4, 0.9), (2.0, 0.5, 1.0)][case]
+    sub = [(2, 1, 2), (1, 3, 1), (2, 3, 5), (4, 1, 2), (2, 2, 3)][case]
+    n_iter = [1, 2, 3, 2, 3][case]
+    bot, top, ib = [(0, 0, 0.0), (1, 1, 1.7), (0, 1, 0.0), (1, 0, 0.4), (0, 0, 0.0)][case]
+    chi, S = _rand_atm(nx, ny, nz, 40 + case, 0.02, 8.0)
+    mu, w = inputs.s4_quadrature()
+    r = np.random.default_rng(140 + case)
+    dirs = [mu[i] for i in (0, 5, 10, 19, 23)]
+    v = r.standard_normal(3)
+    dirs.append(v / np.linalg.norm(v))
+    dirs = np.array(dirs)
+    wts = np.full(len(dirs), 1.0 / len(dirs))
+    p = _problem(nx, ny, nz, chi, S, *d, bot=bot, top=top, i_bot=ib, n_iter=n_iter, mu=dirs, w=wts)
+    _, _, _, iters, I = oracle_mod.solve_sub(p, sub, want_intensity=True)
+    assert iters == n_iter
+    for ri, m in enumerate(dirs):
+        ref = _dense_blocks_ray(nx, ny, nz, d, m, chi, S, bot, top, ib, n_iter, sub)
+        assert np.allclose(I[0, ri], ref, rtol=1e-11, atol=1e-12), (case, ri)
+
+
+def test_subdomains_single_block_is_the_undivided_solve(oracle_mod):
+    # one block: the lagged values are exactly the ghost planes of the
+    # undivided solve's boundary iterations
+    p = inputs.random_problem(9, 7, 6, seed=150, bands=2, n_iter=3)
+    ref = oracle_mod.solve(p)
+    got = oracle_mod.solve_sub(p, (1, 1, 1))
+    assert got[3] == 3
+    for a, b in zip(got[:3], ref):
+        assert np.array_equal(a, b)
+
+
+def test_subdomains_converge_to_the_undivided_fixed_point(oracle_mod):
+    # many iterations: the decomposed and the undivided solves reach the same
+    # fixed point (the periodic iteration converged in both)
+    p = inputs.random_problem(10, 8, 9, seed=151, bands=1, lo=0.05, hi=3.0, n_iter=150)
+    ref = oracle_mod.solve(p)
+    for sub in ((2, 2, 3), (5, 1, 1), (1, 4, 9)):
+        got = oracle_mod.solve_sub(p, sub)
+        for a, b in zip(got[:3], ref):
+            assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max(), sub
+    # and few iterations do not: the lag is real
+    p.n_iter = 2
+    got = oracle_mod.solve_sub(p, (2, 2, 3))
+    assert np.abs(got[1] - oracle_mod.solve(p)[1]).max() > 1e-6
+
+
+def test_subdomains_tolerance_rule(oracle_mod):
+    # tol > 0 stops after the first iteration k whose largest intensity change
+    # (over every cell, ray and band) is within tol of the largest intensity;
+    # checked against fixed-count runs of k - 1, k and k + 1 iterations
+    p = inputs.random_problem(8, 7, 8, seed=152, bands=2, lo=0.05, hi=3.0, n_iter=40)
+    sub = (2, 1, 2)
+    tol = 1e-6
+    Q, J, It, k = oracle_mod.solve_sub(p, sub, tol=tol)
+    assert 2 <= k < 40
+
+    def field(n):
+        q = inputs.random_problem(8, 7, 8, seed=152, bands=2, lo=0.05, hi=3.0, n_iter=n)
+        return oracle_mod.solve_sub(q, sub, want_intensity=True)
+
+    Ikm2, Ikm1, Ik = field(k - 2)[4] if k > 2 else None, field(k - 1)[4], field(k)
+    change = np.abs(Ik[4] - Ikm1).max()
+    assert change <= tol * np.abs(Ik[4]).max()
+    if Ikm2 is not None:
+        assert np.abs(Ikm1 - Ikm2).max() > tol * np.abs(Ikm1).max()
+    for a, b in zip((Q, J, It), Ik[:3]):
+        assert np.array_equal(a, b)
+    # a huge tolerance stops after one iteration, an unreachable one runs them
+    # all (before the exact fixed point, where the change is 0)
+    assert oracle_mod.solve_sub(p, sub, tol=1e30)[3] == 1
+    p.n_iter = 6
+    assert oracle_mod.solve_sub(p, sub, tol=1e-300)[3] == 6
+
+
+# ---------------------------------------------------------------------------
 # C5 symmetries, C6 linearity and scaling, C7 iteration logic
 
 
