@@ -100,6 +100,24 @@ typedef struct {
                              Needs such a group to be one sweep task (at most four rays, one per
                              in-plane sign pattern, as S4): else RTS_E_UNSUPPORTED at
                              rts_plan_create.  rts_adjoint rejects it (RTS_E_UNSUPPORTED). */
+  int32_t sub[3];         /* subdomain decomposition with lagged exchange (the paper's domain-
+                             decomposed RTS: each subdomain integrates from the boundary
+                             intensities its upwind neighbours produced in the previous
+                             iteration, then passes its outflow intensities downstream).
+                             All 0: the undivided solve above.  Else the box is cut into
+                             sub[0] x sub[1] x sub[2] blocks along x, y, z (0 counts as 1; block
+                             b of m along an axis of n cells holds cells [b n/m, (b+1) n/m),
+                             1 <= sub[a] <= n along each axis), and every ray and band iterates
+                             n_iter times: iteration k sweeps each block from iteration k's
+                             values inside the block and iteration k-1's outside it (and for
+                             the upwind plane of the block's first plane along the ray);
+                             iteration 0 is I = S off the boundary layers.  With tol > 0 the
+                             iterations stop after the first whose largest intensity change over
+                             all cells, rays and bands of the box is at most tol times the
+                             largest intensity.  One block (sub = {1,1,1}) is the undivided
+                             solve with n_iter boundary iterations.  A plan's boxes are all
+                             decomposed or none; a decomposed box has flux = 0 and no adjoint
+                             (RTS_E_UNSUPPORTED). */
 } rts_desc;
 
 typedef struct {

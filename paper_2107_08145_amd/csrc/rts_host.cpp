@@ -41,6 +41,11 @@ template <class Real>
 hipError_t launch_reduce(const char*, const Task*, const BoxGeo&, const BoxPtrs&, hipStream_t);
 
 template <class Real>
+hipError_t launch_block_init(const BlockArgs&, int64_t, hipStream_t);
+template <class Real>
+hipError_t launch_block_sweep(const BlockArgs&, int, hipStream_t);
+
+template <class Real>
 size_t reverse_lds_bytes(int);
 template <class Real>
 const void* reverse_fn(int cols);
@@ -110,6 +115,7 @@ struct Box {
   std::vector<std::array<int, 4>> groups;  // ray index per slot (-1 unused), same for every band
   int64_t chi_off = 0, chiT_off = 0, sT_off = 0;  // Real-element offsets
   int64_t seed_off = 0, seedT_off = 0;            // adjoint seeds [nbands][N], both layouts
+  int64_t btol_off = -1;  // decomposed with tol: 64-bit word offset of [n_iter][2] maxima
 };
 
 struct Plan {
@@ -145,6 +151,11 @@ struct Plan {
   std::vector<WidthClass> rclasses;  // the same for the reverse sweep (threads: padded columns)
   int threads = 64;
   bool uni = true;  // every task's four slots share f1, f2, ds and w
+  // subdomain decomposition: every box of the plan is divided (rts_desc.sub)
+  bool decomposed = false;
+  int max_blocks = 1;      // blocks of the most divided box
+  int64_t max_cells = 0;   // cells of the largest box
+  int max_iter = 1;        // the largest n_iter
   // device-dependent state, filled on first use
   bool dev_ready = false;
   int device = -1, cus = 0, occupancy_blocks = 0;
@@ -166,6 +177,9 @@ struct Plan {
 };
 
 bool finite(double v) { return std::isfinite(v); }
+
+// A box cut into subdomains with lagged exchange (rts_desc.sub).
+bool decomposed(const rts_desc& d) { return d.sub[0] > 0 || d.sub[1] > 0 || d.sub[2] > 0; }
 
 int validate_desc(const rts_desc& d) {
   const rts_grid& g = d.g;
@@ -191,6 +205,10 @@ int validate_desc(const rts_desc& d) {
   if (d.qweight)
     for (int b = 0; b < d.nbands; ++b)
       if (!finite(d.qweight[b])) return RTS_E_ARG;
+  const int n3[3] = {g.nx, g.ny, g.nz};
+  for (int a = 0; a < 3; ++a)
+    if (d.sub[a] < 0 || d.sub[a] > n3[a]) return RTS_E_ARG;
+  if (decomposed(d) && d.flux) return RTS_E_UNSUPPORTED;
   if (d.nbands > 16 || d.nrays > 64) return RTS_E_UNSUPPORTED;
   if (g.nx > kMaxCols || g.ny > kMaxCols) return RTS_E_UNSUPPORTED;
   if ((int64_t)g.nx * g.ny * g.nz > ((int64_t)1 << 31)) return RTS_E_UNSUPPORTED;
@@ -353,12 +371,33 @@ void build_layout(Plan& P) {
     off = align_up(off + (size_t)T.strips * 2 * 2 * kMaxRaysPerTask * T.n_cols * words * sizeof(uint64_t));
   }
   for (Task& T : P.tasks) {  // tolerance-driven laps: per-lap maxima and arrival counts
-    T.tol = T.z_planes ? 0.0 : P.boxes[T.box].d.tol;
+    T.tol = T.z_planes || P.decomposed ? 0.0 : P.boxes[T.box].d.tol;
     T.tolw_off = -1;
     if (T.tol > 0) {
       T.tolw_off = (int64_t)(off / sizeof(uint64_t));
       off = align_up(off + (size_t)T.laps * 3 * sizeof(uint64_t));
     }
+  }
+  // decomposed boxes with a tolerance: the box's per-iteration maxima (zeroed by every call)
+  for (Box& B : P.boxes) {
+    B.btol_off = -1;
+    if (P.decomposed && B.d.tol > 0) {
+      B.btol_off = (int64_t)(off / sizeof(uint64_t));
+      off = align_up(off + (size_t)B.d.n_iter * 2 * sizeof(uint64_t));
+    }
+  }
+  P.max_blocks = 1;
+  P.max_cells = 0;
+  P.max_iter = 1;
+  for (Task& T : P.tasks) {  // blocks along the task's cols, rows and planes
+    const rts_desc& d = P.boxes[T.box].d;
+    for (int m = 0; m < 3; ++m) T.nblk[m] = P.decomposed ? std::max(1, d.sub[T.frame[m]]) : 1;
+    T.btol_off = P.boxes[T.box].btol_off;
+    T.iters = d.n_iter;
+    if (P.decomposed) T.tol = d.tol;
+    P.max_blocks = std::max(P.max_blocks, T.nblk[0] * T.nblk[1] * T.nblk[2]);
+    P.max_cells = std::max(P.max_cells, P.boxes[T.box].N);
+    P.max_iter = std::max(P.max_iter, (int)d.n_iter);
   }
   P.off_tasks = off;
   off = align_up(off + sizeof(Task) * P.tasks.size());
@@ -389,7 +428,11 @@ void build_layout(Plan& P) {
     off = align_up(off + (size_t)B.N * esz);
     T.n_cells = B.N;
     T.gbuf_off = -1;
-    if (T.tol > 0) {  // the previous last plane of the strips' rows, every slot
+    T.dfield_off = -1;
+    if (P.decomposed) {  // D of every slot and cell, two iteration parities
+      T.dfield_off = (int64_t)(off / esz);
+      off = align_up(off + 2 * (size_t)kMaxRaysPerTask * B.N * esz);
+    } else if (T.tol > 0) {  // the previous last plane of the strips' rows, every slot
       T.gbuf_off = (int64_t)(off / esz);
       off = align_up(off + (size_t)T.n_rows * T.n_cols * kMaxRaysPerTask * esz);
     }
@@ -645,6 +688,29 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
     RTS_HIP(launch_prep<Real>(in[b].kappa, in[b].rho, in[b].S, ws, B.chi_off, B.chiT_off,
                               B.sT_off, B.d.g.nx, B.d.g.ny, B.d.g.nz, B.d.nbands, st));
   }
+  if (P.decomposed) {
+    // subdomains with lagged exchange: iteration 0's field, then one launch
+    // per iteration (the launch boundary is the exchange), then the reduce
+    if (!out || store) return RTS_E_UNSUPPORTED;
+    BlockArgs b;
+    std::memset(&b, 0, sizeof(b));
+    b.ws = ws;
+    b.tasks = reinterpret_cast<const Task*>(ws + P.off_tasks);
+    b.ntasks = (int)P.tasks.size();
+    for (size_t i = 0; i < P.boxes.size(); ++i)
+      b.box[i] = BoxPtrs{in[i].kappa, in[i].rho, in[i].S, out[i].Q, out[i].J, out[i].I_top,
+                         nullptr, nullptr};
+    RTS_HIP(launch_block_init<Real>(b, P.max_cells, st));
+    if (ev) RTS_HIP(hipEventRecordWithFlags(ev[1], st, ev_flags));
+    for (int it = 0; it < P.max_iter; ++it) {
+      b.iter = it;
+      RTS_HIP(launch_block_sweep<Real>(b, P.max_blocks, st));
+    }
+    if (ev) RTS_HIP(hipEventRecordWithFlags(ev[2], st, ev_flags));
+    for (size_t i = 0; i < P.boxes.size(); ++i)
+      RTS_HIP(launch_reduce<Real>(ws, b.tasks, box_geo(P, i), b.box[i], st));
+    return RTS_OK;
+  }
   SweepArgs a;
   std::memset(&a, 0, sizeof(a));
   a.ws = ws;
@@ -772,7 +838,8 @@ int prepare(Plan* P) {
     rc = P->prec == RTS_FP32 ? occupancy<float>(*P) : occupancy<double>(*P);
     if (rc) return rc;
     for (const Plan::WidthClass& c : P->wclasses)
-      if (c.blocks < 1 || c.blocks * P->cus < c.max_strips) {
+      // (a decomposed plan has no co-resident strips: its workgroups never wait)
+      if (!P->decomposed && (c.blocks < 1 || c.blocks * P->cus < c.max_strips)) {
         P->occupancy_blocks = 0;
         g_last_hip = "the strips of one sweep task cannot all be resident; use more rows per strip";
         return RTS_E_UNSUPPORTED;
@@ -966,8 +1033,10 @@ int autotune_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* ou
   int rc = check_call(P, nbox, in, out, ws, SIZE_MAX);  // the size is checked per candidate
   if (rc) return rc;
   if ((rc = dev_init(*P))) return rc;
-  const std::string key = tune_key(*P, P->device);
   *tried = 0;
+  // a decomposed plan has no strip schedule to choose: its launches do not depend on it
+  if (P->decomposed) return RTS_OK;
+  const std::string key = tune_key(*P, P->device);
   rts_schedule cached;
   if (tune_lookup(key, &cached)) {
     set_sched(P, cached);
@@ -1033,8 +1102,14 @@ int rts_plan_create(const rts_desc* descs, int32_t nbox, void** out) {
       if (rc) return rc;
       if (descs[b].prec != descs[0].prec) return RTS_E_ARG;
     }
+    for (int b = 1; b < nbox; ++b)
+      if (decomposed(descs[b]) != decomposed(descs[0])) {
+        g_last_hip = "a plan's boxes are all decomposed into subdomains or none";
+        return RTS_E_UNSUPPORTED;
+      }
     Plan* P = new Plan();
     P->prec = descs[0].prec;
+    P->decomposed = decomposed(descs[0]);
     P->esz = P->prec == RTS_FP32 ? 4 : 8;
     P->sched.rows_per_strip = P->prec == RTS_FP32 ? 4 : 2;  // measured best on MI355X
     for (int b = 0; b < nbox; ++b) {
@@ -1070,7 +1145,8 @@ int rts_plan_create(const rts_desc* descs, int32_t nbox, void** out) {
         }
       }
       // with a tolerance the rays of a group stop together: one sweep task each
-      if (B.d.tol > 0)
+      // (a decomposed box stops all its rays together)
+      if (B.d.tol > 0 && !decomposed(B.d))
         for (auto& k : keys)
           if (k.first != 2 && grp[k].size() > 1) {
             g_last_hip = "tol > 0 needs at most four rays per dominant axis and direction, "
@@ -1151,6 +1227,10 @@ int adjoint_checks(Plan* P, int32_t nbox, const rts_inputs* in, void* ws, size_t
   if (nbox != (int)P->boxes.size() || !in) return RTS_E_ARG;
   for (int b = 0; b < nbox; ++b)
     if (!in[b].kappa || !in[b].rho || !in[b].S) return RTS_E_ARG;
+  if (P->decomposed) {
+    g_last_hip = "no adjoint of a solve decomposed into subdomains";
+    return RTS_E_UNSUPPORTED;
+  }
   for (int b = 0; b < nbox; ++b)
     if (P->boxes[b].d.tol > 0) {  // the reverse sweep replays a fixed number of laps
       g_last_hip = "the adjoint needs a fixed sweep count (tol = 0)";

@@ -62,6 +62,13 @@ struct Task {
   int32_t n_unrolled;      // planes u of the unrolled sweep (u = 0 first plane after the ghost,
                            // or the boundary plane when planes are z)
   int32_t pad;
+  int32_t nblk[3];         // subdomain decomposition: blocks along cols, rows and planes (all 1
+                           // when the box is not divided)
+  int32_t iters;           // decomposed box: its iteration count (n_iter)
+  int64_t dfield_off;      // decomposed box: element offset of this task's D of every slot and
+                           // cell for the two iteration parities [2][slot][plane][row][col]
+  int64_t btol_off;        // decomposed box with tol: 64-bit word offset of the box's per-
+                           // iteration maxima [iterations][2] (change, intensity)
   double pl_a, pl_b;       // boundary-plane value D = pl_a * S + pl_b (z_planes)
   double bu_a, bu_b;       // boundary row 0 of even slots (rows are z, mu_z > 0)
   double bd_a, bd_b;       // boundary row n_rows-1 of odd slots (rows are z, mu_z < 0)
@@ -136,6 +143,15 @@ struct WsHeader {
   int32_t pad[28];
 };
 static_assert(sizeof(WsHeader) == 256, "workspace header is 256 bytes");
+
+// One iteration of a decomposed solve (rts_block_sweep): every (task, block).
+struct BlockArgs {
+  char* ws;
+  const Task* tasks;       // in the workspace
+  int32_t ntasks;
+  int32_t iter;            // iteration 0, 1, ... (tasks of boxes with fewer iterations return)
+  BoxPtrs box[kMaxBoxes];
+};
 
 struct SweepArgs {
   char* ws;                // workspace base

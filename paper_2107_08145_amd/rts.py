@@ -47,7 +47,8 @@ class Desc(ctypes.Structure):
                 ("mu", ctypes.POINTER(ctypes.c_double)), ("w", ctypes.POINTER(ctypes.c_double)),
                 ("qweight", ctypes.POINTER(ctypes.c_double)), ("bot", ctypes.c_int32),
                 ("top", ctypes.c_int32), ("i_bot", ctypes.c_double), ("n_iter", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("flux", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("prec", ctypes.c_int32), ("flux", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("sub", ctypes.c_int32 * 3)]
 
 
 class Inputs(ctypes.Structure):
@@ -158,9 +159,11 @@ def _stream_ptr(stream=None):
 class Plan:
     """A librts plan for one or more boxes (paper_2107_08145_amd.inputs.Problem)."""
 
-    def __init__(self, problems, prec: int = RTS_FP64, flux=False, tol: float = 0.0):
+    def __init__(self, problems, prec: int = RTS_FP64, flux=False, tol: float = 0.0, sub=None):
         """flux: bool, or one bool per box (desc.flux: room for the flux vector);
-        tol: desc.tol of every box (0: n_iter sweeps; > 0: tolerance-driven)."""
+        tol: desc.tol of every box (0: n_iter sweeps; > 0: tolerance-driven);
+        sub: desc.sub, (mx, my, mz) subdomains with lagged exchange, or None (undivided),
+        for every box, or a list with one such entry per box."""
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
         flags = list(flux) if isinstance(flux, (list, tuple)) else [flux] * len(problems)
@@ -182,6 +185,9 @@ class Plan:
             d.bot, d.top, d.i_bot, d.n_iter, d.prec = p.bot, p.top, p.i_bot, p.n_iter, prec
             d.flux = 1 if flags[i] else 0
             d.tol = float(tol)
+            sb = sub[i] if isinstance(sub, list) else sub
+            if sb is not None:
+                d.sub[0], d.sub[1], d.sub[2] = (int(v) for v in sb)
         h = ctypes.c_void_p()
         _check(lib().rts_plan_create(descs, len(problems), ctypes.byref(h)), "rts_plan_create")
         self.handle = h
@@ -342,11 +348,12 @@ class Plan:
 
 
 def solve(p, prec: int = RTS_FP64, plan: Plan | None = None, flux: bool = False,
-          tol: float = 0.0):
+          tol: float = 0.0, sub=None):
     """Forward solve of one problem on the current GPU; returns numpy (Q, J, I_top), or
-    (Q, J, I_top, F, QF) with flux; tol > 0: tolerance-driven boundary iteration."""
+    (Q, J, I_top, F, QF) with flux; tol > 0: tolerance-driven boundary iteration; sub:
+    (mx, my, mz) subdomains with lagged exchange."""
     import torch
-    plan = plan or Plan(p, prec, flux=flux, tol=tol)
+    plan = plan or Plan(p, prec, flux=flux, tol=tol, sub=sub)
     ins = plan.device_inputs(p)
     outs = plan.new_outputs(p, want_flux=flux)
     plan.solve_into([ins], [outs])
