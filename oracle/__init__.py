@@ -46,6 +46,7 @@ def _load():
         head = [i, i, i, d, d, d, i, i, p, p, p, i, i, d, i]
         lib.oracle_solve.argtypes = head + [p, p, p, p, p, p, i]
         lib.oracle_solve_chi.argtypes = head + [p, p, p, p, p, i]
+        lib.oracle_solve_dform.argtypes = head + [p, p, p, p, p, p]
         lib.oracle_flux.argtypes = head + [p, p, p, p, p, p, p, p, i]
         lib.oracle_flux_divergence.argtypes = [i, i, i, d, d, d, p, p]
         lib.oracle_solve_tol.argtypes = head + [d, p, p, p, p, p, p, p, p, p, i]
@@ -54,7 +55,7 @@ def _load():
         lib.oracle_ray.argtypes = [i, i, i, d, d, d, p, i, i, d, i, p, p, p]
         lib.oracle_weights.argtypes = [d, p, p, p, p]
         lib.oracle_solve_sub.argtypes = head + [p, d, p, p, p, p, p, p, p, p, i]
-        for f in ("oracle_solve", "oracle_solve_chi", "oracle_adjoint",
+        for f in ("oracle_solve", "oracle_solve_chi", "oracle_solve_dform", "oracle_adjoint",
                   "oracle_complex_step", "oracle_ray", "oracle_flux", "oracle_flux_divergence",
                   "oracle_solve_tol", "oracle_solve_sub"):
             getattr(lib, f).restype = i
@@ -98,6 +99,23 @@ def solve(p, threads: int = 1, chi=None):
     else:
         c = _f64(chi)
         rc = lib.oracle_solve_chi(*head, _ptr(c), _ptr(S), _ptr(Q), _ptr(J), _ptr(It), threads)
+    if rc:
+        raise ValueError("oracle rejected the problem")
+    del keep
+    return Q, J, It
+
+
+def solve_dform(p):
+    """The second oracle mode: the same scheme swept as D = I - S (serial);
+    returns (Q, J, I_top) as solve()."""
+    lib = _load()
+    keep, head = _head(p)
+    B = p.nbands
+    Q = np.empty((p.nz, p.ny, p.nx))
+    J = np.empty((B, p.nz, p.ny, p.nx))
+    It = np.empty((B, p.n_up, p.ny, p.nx))
+    kap, rho, S = _f64(p.kappa), _f64(p.rho), _f64(p.S)
+    rc = lib.oracle_solve_dform(*head, _ptr(kap), _ptr(rho), _ptr(S), _ptr(Q), _ptr(J), _ptr(It))
     if rc:
         raise ValueError("oracle rejected the problem")
     del keep

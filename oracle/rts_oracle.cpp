@@ -369,6 +369,127 @@ int forward(const Desc& D, const T* chi, const T* S, T* Q, T* J, T* Itop, int nt
   return 0;
 }
 
+// Second oracle mode: the same discrete scheme written for D = I - S.  With
+// e + w0 + w1 = 1 and the bilinear interpolation being linear, the linear-
+// source update becomes D_p = e B(D) + c (B(S) - S_p), c = (1 - e)/x.  This is
+// a separate implementation of every step (boundary values, ghost plane,
+// sweep, flux step) so that agreement with forward() checks the identity.
+//   Boundary layers: D = I_bc - S (0 for a thermal bottom, i_bot - S for a
+//   fixed one, -S for a zero top, 0 for a thermal top); initial ghost D = 0
+//   off the boundary layer; J_b = (sum_r w_r) S_b + sum_r w_r D_r, Q from
+//   J_b - S_b = (sum_r w_r - 1) S_b + sum_r w_r D_r; I_top = S + D.
+double c_weight(double x) {
+  if (x < 0.1) {  // sum_{n>=0} (-x)^n / (n+1)!, through n = 12
+    double term = 1.0, s = 0.0;
+    for (int n = 0; n <= 12; ++n) {
+      s += term;
+      term *= -x / double(n + 2);
+    }
+    return s;
+  }
+  return -std::expm1(-x) / x;
+}
+
+int forward_dform(const Desc& D, const double* chi, const double* S, double* Q, double* J,
+                  double* Itop) {
+  const int64_t N = D.cells();
+  const int64_t plane = (int64_t)D.n[0] * D.n[1];
+  std::vector<Ray> rays(D.nr);
+  for (int r = 0; r < D.nr; ++r)
+    if (!make_ray(D, D.mu + 3 * r, rays[r])) return -1;
+  double wsum = 0.0;
+  for (int r = 0; r < D.nr; ++r) wsum += D.w[r];
+  int nup = 0;
+  for (int r = 0; r < D.nr; ++r) nup += rays[r].up;
+  for (int64_t p = 0; p < N; ++p) Q[p] = 0.0;
+  std::vector<double> Dv(N), dJ(N), ghost;
+  for (int b = 0; b < D.nb; ++b) {
+    const double* cb = chi + b * N;
+    const double* sb = S + b * N;
+    for (int64_t p = 0; p < N; ++p) dJ[p] = 0.0;
+    int ru = 0;
+    for (int r = 0; r < D.nr; ++r) {
+      const Ray& R = rays[r];
+      const int na = D.n[R.axis], nA = D.n[R.ea], nB = D.n[R.eb];
+      const bool periodic = R.axis != 2;
+      auto cell = [&](int q, int a, int bb) {
+        int c[3];
+        c[R.axis] = q; c[R.ea] = a; c[R.eb] = bb;
+        return D.at(c[0], c[1], c[2]);
+      };
+      auto bc_layer = [&](int64_t p) {
+        const int k = (int)(p / plane);
+        return R.up ? k == 0 : k == D.n[2] - 1;
+      };
+      auto bc_d = [&](int64_t p) {
+        if (R.up) return D.bot == 0 ? 0.0 : D.ibot - sb[p];
+        return D.top == 0 ? -sb[p] : 0.0;
+      };
+      for (int64_t p = 0; p < N; ++p) Dv[p] = bc_layer(p) ? bc_d(p) : 0.0;
+      const int q_first = R.sa > 0 ? 0 : na - 1, q_last = R.sa > 0 ? na - 1 : 0;
+      if (periodic) {
+        ghost.assign((size_t)nA * nB, 0.0);
+        for (int a = 0; a < nA; ++a)
+          for (int bb = 0; bb < nB; ++bb) {
+            const int64_t p = cell(q_last, a, bb);
+            if (bc_layer(p)) ghost[(size_t)a * nB + bb] = bc_d(p);
+          }
+      }
+      const double w00 = (1 - R.fa) * (1 - R.fb), w10 = R.fa * (1 - R.fb);
+      const double w01 = (1 - R.fa) * R.fb, w11 = R.fa * R.fb;
+      const int sweeps = periodic ? D.n_iter : 1;
+      for (int it = 0; it < sweeps; ++it) {
+        for (int t = periodic ? 0 : 1; t < na; ++t) {
+          const int q = q_first + R.sa * t;
+          const int qu = wrap(q - R.sa, na);
+          for (int a = 0; a < nA; ++a)
+            for (int bb = 0; bb < nB; ++bb) {
+              const int64_t p = cell(q, a, bb);
+              if (bc_layer(p)) continue;
+              const int a1 = R.ea == 2 ? a - R.sea : wrap(a - R.sea, nA);
+              const int b1 = R.eb == 2 ? bb - R.seb : wrap(bb - R.seb, nB);
+              const int64_t u[4] = {cell(qu, a, bb), cell(qu, a1, bb), cell(qu, a, b1),
+                                    cell(qu, a1, b1)};
+              double du[4];
+              if (periodic && t == 0) {
+                du[0] = ghost[(size_t)a * nB + bb];
+                du[1] = ghost[(size_t)a1 * nB + bb];
+                du[2] = ghost[(size_t)a * nB + b1];
+                du[3] = ghost[(size_t)a1 * nB + b1];
+              } else {
+                for (int m = 0; m < 4; ++m) du[m] = Dv[u[m]];
+              }
+              const double bd = w00 * du[0] + w10 * du[1] + w01 * du[2] + w11 * du[3];
+              const double bs = w00 * sb[u[0]] + w10 * sb[u[1]] + w01 * sb[u[2]] + w11 * sb[u[3]];
+              const double bx = w00 * cb[u[0]] + w10 * cb[u[1]] + w01 * cb[u[2]] + w11 * cb[u[3]];
+              const double x = 0.5 * R.ds * (cb[p] + bx);
+              Dv[p] = std::exp(-x) * bd + c_weight(x) * (bs - sb[p]);
+            }
+        }
+        if (periodic)
+          for (int a = 0; a < nA; ++a)
+            for (int bb = 0; bb < nB; ++bb) ghost[(size_t)a * nB + bb] = Dv[cell(q_last, a, bb)];
+      }
+      for (int64_t p = 0; p < N; ++p) dJ[p] += D.w[r] * Dv[p];
+      if (R.up) {
+        if (Itop) {
+          double* dst = Itop + ((int64_t)b * nup + ru) * plane;
+          const int64_t top = (int64_t)(D.n[2] - 1) * plane;
+          for (int64_t p = 0; p < plane; ++p) dst[p] = sb[top + p] + Dv[top + p];
+        }
+        ++ru;
+      }
+    }
+    const double qf = 4.0 * kPi * D.qw[b];
+    for (int64_t p = 0; p < N; ++p) {
+      const double djs = (wsum - 1.0) * sb[p] + dJ[p];
+      Q[p] += qf * cb[p] * djs;
+      if (J) J[b * N + p] = sb[p] + djs;
+    }
+  }
+  return 0;
+}
+
 // Reverse-mode derivative of forward() for T = double.
 int adjoint(const Desc& D, const double* chi, const double* S, const double* gQ,
             const double* gJ, const double* gItop, double* dS, double* dchi, int nt) {
@@ -759,6 +880,20 @@ int oracle_solve(int nx, int ny, int nz, double dx, double dy, double dz, int nb
     for (int64_t p = 0; p < N; ++p) chi[b * N + p] = kappa[b * N + p] * rho[p];
   return forward<double>(D, chi.data(), S, Q, J, Itop, nthreads > 0 ? nthreads : 1, nullptr,
                          nullptr);
+}
+
+// The D-form second mode (forward_dform): inputs and outputs as oracle_solve.
+int oracle_solve_dform(int nx, int ny, int nz, double dx, double dy, double dz, int nb, int nr,
+                       const double* mu, const double* w, const double* qw, int bot, int top,
+                       double ibot, int n_iter, const double* kappa, const double* rho,
+                       const double* S, double* Q, double* J, double* Itop) {
+  Desc D = make_desc(nx, ny, nz, dx, dy, dz, nb, nr, mu, w, qw, bot, top, ibot, n_iter);
+  if (!valid(D)) return -1;
+  const int64_t N = D.cells();
+  std::vector<double> chi((size_t)nb * N);
+  for (int b = 0; b < nb; ++b)
+    for (int64_t p = 0; p < N; ++p) chi[b * N + p] = kappa[b * N + p] * rho[p];
+  return forward_dform(D, chi.data(), S, Q, J, Itop);
 }
 
 // Forward solve with the radiative flux vector F [3][N] (x, y, z components,

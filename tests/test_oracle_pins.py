@@ -536,6 +536,36 @@ def test_subdomains_tolerance_rule(oracle_mod):
 # C5 symmetries, C6 linearity and scaling, C7 iteration logic
 
 
+@pytest.mark.parametrize("case", [
+    dict(shape=(7, 6, 8), seed=31),
+    dict(shape=(6, 9, 5), seed=32, bands=2, bot=1, i_bot=3.0, top=1, n_iter=2),
+    dict(shape=(8, 5, 7), seed=33, lo=1e-4, hi=1e4, n_iter=4),
+    dict(shape=(5, 6, 9), seed=34, general=True),
+])
+def test_dform_second_mode_agrees_with_iform(oracle_mod, case):
+    # The D = I - S sweep (a separate implementation of boundary values, ghost
+    # plane, recursion and flux step) is the same scheme by the identity
+    # e + w0 + w1 = 1: Q per cell within 1e-10 relative (plus the I-form's own
+    # J - S cancellation, 1e-13 of 4 pi chi S), J and I_top within 1e-13 of max.
+    # Random directions with weights not summing to one test the (sum w - 1) S term.
+    c = dict(case)
+    shape, seed, general = c.pop("shape"), c.pop("seed"), c.pop("general", False)
+    p = inputs.random_problem(*shape, seed=seed, **c)
+    if general:
+        r = np.random.default_rng(seed)
+        mu = r.standard_normal((7, 3))
+        p.mu = mu / np.linalg.norm(mu, axis=1, keepdims=True)
+        p.w = r.uniform(0.05, 0.3, 7)
+        p.dx, p.dy, p.dz = 1.3, 0.8, 1.1
+    Qi, Ji, Ii = oracle_mod.solve(p)
+    Qd, Jd, Id = oracle_mod.solve_dform(p)
+    chi = oracle_mod.chi_of(p)
+    floor = 4 * math.pi * (np.abs(chi) * np.abs(p.S)).max(axis=0) * 1e-13
+    assert np.all(np.abs(Qd - Qi) <= 1e-10 * np.abs(Qi) + floor)
+    assert np.abs(Jd - Ji).max() <= 1e-13 * np.abs(Ji).max()
+    assert np.abs(Id - Ii).max() <= 1e-13 * np.abs(Ii).max()
+
+
 def test_mirror_and_transpose_symmetry(oracle_mod):
     n, nz = 6, 5
     kap, S = _rand_atm(n, n, nz, 3, 0.05, 20.0)
