@@ -96,9 +96,11 @@ __global__ __launch_bounds__(256) void rts_block_sweep(BlockArgs A) {
   const Real* chi = reinterpret_cast<const Real*>(A.ws) + T.chi_off;
   const Real* Sv = T.transposed ? reinterpret_cast<const Real*>(A.ws) + T.s_off
                                 : reinterpret_cast<const Real*>(A.box[T.box].S) + T.s_off;
-  Real* Dcur = reinterpret_cast<Real*>(A.ws) + T.dfield_off + (int64_t)(A.iter & 1) * R * N;
+  // launch A.iter computes iteration A.iter + 1 from iteration A.iter (iteration
+  // 0 is rts_block_init's field, parity 0)
+  Real* Dcur = reinterpret_cast<Real*>(A.ws) + T.dfield_off + (int64_t)((A.iter + 1) & 1) * R * N;
   const Real* Dprv = reinterpret_cast<const Real*>(A.ws) + T.dfield_off +
-                     (int64_t)((A.iter + 1) & 1) * R * N;
+                     (int64_t)(A.iter & 1) * R * N;
   Real* P = reinterpret_cast<Real*>(A.ws) + T.part_off;
   Real* Itop = reinterpret_cast<Real*>(A.box[T.box].I_top);
   // per-slot constants; FP32 folds log2(e) into ds/2 (rts_exp_step)

@@ -671,11 +671,32 @@ BoxGeo box_geo(const Plan& P, size_t b) {
 // With out == nullptr (the forward pass of the adjoint) the sweep also stores
 // D of every plane, writes no I_top and the reduce is skipped; with store the
 // sweep stores D as well as writing the outputs (rts_solve_for_adjoint).
+// Marks 1 and 2 bracket the sweep launches: an eager timed call records its
+// events there, a timed graph capture cuts its segments there.
+struct Marks {
+  hipEvent_t* ev = nullptr;          // eager: events [4], marks record ev[1], ev[2]
+  hipStream_t cap = nullptr;         // capture: the capturing stream
+  std::vector<hipGraph_t>* segs = nullptr;  // capture: the segments ended so far
+  int mark(int i, hipStream_t st) const {
+    if (ev) {
+      RTS_HIP(hipEventRecord(ev[i], st));
+      return RTS_OK;
+    }
+    if (!segs) return RTS_OK;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cap, &g);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    segs->push_back(g);
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    return RTS_OK;
+  }
+};
+
 template <class Real>
 int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char* ws,
-                    hipStream_t st, hipEvent_t* ev, bool store = false, bool ev_ext = false) {
-  // (under graph capture the sweep's events become event-record nodes)
-  const unsigned ev_flags = ev_ext ? hipEventRecordExternal : hipEventRecordDefault;
+                    hipStream_t st, const Marks* mk, bool store = false) {
+  int mrc = RTS_OK;
   // header and exchange buffers to zero
   RTS_HIP(launch_zero(reinterpret_cast<int*>(ws),
                       (int64_t)((P.off_tasks) / sizeof(int32_t)), st));
@@ -701,12 +722,12 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
       b.box[i] = BoxPtrs{in[i].kappa, in[i].rho, in[i].S, out[i].Q, out[i].J, out[i].I_top,
                          nullptr, nullptr};
     RTS_HIP(launch_block_init<Real>(b, P.max_cells, st));
-    if (ev) RTS_HIP(hipEventRecordWithFlags(ev[1], st, ev_flags));
+    if (mk && (mrc = mk->mark(1, st))) return mrc;
     for (int it = 0; it < P.max_iter; ++it) {
       b.iter = it;
       RTS_HIP(launch_block_sweep<Real>(b, P.max_blocks, st));
     }
-    if (ev) RTS_HIP(hipEventRecordWithFlags(ev[2], st, ev_flags));
+    if (mk && (mrc = mk->mark(2, st))) return mrc;
     for (size_t i = 0; i < P.boxes.size(); ++i)
       RTS_HIP(launch_reduce<Real>(ws, b.tasks, box_geo(P, i), b.box[i], st));
     return RTS_OK;
@@ -734,7 +755,7 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
   // count; tickets are claimed in order, hence with that many resident
   // workgroups the tasks being worked on always make progress.
   if (P.wclasses.size() > (size_t)kMaxWidths) return RTS_E_UNSUPPORTED;  // (widths <= kMaxCols)
-  if (ev) RTS_HIP(hipEventRecordWithFlags(ev[1], st, ev_flags));
+  if (mk && (mrc = mk->mark(1, st))) return mrc;
   for (size_t k = 0; k < P.wclasses.size(); ++k) {
     const Plan::WidthClass& c = P.wclasses[k];
     a.queue = reinterpret_cast<const int32_t*>(ws + P.off_queue) + 2 * c.q0;
@@ -747,7 +768,7 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
     grid = std::max(1, std::min(grid, c.strips));
     RTS_HIP(launch_sweep<Real>(P, c, a, grid, st));
   }
-  if (ev) RTS_HIP(hipEventRecordWithFlags(ev[2], st, ev_flags));
+  if (mk && (mrc = mk->mark(2, st))) return mrc;
   if (!out) return RTS_OK;
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     const BoxGeo G = box_geo(P, b);
@@ -880,9 +901,11 @@ int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
   hipEvent_t* ev = nullptr;
   if ((rc = next_events(P, &ev))) return rc;
   if (!graph) {
+    Marks mk;
+    mk.ev = ev;
     if (ev) RTS_HIP(hipEventRecord(ev[0], st));
-    rc = P->prec == RTS_FP32 ? enqueue_forward<float>(*P, in, out, (char*)ws, st, ev)
-                             : enqueue_forward<double>(*P, in, out, (char*)ws, st, ev);
+    rc = P->prec == RTS_FP32 ? enqueue_forward<float>(*P, in, out, (char*)ws, st, ev ? &mk : nullptr)
+                             : enqueue_forward<double>(*P, in, out, (char*)ws, st, ev ? &mk : nullptr);
     if (rc) return rc;
     if (ev) {
       RTS_HIP(hipEventRecord(ev[3], st));
@@ -903,51 +926,60 @@ int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
     if (!P->cap_stream) RTS_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
     if (timed && !P->cap_ev[0])
       for (auto& e : P->cap_ev) RTS_HIP(hipEventCreate(&e));
+    // A timed graph is captured in three segments (before, during and after
+    // the sweep launches) and assembled as child graphs between explicit
+    // event-record nodes; an untimed graph is one capture.
+    std::vector<hipGraph_t> segs;
+    Marks mk;
+    mk.cap = P->cap_stream;
+    mk.segs = &segs;
+    auto drop_segs = [&]() {
+      for (hipGraph_t x : segs) (void)hipGraphDestroy(x);
+      segs.clear();
+    };
     RTS_HIP(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
-    // event-record nodes (external events: their timestamps are kept), whose
-    // events are re-pointed before each timed replay
-    hipError_t e0 = timed ? hipEventRecordWithFlags(P->cap_ev[0], P->cap_stream, hipEventRecordExternal)
-                          : hipSuccess;
-    rc = e0 != hipSuccess ? hip_fail(e0, "hipEventRecordWithFlags")
-         : P->prec == RTS_FP32
-             ? enqueue_forward<float>(*P, in, out, (char*)ws, P->cap_stream, timed ? P->cap_ev : nullptr, false, true)
-             : enqueue_forward<double>(*P, in, out, (char*)ws, P->cap_stream, timed ? P->cap_ev : nullptr, false, true);
-    if (!rc && timed) {
-      e0 = hipEventRecordWithFlags(P->cap_ev[3], P->cap_stream, hipEventRecordExternal);
-      if (e0 != hipSuccess) rc = hip_fail(e0, "hipEventRecordWithFlags");
-    }
+    rc = P->prec == RTS_FP32
+             ? enqueue_forward<float>(*P, in, out, (char*)ws, P->cap_stream, timed ? &mk : nullptr)
+             : enqueue_forward<double>(*P, in, out, (char*)ws, P->cap_stream, timed ? &mk : nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
-    if (rc) {
+    if (rc || e != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
-      return rc;
+      drop_segs();
+      return rc ? rc : hip_fail(e, "hipStreamEndCapture");
     }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    if (timed) {  // the event-record nodes, by the event each records
-      size_t n = 0;
-      RTS_HIP(hipGraphGetNodes(g, nullptr, &n));
-      std::vector<hipGraphNode_t> nodes(n);
-      RTS_HIP(hipGraphGetNodes(g, nodes.data(), &n));
-      for (hipGraphNode_t nd : nodes) {
-        hipGraphNodeType ty;
-        RTS_HIP(hipGraphNodeGetType(nd, &ty));
-        if (ty != hipGraphNodeTypeEventRecord) continue;
-        hipEvent_t ee = nullptr;
-        RTS_HIP(hipGraphEventRecordNodeGetEvent(nd, &ee));
-        for (int i = 0; i < 4; ++i)
-          if (ee == P->cap_ev[i]) P->ev_nodes[i] = nd;
+    if (timed) {
+      segs.push_back(g);
+      g = nullptr;
+      if (segs.size() != 3) {
+        drop_segs();
+        g_last_hip = "timed graph capture: expected three segments";
+        return RTS_E_HIP;
       }
-      for (auto nd : P->ev_nodes)
-        if (!nd) {
-          (void)hipGraphDestroy(g);
-          for (auto& x : P->ev_nodes) x = nullptr;
-          g_last_hip = "timed graph capture: an event-record node is missing";
-          return RTS_E_HIP;
+      e = hipGraphCreate(&g, 0);
+      hipGraphNode_t prev = nullptr;
+      for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+        hipGraphNode_t n = nullptr;
+        e = hipGraphAddEventRecordNode(&n, g, prev ? &prev : nullptr, prev ? 1 : 0, P->cap_ev[i]);
+        if (e != hipSuccess) break;
+        P->ev_nodes[i] = n;
+        prev = n;
+        if (i < 3) {  // (the child node holds its own copy of the segment)
+          e = hipGraphAddChildGraphNode(&n, g, &prev, 1, segs[i]);
+          prev = n;
         }
+      }
+      drop_segs();
+      if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        for (auto& x : P->ev_nodes) x = nullptr;
+        return hip_fail(e, "timed graph assembly");
+      }
     }
     e = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
       (void)hipGraphDestroy(g);
+      for (auto& x : P->ev_nodes) x = nullptr;
       return hip_fail(e, "hipGraphInstantiate");
     }
     P->graph = g;  // kept: its nodes address the exec's event-record nodes
