@@ -47,6 +47,7 @@ def _load():
         lib.oracle_solve.argtypes = head + [p, p, p, p, p, p, i]
         lib.oracle_solve_chi.argtypes = head + [p, p, p, p, p, i]
         lib.oracle_solve_dform.argtypes = head + [p, p, p, p, p, p]
+        lib.oracle_solve_gs.argtypes = head + [p, p, p, p, i, p, p, p, p]
         lib.oracle_flux.argtypes = head + [p, p, p, p, p, p, p, p, i]
         lib.oracle_flux_divergence.argtypes = [i, i, i, d, d, d, p, p]
         lib.oracle_solve_tol.argtypes = head + [d, p, p, p, p, p, p, p, p, p, i]
@@ -55,7 +56,8 @@ def _load():
         lib.oracle_ray.argtypes = [i, i, i, d, d, d, p, i, i, d, i, p, p, p]
         lib.oracle_weights.argtypes = [d, p, p, p, p]
         lib.oracle_solve_sub.argtypes = head + [p, d, p, p, p, p, p, p, p, p, i]
-        for f in ("oracle_solve", "oracle_solve_chi", "oracle_solve_dform", "oracle_adjoint",
+        for f in ("oracle_solve", "oracle_solve_chi", "oracle_solve_dform", "oracle_solve_gs",
+                  "oracle_adjoint",
                   "oracle_complex_step", "oracle_ray", "oracle_flux", "oracle_flux_divergence",
                   "oracle_solve_tol", "oracle_solve_sub"):
             getattr(lib, f).restype = i
@@ -120,6 +122,27 @@ def solve_dform(p):
         raise ValueError("oracle rejected the problem")
     del keep
     return Q, J, It
+
+
+def solve_gs(p, eps, n_gs: int):
+    """Scattering with Gauss-Seidel source updates along the rays: p.S is the
+    thermal source B, eps [B,nz,ny,nx] the photon destruction probability,
+    n_gs iterations.  Returns (Q, J, I_top, S) in float64 (S the final source
+    function)."""
+    lib = _load()
+    keep, head = _head(p)
+    B = p.nbands
+    Q = np.empty((p.nz, p.ny, p.nx))
+    J = np.empty((B, p.nz, p.ny, p.nx))
+    It = np.empty((B, p.n_up, p.ny, p.nx))
+    So = np.empty((B, p.nz, p.ny, p.nx))
+    kap, rho, Bs, ep = _f64(p.kappa), _f64(p.rho), _f64(p.S), _f64(eps)
+    rc = lib.oracle_solve_gs(*head, _ptr(kap), _ptr(rho), _ptr(Bs), _ptr(ep), int(n_gs),
+                             _ptr(Q), _ptr(J), _ptr(It), _ptr(So))
+    if rc:
+        raise ValueError("oracle rejected the problem")
+    del keep
+    return Q, J, It, So
 
 
 def solve_sub(p, sub, tol: float = 0.0, threads: int = 1, want_intensity: bool = False):

@@ -50,6 +50,9 @@
 //     one-sided differences in the bottom and top layers).
 //   * Adjoint: the reverse-mode derivative of the above (downwind to upwind,
 //     last sweep first, ghost sensitivities carried into the previous sweep).
+//   * Scattering (the paper's Gauss-Seidel scheme for strongly scattering
+//     media): S = (1 - eps) J + eps B updated at every point as the rays are
+//     integrated, the new value feeding the next point along the ray.
 //   * Subdomain decomposition (the paper's domain-decomposed RTS): blocks of
 //     the grid iterate with the intensities their upwind neighbours produced
 //     in the previous iteration (block Jacobi across blocks, exact sweeps
@@ -490,6 +493,231 @@ int forward_dform(const Desc& D, const double* chi, const double* S, double* Q, 
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Scattering with Gauss-Seidel source updates along the rays.  In a strongly
+// scattering medium the source function depends on the radiation field,
+// S = (1 - eps) J + eps B (eps: photon destruction probability, B: thermal
+// source).  The paper proposes the Gauss-Seidel scheme of Trujillo Bueno &
+// Fabiani Bendicho (1995): as a ray is integrated, the source function of
+// each point is updated at once and the new value is used for the next point
+// along the ray, which merges interpolation and integration.  As in that
+// scheme, the rays of the other directions are first integrated with the
+// current source function, so that the update at a point sees its complete
+// mean intensity, and the update is a local Newton step with the diagonal of
+// the transfer operator.  Reading (per band):
+//   * Local operator: L(p) = sum_r w_r dI_r(p)/dS_p over every ray, the weight
+//     of S_p in the intensities at p itself: w0 of the ray's linear-source
+//     step at p (1 for a boundary cell of a ray whose boundary value is S, 0
+//     for the others).
+//   * S starts at B; every group of rays sharing the dominant axis and its
+//     direction (the rays swept together) holds its contribution P_g =
+//     sum_{r in g} w_r I_r to J, initially (sum_{r in g} w_r) S, and
+//     J = sum_g P_g.
+//   * One Gauss-Seidel iteration sweeps the groups in order of first
+//     appearance, each with its laps (n_iter for x or y dominant axes, from
+//     the ghost plane I = S of the current S, 1 for z).  At every cell p of a
+//     plane, each ray of the group takes the linear-source step of the plain
+//     solve with the current S (upwind values from the cells already
+//     updated), or its boundary value.  The laps before the last iterate the
+//     periodic boundary intensities only.  In the last lap, at every cell,
+//     P_new = sum_{r in g} w_r I_r and J_p += P_new - P_g(p), P_g(p) = P_new;
+//     in the last lap of the last group, before that, the update:
+//       J' = J_p + P_new - P_g(p),
+//       dS = ((1 - eps_p) J' + eps_p B_p - S_p) / (1 - (1 - eps_p) L(p)),
+//       S_p += dS,  I_r += (dI_r/dS_p) dS for the group's rays (so that the
+//       next points along the rays integrate from the new source function),
+//     with P_new taken from the corrected intensities.
+//     A fixed point has dS = 0: S = (1 - eps) J[S] + eps B with J[S] the
+//     plain solve's mean intensity.
+//   * After n_gs iterations: S, J, Q = sum_b qw_b 4 pi chi_b (J_b - S_b), and
+//     I_top from the last sweep of each upward ray.
+// With eps = 1 every dS is B - S = 0: S stays B and the sweeps are those of
+// forward() on S = B.
+
+// w0 of ray r's step at every cell (dI/dS_p; boundary cells: 1 if their value
+// is S, else 0), from chi alone.
+void local_weights(const Desc& D, const Ray& r, const double* chi, double* out) {
+  const int na = D.n[r.axis], nA = D.n[r.ea], nB = D.n[r.eb];
+  const int64_t plane = (int64_t)D.n[0] * D.n[1];
+  auto cell = [&](int q, int a, int bb) {
+    int c[3];
+    c[r.axis] = q; c[r.ea] = a; c[r.eb] = bb;
+    return D.at(c[0], c[1], c[2]);
+  };
+  const double b00 = (1 - r.fa) * (1 - r.fb), b10 = r.fa * (1 - r.fb);
+  const double b01 = (1 - r.fa) * r.fb, b11 = r.fa * r.fb;
+  for (int q = 0; q < na; ++q) {
+    const int qu = wrap(q - r.sa, na);
+    for (int a = 0; a < nA; ++a)
+      for (int bb = 0; bb < nB; ++bb) {
+        const int64_t p = cell(q, a, bb);
+        if (is_bc_layer(D, r, (int)(p / plane))) {
+          out[p] = r.up ? (D.bot == 0 ? 1.0 : 0.0) : (D.top == 0 ? 0.0 : 1.0);
+          continue;
+        }
+        const int a1 = r.ea == 2 ? a - r.sea : wrap(a - r.sea, nA);
+        const int b1 = r.eb == 2 ? bb - r.seb : wrap(bb - r.seb, nB);
+        const double cu = b00 * chi[cell(qu, a, bb)] + b10 * chi[cell(qu, a1, bb)] +
+                          b01 * chi[cell(qu, a, b1)] + b11 * chi[cell(qu, a1, b1)];
+        out[p] = weights(0.5 * r.ds * (chi[p] + cu)).w0;
+      }
+  }
+}
+
+int forward_gs(const Desc& D, const double* chi, const double* Bsrc, const double* eps,
+               int n_gs, double* Q, double* J, double* Itop, double* Sout) {
+  const int64_t N = D.cells();
+  const int64_t plane = (int64_t)D.n[0] * D.n[1];
+  std::vector<Ray> rays(D.nr);
+  for (int r = 0; r < D.nr; ++r)
+    if (!make_ray(D, D.mu + 3 * r, rays[r])) return -1;
+  // groups: (dominant axis, direction) in order of first appearance, rays in order
+  std::vector<std::vector<int>> groups;
+  for (int r = 0; r < D.nr; ++r) {
+    bool placed = false;
+    for (auto& g : groups)
+      if (rays[g[0]].axis == rays[r].axis && rays[g[0]].sa == rays[r].sa) {
+        g.push_back(r);
+        placed = true;
+        break;
+      }
+    if (!placed) groups.push_back({r});
+  }
+  const size_t G = groups.size();
+  int nup = 0;
+  for (int r = 0; r < D.nr; ++r) nup += rays[r].up;
+  for (int64_t p = 0; p < N; ++p) Q[p] = 0.0;
+  std::vector<double> S(N), Jb(N), P(G * N), Lop(N), W0((size_t)D.nr * N);
+  std::vector<std::vector<double>> I, ghost;
+  for (int b = 0; b < D.nb; ++b) {
+    const double* cb = chi + b * N;
+    const double* Bb = Bsrc + b * N;
+    const double* eb = eps + b * N;
+    for (int r = 0; r < D.nr; ++r) local_weights(D, rays[r], cb, W0.data() + (size_t)r * N);
+    for (int64_t p = 0; p < N; ++p) {
+      double l = 0.0;
+      for (int r = 0; r < D.nr; ++r) l += D.w[r] * W0[(size_t)r * N + p];
+      Lop[p] = l;
+      S[p] = Bb[p];
+      Jb[p] = 0.0;
+    }
+    for (size_t g = 0; g < G; ++g) {
+      double wg = 0.0;
+      for (int r : groups[g]) wg += D.w[r];
+      for (int64_t p = 0; p < N; ++p) {
+        P[g * N + p] = wg * S[p];
+        Jb[p] += P[g * N + p];
+      }
+    }
+    for (int it = 0; it < n_gs; ++it) {
+      for (size_t g = 0; g < G; ++g) {
+        const std::vector<int>& rg = groups[g];
+        const Ray& R0 = rays[rg[0]];
+        const int na = D.n[R0.axis], nA = D.n[R0.ea], nB = D.n[R0.eb];
+        const bool periodic = R0.axis != 2;
+        const int laps = periodic ? D.n_iter : 1;
+        const int q_first = R0.sa > 0 ? 0 : na - 1, q_last = R0.sa > 0 ? na - 1 : 0;
+        auto cell = [&](int q, int a, int bb) {
+          int c[3];
+          c[R0.axis] = q; c[R0.ea] = a; c[R0.eb] = bb;
+          return D.at(c[0], c[1], c[2]);
+        };
+        I.assign(rg.size(), std::vector<double>(N, 0.0));
+        ghost.assign(rg.size(), std::vector<double>((size_t)nA * nB, 0.0));
+        if (periodic)  // the ghost plane: I = S of the current S (boundary layer at its value)
+          for (size_t k = 0; k < rg.size(); ++k)
+            for (int a = 0; a < nA; ++a)
+              for (int bb = 0; bb < nB; ++bb) {
+                const int64_t p = cell(q_last, a, bb);
+                const int kz = (int)(p / plane);
+                ghost[k][(size_t)a * nB + bb] =
+                    is_bc_layer(D, rays[rg[k]], kz) ? bc_value(D, rays[rg[k]], S[p]) : S[p];
+              }
+        for (int lap = 0; lap < laps; ++lap) {
+          const bool update = lap == laps - 1 && g == G - 1;
+          for (int t = 0; t < na; ++t) {
+            const int q = q_first + R0.sa * t;
+            const int qu = wrap(q - R0.sa, na);
+            for (int a = 0; a < nA; ++a)
+              for (int bb = 0; bb < nB; ++bb) {
+                const int64_t p = cell(q, a, bb);
+                const int kz = (int)(p / plane);
+                double pn = 0.0;
+                for (size_t k = 0; k < rg.size(); ++k) {
+                  const Ray& r = rays[rg[k]];
+                  double v;
+                  if (is_bc_layer(D, r, kz)) {
+                    v = bc_value(D, r, S[p]);
+                  } else {
+                    const int a1 = r.ea == 2 ? a - r.sea : wrap(a - r.sea, nA);
+                    const int b1 = r.eb == 2 ? bb - r.seb : wrap(bb - r.seb, nB);
+                    const int64_t u00 = cell(qu, a, bb), u10 = cell(qu, a1, bb);
+                    const int64_t u01 = cell(qu, a, b1), u11 = cell(qu, a1, b1);
+                    double i00, i10, i01, i11;
+                    if (periodic && t == 0) {
+                      const std::vector<double>& gh = ghost[k];
+                      i00 = gh[(size_t)a * nB + bb];  i10 = gh[(size_t)a1 * nB + bb];
+                      i01 = gh[(size_t)a * nB + b1];  i11 = gh[(size_t)a1 * nB + b1];
+                    } else {
+                      i00 = I[k][u00]; i10 = I[k][u10]; i01 = I[k][u01]; i11 = I[k][u11];
+                    }
+                    const double b00 = (1 - r.fa) * (1 - r.fb), b10 = r.fa * (1 - r.fb);
+                    const double b01 = (1 - r.fa) * r.fb, b11 = r.fa * r.fb;
+                    const double iu = b00 * i00 + b10 * i10 + b01 * i01 + b11 * i11;
+                    const double su = b00 * S[u00] + b10 * S[u10] + b01 * S[u01] + b11 * S[u11];
+                    const double cu = b00 * cb[u00] + b10 * cb[u10] + b01 * cb[u01] + b11 * cb[u11];
+                    const double x = 0.5 * r.ds * (cb[p] + cu);
+                    const Wts<double> wt = weights(x);
+                    v = wt.e * iu + wt.w0 * S[p] + wt.w1 * su;
+                  }
+                  I[k][p] = v;
+                  pn += D.w[rg[k]] * v;
+                }
+                if (update) {  // the Gauss-Seidel update of S_p and the group's intensities
+                  const double jn = Jb[p] + (pn - P[g * N + p]);
+                  const double om = 1.0 - eb[p];
+                  const double dS = (om * jn + eb[p] * Bb[p] - S[p]) / (1.0 - om * Lop[p]);
+                  S[p] += dS;
+                  pn = 0.0;
+                  for (size_t k = 0; k < rg.size(); ++k) {
+                    I[k][p] += W0[(size_t)rg[k] * N + p] * dS;
+                    pn += D.w[rg[k]] * I[k][p];
+                  }
+                }
+                if (lap == laps - 1) {  // the group's contribution to J
+                  Jb[p] = Jb[p] + (pn - P[g * N + p]);
+                  P[g * N + p] = pn;
+                }
+              }
+          }
+          if (periodic)  // exchange: the outflow plane becomes the next lap's ghost
+            for (size_t k = 0; k < rg.size(); ++k)
+              for (int a = 0; a < nA; ++a)
+                for (int bb = 0; bb < nB; ++bb)
+                  ghost[k][(size_t)a * nB + bb] = I[k][cell(q_last, a, bb)];
+        }
+        if (it == n_gs - 1 && Itop) {  // I_top of the group's upward rays
+          for (size_t k = 0; k < rg.size(); ++k) {
+            const int r = rg[k];
+            if (!rays[r].up) continue;
+            int ru = 0;
+            for (int r2 = 0; r2 < r; ++r2) ru += rays[r2].up;
+            double* dst = Itop + ((int64_t)b * nup + ru) * plane;
+            for (int64_t p = 0; p < plane; ++p) dst[p] = I[k][(int64_t)(D.n[2] - 1) * plane + p];
+          }
+        }
+      }
+    }
+    const double qf = 4.0 * kPi * D.qw[b];
+    for (int64_t p = 0; p < N; ++p) {
+      Q[p] += qf * cb[p] * (Jb[p] - S[p]);
+      if (J) J[b * N + p] = Jb[p];
+      if (Sout) Sout[b * N + p] = S[p];
+    }
+  }
+  return 0;
+}
+
 // Reverse-mode derivative of forward() for T = double.
 int adjoint(const Desc& D, const double* chi, const double* S, const double* gQ,
             const double* gJ, const double* gItop, double* dS, double* dchi, int nt) {
@@ -880,6 +1108,24 @@ int oracle_solve(int nx, int ny, int nz, double dx, double dy, double dz, int nb
     for (int64_t p = 0; p < N; ++p) chi[b * N + p] = kappa[b * N + p] * rho[p];
   return forward<double>(D, chi.data(), S, Q, J, Itop, nthreads > 0 ? nthreads : 1, nullptr,
                          nullptr);
+}
+
+// Gauss-Seidel scattering (forward_gs): kappa, rho as oracle_solve, B the
+// thermal source [nb][N] and eps [nb][N] the photon destruction probability;
+// n_gs iterations; Q, J, Itop as oracle_solve and Sout [nb][N] the final
+// source function (J, Itop, Sout may be null).
+int oracle_solve_gs(int nx, int ny, int nz, double dx, double dy, double dz, int nb, int nr,
+                    const double* mu, const double* w, const double* qw, int bot, int top,
+                    double ibot, int n_iter, const double* kappa, const double* rho,
+                    const double* B, const double* eps, int n_gs, double* Q, double* J,
+                    double* Itop, double* Sout) {
+  Desc D = make_desc(nx, ny, nz, dx, dy, dz, nb, nr, mu, w, qw, bot, top, ibot, n_iter);
+  if (!valid(D) || n_gs < 1) return -1;
+  const int64_t N = D.cells();
+  std::vector<double> chi((size_t)nb * N);
+  for (int b = 0; b < nb; ++b)
+    for (int64_t p = 0; p < N; ++p) chi[b * N + p] = kappa[b * N + p] * rho[p];
+  return forward_gs(D, chi.data(), B, eps, n_gs, Q, J, Itop, Sout);
 }
 
 // The D-form second mode (forward_dform): inputs and outputs as oracle_solve.

@@ -888,3 +888,88 @@ def test_tolerance_stopping_rule(oracle_mod):
         assert s == 8 or d <= tol * sc, (ax, pos, s, d, sc)
         d, sc = change(s - 1) if s > 1 else (np.inf, 0.0)
         assert d > tol * sc, (ax, pos, s, d, sc)
+
+
+# ---------------------------------------------------------------------------
+# Gauss-Seidel scattering: S = (1 - eps) J + eps B updated along the rays
+
+
+def _gs_problem(nx, ny, nz, seed, eps_lo, eps_hi, **kw):
+    p = inputs.random_problem(nx, ny, nz, seed=seed, **kw)
+    r = np.random.default_rng(seed + 1)
+    eps = 10 ** r.uniform(math.log10(eps_lo), math.log10(eps_hi), p.S.shape)
+    return p, eps
+
+
+def test_gs_eps_one_is_the_plain_solve(oracle_mod):
+    # eps = 1 keeps S = B: the sweeps are those of the plain solve on S = B
+    # (I_top bitwise), and J is the same sum in another order
+    p = inputs.random_problem(7, 6, 9, seed=61, bands=2)
+    Qg, Jg, Ig, Sg = oracle_mod.solve_gs(p, np.ones_like(p.S), n_gs=3)
+    Qo, Jo, Io = oracle_mod.solve(p)
+    assert np.array_equal(Sg, p.S)
+    assert np.array_equal(Ig, Io)
+    assert np.abs(Jg - Jo).max() <= 1e-14 * np.abs(Jo).max()
+
+
+def _dense_fixed_point(oracle_mod, p, eps):
+    # J of the plain solve is affine in S: J = A S + j0 (the boundary values
+    # enter j0); the scattering fixed point solves S = (1 - eps) J + eps B
+    N = p.ncells
+    S0 = p.S.copy()
+    q = p.astype(np.float64)
+    Sfix = np.empty_like(p.S)
+    for b in range(p.nbands):
+        qb = q.astype(np.float64)
+        qb.kappa, qb.S, qb.qweight = p.kappa[b:b + 1], np.zeros((1,) + p.S.shape[1:]), np.ones(1)
+        j0 = oracle_mod.solve(qb)[1][0].reshape(N)
+        A = np.empty((N, N))
+        for i in range(N):
+            e = np.zeros(N)
+            e[i] = 1.0
+            qb.S = e.reshape((1,) + p.S.shape[1:])
+            A[:, i] = oracle_mod.solve(qb)[1][0].reshape(N) - j0
+        om = 1.0 - eps[b].reshape(N)
+        M = np.eye(N) - om[:, None] * A
+        Sfix[b] = np.linalg.solve(M, om * j0 + eps[b].reshape(N) * S0[b].reshape(N)).reshape(p.S.shape[1:])
+    return Sfix
+
+
+@pytest.mark.parametrize("case", [
+    dict(shape=(4, 3, 5), seed=62, eps=(0.05, 0.5)),
+    dict(shape=(4, 3, 5), seed=63, eps=(0.1, 0.9), bands=2, bot=1, i_bot=2.0, top=1, n_iter=2),
+    dict(shape=(3, 4, 5), seed=64, eps=(0.02, 0.2), n_iter=1),
+])
+def test_gs_converges_to_the_dense_fixed_point(oracle_mod, case):
+    # the Gauss-Seidel iterates converge to the solution of the linear system
+    # S = (1 - eps) (A S + j0) + eps B built column by column from the plain solve
+    c = dict(case)
+    shape, seed, (lo, hi) = c.pop("shape"), c.pop("seed"), c.pop("eps")
+    p, eps = _gs_problem(*shape, seed, lo, hi, **c)
+    Sfix = _dense_fixed_point(oracle_mod, p, eps)
+    _, Jg, _, Sg = oracle_mod.solve_gs(p, eps, n_gs=400)
+    assert np.abs(Sg - Sfix).max() <= 1e-10 * np.abs(Sfix).max()
+    # at the fixed point J is the plain solve's J of S*
+    q = p.astype(np.float64)
+    q.S = Sfix
+    assert np.abs(Jg - oracle_mod.solve(q)[1]).max() <= 1e-10 * np.abs(Jg).max()
+
+
+def test_gs_faster_than_lambda_iteration(oracle_mod):
+    # Lambda iteration S <- (1 - eps) J[S] + eps B with the plain solve, against
+    # the Gauss-Seidel sweeps from the same start: closer to the fixed point
+    # after the same number of iterations in an optically thick scattering box
+    # (eps 0.01 - 0.03, where Lambda iteration converges slowly)
+    p, eps = _gs_problem(5, 4, 8, 65, 0.01, 0.03, lo=1.0, hi=10.0, h_rho=50.0)
+    Sfix = _dense_fixed_point(oracle_mod, p, eps)
+    S = p.S.copy()
+    q = p.astype(np.float64)
+    errs_l, errs_g = [], []
+    for k in range(1, 13):
+        q.S = S
+        S = (1 - eps) * oracle_mod.solve(q)[1] + eps * p.S
+        if k in (3, 6, 12):
+            errs_l.append(np.abs(S - Sfix).max())
+            errs_g.append(np.abs(oracle_mod.solve_gs(p, eps, n_gs=k)[3] - Sfix).max())
+    # (measured: 0.29, 0.20 and 0.13 of the Lambda-iteration error)
+    assert all(g < 0.5 * l for g, l in zip(errs_g, errs_l)), (errs_g, errs_l)
