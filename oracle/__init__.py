@@ -48,6 +48,7 @@ def _load():
         lib.oracle_solve_chi.argtypes = head + [p, p, p, p, p, i]
         lib.oracle_solve_dform.argtypes = head + [p, p, p, p, p, p]
         lib.oracle_solve_gs.argtypes = head + [p, p, p, p, i, p, p, p, p]
+        lib.oracle_solve_warm.argtypes = head + [d, p, p, p, p, p, p, p, p, p, i]
         lib.oracle_flux.argtypes = head + [p, p, p, p, p, p, p, p, i]
         lib.oracle_flux_divergence.argtypes = [i, i, i, d, d, d, p, p]
         lib.oracle_solve_tol.argtypes = head + [d, p, p, p, p, p, p, p, p, p, i]
@@ -57,6 +58,7 @@ def _load():
         lib.oracle_weights.argtypes = [d, p, p, p, p]
         lib.oracle_solve_sub.argtypes = head + [p, d, p, p, p, p, p, p, p, p, i]
         for f in ("oracle_solve", "oracle_solve_chi", "oracle_solve_dform", "oracle_solve_gs",
+                  "oracle_solve_warm",
                   "oracle_adjoint",
                   "oracle_complex_step", "oracle_ray", "oracle_flux", "oracle_flux_divergence",
                   "oracle_solve_tol", "oracle_solve_sub"):
@@ -122,6 +124,35 @@ def solve_dform(p):
         raise ValueError("oracle rejected the problem")
     del keep
     return Q, J, It
+
+
+def solve_warm(p, gin=None, tol: float = 0.0, threads: int = 1):
+    """The solve from given initial ghost planes (warm start): gin
+    [B, R, nz, max(nx, ny)] the intensities of each x or y dominant ray's ghost
+    plane (row k, horizontal index j: y for x-dominant rays, x for y-dominant),
+    or None (I = S); tol > 0 tolerance-driven.  Returns (Q, J, I_top, gout,
+    sweeps) with gout the final ghost planes in the same layout (zeros for
+    z-dominant rays) and sweeps [B, R] (tol > 0) or None."""
+    lib = _load()
+    keep, head = _head(p)
+    B, R, M = p.nbands, p.nrays, max(p.nx, p.ny)
+    Q = np.empty((p.nz, p.ny, p.nx))
+    J = np.empty((B, p.nz, p.ny, p.nx))
+    It = np.empty((B, p.n_up, p.ny, p.nx))
+    gout = np.zeros((B, R, p.nz, M))
+    sw = np.zeros((B, R), dtype=np.int32)
+    kap, rho, S = _f64(p.kappa), _f64(p.rho), _f64(p.S)
+    g = None if gin is None else _f64(gin)
+    if g is not None and g.shape != (B, R, p.nz, M):
+        raise ValueError("gin shape")
+    rc = lib.oracle_solve_warm(*head, float(tol), _ptr(kap), _ptr(rho), _ptr(S),
+                               None if g is None else _ptr(g), _ptr(gout), _ptr(Q), _ptr(J),
+                               _ptr(It), _ptr(sw) if tol > 0 else None,
+                               threads)
+    if rc:
+        raise ValueError("oracle rejected the problem")
+    del keep
+    return Q, J, It, gout, (sw if tol > 0 else None)
 
 
 def solve_gs(p, eps, n_gs: int):

@@ -91,6 +91,10 @@ struct Desc {
   double ibot;
   int n_iter;
   double tol = 0.0;  // > 0: sweeps of a group stop at this relative change (n_iter at most)
+  // warm start: the initial ghost planes (I) of the x and y dominant rays, and
+  // their final ones, [nb][nr][nz][max(nx, ny)] (row k, horizontal index j)
+  const double* gin = nullptr;
+  double* gout = nullptr;
   int64_t cells() const { return (int64_t)n[0] * n[1] * n[2]; }
   int64_t at(int i, int j, int k) const { return ((int64_t)k * n[1] + j) * n[0] + i; }
 };
@@ -206,7 +210,9 @@ struct RaySweeper {
     return c[2];
   }
 
-  RaySweeper(const Desc& D_, const Ray& r_, const T* chi_, const T* S_, T* I_, int nt_)
+  // warm: this ray's initial ghost plane [nz][max(nx, ny)] or null (I = S)
+  RaySweeper(const Desc& D_, const Ray& r_, const T* chi_, const T* S_, T* I_, int nt_,
+             const double* warm = nullptr)
       : D(D_), r(r_), chi(chi_), S(S_), I(I_), nt(nt_) {
     na = D.n[r.axis]; nA = D.n[r.ea]; nB = D.n[r.eb];
     periodic = r.axis != 2;
@@ -222,16 +228,29 @@ struct RaySweeper {
             int64_t p = cell(q, a, b);
             I[p] = bc_value(D, r, S[p]);
           }
-    // Ghost plane for periodic sweeps: I = S of the wrapped upwind plane.
+    // Ghost plane for periodic sweeps: I = S of the wrapped upwind plane, or
+    // the given warm-start intensities (the in-plane axes are the horizontal
+    // one, a, and z, b); boundary-layer cells at their boundary value.
     if (periodic) {
+      const int M = std::max(D.n[0], D.n[1]);
       ghost.resize((size_t)nA * nB);
       for (int a = 0; a < nA; ++a)
         for (int b = 0; b < nB; ++b) {
           int64_t p = cell(q_last, a, b);
           ghost[(size_t)a * nB + b] =
-              is_bc_layer(D, r, kz(q_last, a, b)) ? bc_value(D, r, S[p]) : S[p];
+              is_bc_layer(D, r, kz(q_last, a, b)) ? bc_value(D, r, S[p])
+              : warm                              ? T(warm[(size_t)b * M + a])
+                                                  : S[p];
         }
     }
+  }
+
+  // The current ghost plane (the last sweep's outflow plane) into out [nz][max(nx, ny)].
+  void save_ghost(double* out) const {
+    if (!periodic || !out) return;
+    const int M = std::max(D.n[0], D.n[1]);
+    for (int a = 0; a < nA; ++a)
+      for (int b = 0; b < nB; ++b) out[(size_t)b * M + a] = re(ghost[(size_t)a * nB + b]);
   }
 
   // One sweep; the outflow plane becomes the next sweep's ghost.  Returns the
@@ -287,13 +306,15 @@ struct RaySweeper {
 // If `store` is given, the intensities after every sweep are appended to it.
 template <class T>
 void solve_ray(const Desc& D, const Ray& r, const T* chi, const T* S, T* I,
-               std::vector<std::vector<T>>* store, int nt) {
-  RaySweeper<T> w(D, r, chi, S, I, nt);
+               std::vector<std::vector<T>>* store, int nt, const double* warm = nullptr,
+               double* gout = nullptr) {
+  RaySweeper<T> w(D, r, chi, S, I, nt, warm);
   const int sweeps = w.periodic ? D.n_iter : 1;
   for (int sweep = 0; sweep < sweeps; ++sweep) {
     w.sweep();
     if (store) store->emplace_back(I, I + D.cells());
   }
+  w.save_ghost(gout);
 }
 
 template <class T>
@@ -313,6 +334,9 @@ int forward(const Desc& D, const T* chi, const T* S, T* Q, T* J, T* Itop, int nt
   for (int r = 0; r < D.nr; ++r) nup += rays[r].up;
   std::vector<std::vector<T>> Iall;
   if (D.tol > 0) Iall.assign(D.nr, std::vector<T>(N));
+  const int64_t gstride = (int64_t)D.n[2] * std::max(D.n[0], D.n[1]);  // one ray's ghost
+  auto gin_of = [&](int b, int r) { return D.gin ? D.gin + ((int64_t)b * D.nr + r) * gstride : nullptr; };
+  auto gout_of = [&](int b, int r) { return D.gout ? D.gout + ((int64_t)b * D.nr + r) * gstride : nullptr; };
   for (int b = 0; b < D.nb; ++b) {
     const T* chib = chi + b * N;
     const T* Sb = S + b * N;
@@ -328,7 +352,7 @@ int forward(const Desc& D, const T* chi, const T* S, T* Q, T* J, T* Itop, int nt
         std::vector<RaySweeper<T>> ws;
         for (int r : grp) {
           done[r] = 1;
-          ws.emplace_back(D, rays[r], chib, Sb, Iall[r].data(), nt);
+          ws.emplace_back(D, rays[r], chib, Sb, Iall[r].data(), nt, gin_of(b, r));
         }
         const int max_sweeps = rays[r0].axis != 2 ? D.n_iter : 1;
         int used = 0;
@@ -344,12 +368,13 @@ int forward(const Desc& D, const T* chi, const T* S, T* Q, T* J, T* Itop, int nt
         }
         if (sweeps_used)
           for (int r : grp) sweeps_used[b * D.nr + r] = used;
+        for (size_t k = 0; k < grp.size(); ++k) ws[k].save_ghost(gout_of(b, grp[k]));
       }
     }
     int ru = 0;
     for (int r = 0; r < D.nr; ++r) {
       if (D.tol > 0) std::copy(Iall[r].begin(), Iall[r].end(), I.begin());
-      else solve_ray(D, rays[r], chib, Sb, I.data(), store, nt);
+      else solve_ray(D, rays[r], chib, Sb, I.data(), store, nt, gin_of(b, r), gout_of(b, r));
       for (int64_t p = 0; p < N; ++p) Jb[p] += D.w[r] * I[p];
       if (F)
         for (int k = 0; k < 3; ++k) {
@@ -1184,6 +1209,29 @@ int oracle_solve_tol(int nx, int ny, int nz, double dx, double dy, double dz, in
   if (rc) return rc;
   if (F && QF) flux_divergence(D, F, QF);
   return 0;
+}
+
+// Warm start: the solve (with tol > 0 tolerance-driven, else n_iter sweeps)
+// from the given initial ghost planes gin (or null: I = S), writing the final
+// ghost planes to gout (if not null), both [nb][nr][nz][max(nx, ny)] (entries
+// of z-dominant rays untouched); Q, J, Itop as oracle_solve; sweeps [nb][nr]
+// (tol > 0 only, may be null).
+int oracle_solve_warm(int nx, int ny, int nz, double dx, double dy, double dz, int nb, int nr,
+                      const double* mu, const double* w, const double* qw, int bot, int top,
+                      double ibot, int n_iter, double tol, const double* kappa, const double* rho,
+                      const double* S, const double* gin, double* gout, double* Q, double* J,
+                      double* Itop, int* sweeps, int nthreads) {
+  Desc D = make_desc(nx, ny, nz, dx, dy, dz, nb, nr, mu, w, qw, bot, top, ibot, n_iter);
+  if (!valid(D) || !(tol >= 0) || !std::isfinite(tol)) return -1;
+  D.tol = tol;
+  D.gin = gin;
+  D.gout = gout;
+  const int64_t N = D.cells();
+  std::vector<double> chi((size_t)nb * N);
+  for (int b = 0; b < nb; ++b)
+    for (int64_t p = 0; p < N; ++p) chi[b * N + p] = kappa[b * N + p] * rho[p];
+  return forward<double>(D, chi.data(), S, Q, J, Itop, nthreads > 0 ? nthreads : 1, nullptr,
+                         nullptr, nullptr, sweeps);
 }
 
 // Divergence heating -div F [N] of a given flux field F [3][N] (the same

@@ -973,3 +973,65 @@ def test_gs_faster_than_lambda_iteration(oracle_mod):
             errs_g.append(np.abs(oracle_mod.solve_gs(p, eps, n_gs=k)[3] - Sfix).max())
     # (measured: 0.29, 0.20 and 0.13 of the Lambda-iteration error)
     assert all(g < 0.5 * l for g, l in zip(errs_g, errs_l)), (errs_g, errs_l)
+
+
+# ---------------------------------------------------------------------------
+# warm start: the periodic boundary iteration from given initial ghost planes
+
+
+def _cold_ghost(p):
+    # the cold start's ghost planes in the caller layout: I = S of the outflow
+    # plane, boundary-layer cells at their boundary value (thermal bottom: S;
+    # zero top: 0 in the default variant)
+    M = max(p.nx, p.ny)
+    g = np.zeros((p.nbands, p.nrays, p.nz, M))
+    d = (p.dx, p.dy, p.dz)
+    for r, m in enumerate(p.mu):
+        s = [d[a] / abs(m[a]) if m[a] != 0 else np.inf for a in range(3)]
+        ax = max(a for a in range(3) if s[a] == min(s))
+        if ax == 2:
+            continue
+        last = p.nx - 1 if (ax == 0 and m[0] > 0) else 0 if ax == 0 else (p.ny - 1 if m[1] > 0 else 0)
+        plane = p.S[:, :, :, last] if ax == 0 else p.S[:, :, last, :]      # [B][nz][ny or nx]
+        g[:, r, :, :plane.shape[2]] = plane
+        if m[2] > 0:
+            g[:, r, 0, :plane.shape[2]] = plane[:, 0] if p.bot == 0 else p.i_bot
+        else:
+            g[:, r, -1, :plane.shape[2]] = 0.0 if p.top == 0 else plane[:, -1]
+    return g
+
+
+def test_warm_start_from_the_cold_ghost_is_the_cold_solve(oracle_mod):
+    p = inputs.random_problem(7, 5, 6, seed=71, bands=2)
+    Q0, J0, I0 = oracle_mod.solve(p)
+    Q1, J1, I1, gout, _ = oracle_mod.solve_warm(p, _cold_ghost(p))
+    assert np.array_equal(J1, J0) and np.array_equal(I1, I0) and np.array_equal(Q1, Q0)
+
+
+def test_warm_start_from_the_fixed_point_is_converged(oracle_mod):
+    # the outflow planes of a converged solve are the fixed point of the
+    # periodic iteration: one sweep from them reproduces the converged solve
+    p = inputs.random_problem(6, 7, 5, seed=72, n_iter=80)
+    Qc, Jc, Ic, gc, _ = oracle_mod.solve_warm(p)
+    p1 = p.astype(np.float64)
+    p1.n_iter = 1
+    Q1, J1, I1, g1, _ = oracle_mod.solve_warm(p1, gc)
+    assert np.abs(J1 - Jc).max() <= 1e-13 * np.abs(Jc).max()
+    assert np.abs(g1 - gc).max() <= 1e-13 * np.abs(gc).max()
+    # and the cold single sweep is far from it
+    J0 = oracle_mod.solve(p1)[1]
+    assert np.abs(J0 - Jc).max() > 1e-4 * np.abs(Jc).max()
+
+
+def test_warm_start_saves_sweeps_under_a_tolerance(oracle_mod):
+    # a 1 % perturbed atmosphere started from the previous one's outflow planes
+    # stops earlier than a cold start, at the same tolerance
+    p = inputs.random_problem(8, 6, 7, seed=73, lo=1e-3, hi=1.0, n_iter=40)
+    _, _, _, g, sw_prev = oracle_mod.solve_warm(p, tol=1e-6)
+    q = p.astype(np.float64)
+    q.S = p.S * (1 + 0.01 * np.random.default_rng(74).standard_normal(p.S.shape))
+    _, Jc, _, _, sw_cold = oracle_mod.solve_warm(q, tol=1e-6)
+    _, Jw, _, _, sw_warm = oracle_mod.solve_warm(q, g, tol=1e-6)
+    xy = sw_cold > 1
+    assert sw_warm[xy].sum() < sw_cold[xy].sum(), (sw_warm, sw_cold)
+    assert np.abs(Jw - Jc).max() <= 1e-4 * np.abs(Jc).max()
