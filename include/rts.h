@@ -242,8 +242,37 @@ int rts_plan_autotune(void* plan, int32_t nbox, const rts_inputs* in, const rts_
                       void* ws, size_t ws_bytes, void* hip_stream, int32_t reps,
                       rts_schedule* chosen);
 
+/* For callers that cannot allocate device memory (code under hipGraph stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the forward
+ * solve of all `nbox` boxes, as rts_solve_batched, with the library's own fixed
+ * device array of RTS_STATIC_SCRATCH_BYTES bytes as its workspace instead of a
+ * caller's.  Inputs and outputs are the caller's device pointers as above.
+ *   - Limit: plans with rts_workspace_bytes(RTS_OP_SOLVE) above
+ *     RTS_STATIC_SCRATCH_BYTES (64 MiB; at the default schedule 64^3 with 5
+ *     bands in FP32 needs 49 MiB, 64^3 with 1 band in FP64 21 MiB) are refused
+ *     with RTS_E_WORKSPACE before any device work.
+ *   - The call allocates nothing: no device memory, no pinned host memory, no
+ *     events or graphs.  It always runs eagerly (the schedule's use_graph and
+ *     timing are ignored) and needs the plan's pinned task table, which
+ *     rts_plan_create and rts_plan_set_schedule / rts_plan_autotune allocate
+ *     when a GPU is visible (else RTS_E_UNSUPPORTED).
+ *   - Each GPU holds one copy of the array from the library's first use on it
+ *     until the process ends (its address is looked up once per device).  All
+ *     calls on one GPU share it and it keeps the last call's contents (every
+ *     call clears what must start at zero): two calls in flight on the same
+ *     GPU at once, on any plans or streams, race and give wrong results.
+ *     Serialise them (one stream, or events).
+ *   - Results are bitwise those of rts_solve_batched with the same plan and
+ *     schedule.  rts_check_status(plan, NULL, stream) reads the device status
+ *     word the last call left in the array. */
+#define RTS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int rts_solve_static(void* plan, int32_t nbox, const rts_inputs* in, const rts_outputs* out,
+                     void* hip_stream);
+
 /* Synchronise `hip_stream` and read the device status word left in `ws` by
- * the last call: RTS_OK, or RTS_E_DEADLOCK if a neighbour wait timed out. */
+ * the last call: RTS_OK, or RTS_E_DEADLOCK if a neighbour wait timed out.
+ * ws = NULL reads the status word of rts_solve_static's array on the current
+ * device. */
 int rts_check_status(void* plan, const void* ws, void* hip_stream);
 
 int rts_plan_get_schedule(void* plan, rts_schedule* s);

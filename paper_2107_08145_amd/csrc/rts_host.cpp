@@ -851,8 +851,9 @@ int check_call(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
   return RTS_OK;
 }
 
-// Device state a call needs: the device check, occupancy and the pinned task table.
-int prepare(Plan* P) {
+// Device state a call needs: the device check, occupancy and the pinned task
+// table.  Without may_alloc a missing table is an error, not an allocation.
+int prepare(Plan* P, bool may_alloc = true) {
   int rc = dev_init(*P);
   if (rc) return rc;
   if (P->occupancy_blocks == 0) {
@@ -866,7 +867,22 @@ int prepare(Plan* P) {
         return RTS_E_UNSUPPORTED;
       }
   }
+  if (!may_alloc && (!P->pinned || P->pinned_bytes < (P->off_data - P->off_tasks))) {
+    g_last_hip = "the plan has no pinned task table (it was created with no GPU visible)";
+    return RTS_E_UNSUPPORTED;
+  }
   return ensure_pinned(*P);
+}
+
+// The pinned task table, allocated when the plan is made or rescheduled if a
+// GPU is visible, so that a call of the allocation-free entry point finds it.
+void pin_early(Plan* P) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    return;
+  }
+  (void)ensure_pinned(*P);
 }
 
 // One set of timing events (call start, sweep start, sweep end, call end) for
@@ -994,6 +1010,42 @@ int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
   return RTS_OK;
 }
 
+}  // namespace
+
+namespace rts {
+// The allocation-free forward solve behind rts_solve_static (rts_static.hip):
+// the argument checks against a workspace of `cap` bytes, then the eager path
+// on `ws` (no graph, no timing events, no staging allocation).
+int static_solve_check(void* plan, int nbox, const rts_inputs* in, const rts_outputs* out,
+                       size_t cap) {
+  if (!plan) return RTS_E_ARG;
+  Plan* P = static_cast<Plan*>(plan);
+  if (!in || !out || nbox != (int)P->boxes.size()) return RTS_E_ARG;
+  if (P->total > cap) return RTS_E_WORKSPACE;
+  return RTS_OK;
+}
+
+int static_solve(void* plan, int nbox, const rts_inputs* in, const rts_outputs* out, void* ws,
+                 size_t cap, void* stream) {
+  Plan* P = static_cast<Plan*>(plan);
+  try {
+    int rc = check_call(P, nbox, in, out, ws, cap);
+    if (rc) return rc;
+    if ((rc = prepare(P, false))) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return P->prec == RTS_FP32 ? enqueue_forward<float>(*P, in, out, (char*)ws, st, nullptr)
+                               : enqueue_forward<double>(*P, in, out, (char*)ws, st, nullptr);
+  } catch (...) {
+    return RTS_E_HIP;
+  }
+}
+
+int static_fail(hipError_t e, const char* where) { return hip_fail(e, where); }
+int static_scratch(void** out);  // rts_static.hip
+}  // namespace rts
+
+namespace {
+
 // Schedules the autotuner tries: every strip height of the precision, both
 // queue orders and, when the sweep planes have more than one padded width,
 // both launch forms (one launch per width, one at the widest).
@@ -1055,6 +1107,7 @@ void set_sched(Plan* P, const rts_schedule& s) {
     P->pinned_bytes = 0;
   }
   build_layout(*P);
+  pin_early(P);
 }
 
 // Time every candidate schedule on the caller's data (HIP events, `reps`
@@ -1192,6 +1245,7 @@ int rts_plan_create(const rts_desc* descs, int32_t nbox, void** out) {
       P->boxes.push_back(std::move(B));
     }
     build_layout(*P);
+    pin_early(P);
     *out = P;
     return RTS_OK;
   } catch (...) {
@@ -1348,7 +1402,13 @@ int rts_plan_autotune(void* plan, int32_t nbox, const rts_inputs* in, const rts_
 }
 
 int rts_check_status(void* plan, const void* ws, void* hip_stream) {
-  if (!plan || !ws) return RTS_E_ARG;
+  if (!plan) return RTS_E_ARG;
+  if (!ws) {  // the array of rts_solve_static on the current device
+    void* p = nullptr;
+    const int rc = rts::static_scratch(&p);
+    if (rc) return rc;
+    ws = p;
+  }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   RTS_HIP(hipStreamSynchronize(st));
   int32_t s = 0;

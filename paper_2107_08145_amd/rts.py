@@ -34,7 +34,9 @@ SYMBOLS = ("rts_plan_create", "rts_workspace_bytes", "rts_solve", "rts_solve_bat
            "rts_adjoint", "rts_solve_for_adjoint", "rts_adjoint_from_solve", "rts_plan_autotune",
            "rts_check_status", "rts_plan_get_schedule", "rts_plan_set_schedule",
            "rts_plan_enable_timing", "rts_plan_last_timing",
-           "rts_plan_destroy", "rts_status_string", "rts_version")
+           "rts_plan_destroy", "rts_status_string", "rts_version", "rts_solve_static")
+# rts_solve_static's fixed device array (bytes)
+RTS_STATIC_SCRATCH_BYTES = 64 << 20
 
 
 class Grid(ctypes.Structure):
@@ -118,6 +120,8 @@ def lib():
         L.rts_adjoint_from_solve.argtypes = L.rts_adjoint.argtypes
         L.rts_solve_for_adjoint.argtypes = [vp, i32, ctypes.POINTER(Inputs),
                                             ctypes.POINTER(Outputs), vp, sz, vp]
+        L.rts_solve_static.argtypes = [vp, i32, ctypes.POINTER(Inputs), ctypes.POINTER(Outputs),
+                                       vp]
         L.rts_plan_autotune.argtypes = [vp, i32, ctypes.POINTER(Inputs), ctypes.POINTER(Outputs),
                                          vp, sz, vp, i32, ctypes.POINTER(Schedule)]
         L.rts_check_status.argtypes = [vp, vp, vp]
@@ -134,7 +138,7 @@ def lib():
         L.rts_version.restype = ctypes.c_char_p
         for f in ("rts_plan_create", "rts_workspace_bytes", "rts_solve", "rts_solve_batched",
                   "rts_adjoint", "rts_solve_for_adjoint", "rts_adjoint_from_solve",
-                  "rts_plan_autotune", "rts_check_status", "rts_plan_get_schedule",
+                  "rts_plan_autotune", "rts_check_status", "rts_plan_get_schedule", "rts_solve_static",
                   "rts_plan_set_schedule", "rts_plan_enable_timing", "rts_plan_last_timing"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -273,6 +277,17 @@ class Plan:
         else:
             rc = lib().rts_solve(self.handle, ci, co, ctypes.c_void_p(ws), nbytes, st)
         _check(rc, "rts_solve_batched" if batched else "rts_solve")
+
+    def solve_static_into(self, ins, outs, stream=None):
+        """rts_solve_static: the forward solve of all boxes on the library's fixed device
+        array (no workspace, nothing allocated)."""
+        ci, co = _marshal(ins, outs)
+        _check(lib().rts_solve_static(self.handle, len(ins), ci, co, _stream_ptr(stream)),
+               "rts_solve_static")
+
+    def check_static_status(self, stream=None):
+        """Synchronise and read the status word rts_solve_static left on this device."""
+        _check(lib().rts_check_status(self.handle, None, _stream_ptr(stream)), "device status")
 
     def autotune(self, ins, outs, reps: int = 3, stream=None) -> dict:
         """Time every candidate schedule on these inputs (rts_plan_autotune) and keep

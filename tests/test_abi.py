@@ -97,6 +97,24 @@ def test_null_arguments():
                                ctypes.c_void_p(256), 1 << 40, None) == rts.RTS_E_ARG
 
 
+def test_static_solve_refuses_plans_beyond_its_array():
+    # rts_solve_static checks the plan's workspace against its fixed array
+    # (64 MiB) before any device call, so this runs without a GPU
+    L = rts.lib()
+    big = rts.Plan(inputs.random_problem(72, 72, 72, seed=1, bands=5), rts.RTS_FP32)
+    assert big.workspace_bytes() > rts.RTS_STATIC_SCRATCH_BYTES
+    ci = rts.Inputs(256, 256, 256)
+    co = rts.Outputs(256, None, None)
+    assert L.rts_solve_static(big.handle, 1, ctypes.byref(ci), ctypes.byref(co),
+                              None) == rts.RTS_E_WORKSPACE
+    small = rts.Plan(inputs.random_problem(16, 16, 16, seed=1), rts.RTS_FP32)
+    assert small.workspace_bytes() <= rts.RTS_STATIC_SCRATCH_BYTES
+    assert L.rts_solve_static(None, 1, ctypes.byref(ci), ctypes.byref(co), None) == rts.RTS_E_ARG
+    assert L.rts_solve_static(small.handle, 2, ctypes.byref(ci), ctypes.byref(co),
+                              None) == rts.RTS_E_ARG
+    assert L.rts_solve_static(small.handle, 1, None, None, None) == rts.RTS_E_ARG
+
+
 def test_workspace_and_schedule():
     p = inputs.workload("grey32", size=16)
     pl = rts.Plan(p, rts.RTS_FP32)
