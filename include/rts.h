@@ -118,12 +118,43 @@ typedef struct {
                              solve with n_iter boundary iterations.  A plan's boxes are all
                              decomposed or none; a decomposed box has flux = 0 and no adjoint
                              (RTS_E_UNSUPPORTED). */
+  int32_t gs_iter;        /* >= 0.  0: the source function S is given.  > 0: scattering, the
+                             paper's Gauss-Seidel scheme for strongly scattering media (section
+                             "RTS Integration and Interpolation Merge"): the source function is
+                             S = (1 - eps) J + eps B, with B the `S` input (the thermal source)
+                             and eps the photon destruction probability (rts_inputs.eps), and
+                             gs_iter Gauss-Seidel iterations are run from S = B.  In one
+                             iteration the ray groups (rays sharing the dominant axis and its
+                             direction, in order of first appearance) sweep in turn with the
+                             current S, the laps before a group's last iterating its periodic
+                             boundary; in the last lap of the last group each point p is
+                             updated as it is reached: with J' its mean intensity including the
+                             group's new intensities and L(p) = sum_r w_r dI_r(p)/dS_p over every
+                             ray, dS = ((1 - eps) J' + eps B - S) / (1 - (1 - eps) L(p)), S += dS,
+                             and the group's intensities at p move by dI_r/dS_p dS before the
+                             next points along the rays use them.  Q, J, I_top then come from the
+                             last iteration (Q = sum_b qw_b 4 pi chi_b (J_b - S_b)) and
+                             rts_outputs.S receives S.  Needs prec RTS_FP64, one box per plan,
+                             flux = 0, tol = 0, no subdomains and one sweep task per dominant
+                             axis and direction (at most four rays each, one per in-plane sign
+                             pattern, as S4); else RTS_E_UNSUPPORTED.  No adjoint. */
 } rts_desc;
 
 typedef struct {
   const void* kappa; /* [nbands][N] opacity per unit mass */
   const void* rho;   /* [N] density */
-  const void* S;     /* [nbands][N] source function */
+  const void* S;     /* [nbands][N] source function (with desc.gs_iter > 0: the thermal source B) */
+  const void* eps;   /* [nbands][N] photon destruction probability in (0, 1] for desc.gs_iter > 0
+                        (required then, else ignored; may be NULL) */
+  const void* ghost; /* warm start (the paper starts the boundary iteration from the previous time
+                        step's intensities), or NULL (cold: I = S): the initial ghost-plane
+                        intensities of every ray whose dominant axis is x or y,
+                        [nbands][nrays][nz][max(nx, ny)]: the plane is the ray's outflow plane
+                        (x = nx-1 or 0, y = ny-1 or 0 by its direction), row k its layer, column j
+                        its y (x-dominant rays) or x (y-dominant rays) index; entries of
+                        z-dominant rays and of the ray's boundary layer are not read.  Not with
+                        subdomains, scattering or the adjoint (RTS_E_UNSUPPORTED); the element
+                        type is the plan's. */
 } rts_inputs;
 
 typedef struct {
@@ -135,6 +166,12 @@ typedef struct {
                   or NULL; non-NULL needs the box's desc.flux (else RTS_E_ARG) */
   double* QF;  /* [N] heating -div F, or NULL; needs F: central differences, periodic in x and
                   y, second-order one-sided in the bottom and top layers (first-order if nz = 2) */
+  void* S;     /* [nbands][N] the final source function of a scattering solve (desc.gs_iter > 0),
+                  or NULL; ignored otherwise */
+  void* ghost; /* the final ghost planes (each x or y dominant ray's outflow plane after its last
+                  sweep), in the layout of rts_inputs.ghost, for the next call's warm start, or
+                  NULL; must not alias rts_inputs.ghost.  Entries of z-dominant rays are not
+                  written. */
 } rts_outputs;
 
 /* Adjoint seeds: L = <gQ, Q> + <gJ, J> + <gItop, I_top>; any may be NULL. */
@@ -167,6 +204,13 @@ typedef struct {
                              identical; adjoint gradients differ by rounding only (a task's
                              slot contributions are summed over as many partials as its
                              reverse launch has threads per column). */
+  int32_t split_reverse;  /* 0: the adjoint's reverse sweep takes a task's four ray slots in one
+                             workgroup per strip, except for tasks whose strips could not all be
+                             resident that way (planes wider than about 670 columns in FP32 or
+                             330 in FP64, or more than 512 rows), which are reversed as two
+                             slot-pair passes (even slots, odd slots; strips of 4 rows in FP32,
+                             2 in FP64); 1: every task as two passes.  Gradients differ by
+                             rounding only. */
 } rts_schedule;
 
 /* Create a plan for `nbox` boxes (host only; validates every field; the

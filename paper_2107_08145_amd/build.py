@@ -13,7 +13,7 @@ OUT = os.path.join(HERE, "librts.so")
 # the heaviest units first
 SOURCES = ["rts_sweep_f8.hip", "rts_sweep_f6.hip", "rts_sweep_f4.hip", "rts_sweep_f2.hip",
            "rts_sweep_d4.hip", "rts_sweep_d2.hip", "rts_reverse_f.hip", "rts_reverse_d.hip",
-           "rts_block.hip", "rts_misc.hip", "rts_static.hip", "rts_host.cpp"]
+           "rts_block.hip", "rts_gs.hip", "rts_misc.hip", "rts_static.hip", "rts_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # every fused multiply-add is explicit in the source

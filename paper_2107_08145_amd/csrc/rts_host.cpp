@@ -40,19 +40,24 @@ hipError_t launch_sweep_h(const SweepArgs&, int, int, hipStream_t);
 template <class Real>
 hipError_t launch_reduce(const char*, const Task*, const BoxGeo&, const BoxPtrs&, hipStream_t);
 
+hipError_t launch_gs_init(const GsArgs&, hipStream_t);
+hipError_t launch_gs_ghost(const GsArgs&, int, int, hipStream_t);
+hipError_t launch_gs_plane(const GsArgs&, int, int, int, int, int, int, hipStream_t);
+hipError_t launch_gs_finish(const GsArgs&, hipStream_t);
+
 template <class Real>
 hipError_t launch_block_init(const BlockArgs&, int64_t, hipStream_t);
 template <class Real>
 hipError_t launch_block_sweep(const BlockArgs&, int, hipStream_t);
 
 template <class Real>
-size_t reverse_lds_bytes(int);
+size_t reverse_lds_bytes(int, bool);
 template <class Real>
-const void* reverse_fn(int cols);
+const void* reverse_fn(int cols, bool split);
 int reverse_threads(int cols);
 int reverse_parts(int cols);
 template <class Real>
-hipError_t launch_reverse(const RevArgs&, int, int, hipStream_t);
+hipError_t launch_reverse(const RevArgs&, int, int, bool, hipStream_t);
 template <class Real>
 hipError_t launch_adj_seed(const void*, const void*, const double*, const void*, void*, void*,
                            double, int, int, int, hipStream_t);
@@ -122,7 +127,7 @@ struct Plan {
   std::vector<Box> boxes;
   int prec = RTS_FP64;
   size_t esz = 8;
-  rts_schedule sched{4, 0, 0, 0, 0};
+  rts_schedule sched{4, 0, 0, 0, 0, 0};
   // layout (bytes)
   size_t off_flags = 0, off_tasks = 0, off_queue = 0, off_atasks = 0, off_rqueue = 0,
          off_data = 0, total = 0;
@@ -146,6 +151,7 @@ struct Plan {
     int max_strips;  // strips of its largest task
     int blocks;      // resident workgroups per CU
     bool uni;        // every task of the launch has four uniform slots
+    bool split;      // reverse: the launch runs slot-pair passes (AdjTask::part)
   };
   std::vector<WidthClass> wclasses;
   std::vector<WidthClass> rclasses;  // the same for the reverse sweep (threads: padded columns)
@@ -153,6 +159,11 @@ struct Plan {
   bool uni = true;  // every task's four slots share f1, f2, ds and w
   // subdomain decomposition: every box of the plan is divided (rts_desc.sub)
   bool decomposed = false;
+  // scattering with Gauss-Seidel source updates (rts_desc.gs_iter > 0)
+  int gs_iter = 0;
+  std::vector<GsGroup> gsg;
+  size_t off_gsg = 0;             // the group table (with the task tables)
+  int64_t gs_s = 0, gs_j = 0, gs_p = 0, gs_l = 0, gs_i = 0;  // double offsets of the state
   int max_blocks = 1;      // blocks of the most divided box
   int64_t max_cells = 0;   // cells of the largest box
   int max_iter = 1;        // the largest n_iter
@@ -209,6 +220,11 @@ int validate_desc(const rts_desc& d) {
   for (int a = 0; a < 3; ++a)
     if (d.sub[a] < 0 || d.sub[a] > n3[a]) return RTS_E_ARG;
   if (decomposed(d) && d.flux) return RTS_E_UNSUPPORTED;
+  if (d.gs_iter < 0) return RTS_E_ARG;
+  if (d.gs_iter > 0 && (d.prec != RTS_FP64 || decomposed(d) || d.flux || d.tol > 0)) {
+    g_last_hip = "scattering (gs_iter > 0) needs FP64, no flux, no tolerance and no subdomains";
+    return RTS_E_UNSUPPORTED;
+  }
   if (d.nbands > 16 || d.nrays > 64) return RTS_E_UNSUPPORTED;
   if (g.nx > kMaxCols || g.ny > kMaxCols) return RTS_E_UNSUPPORTED;
   if ((int64_t)g.nx * g.ny * g.nz > ((int64_t)1 << 31)) return RTS_E_UNSUPPORTED;
@@ -217,6 +233,19 @@ int validate_desc(const rts_desc& d) {
 }
 
 // Build every task of every box and the workspace layout for the current schedule.
+// The reverse sweep of a task runs as two slot-pair passes when its four-slot
+// form cannot have every two-row strip resident: that form takes one
+// workgroup per CU (two waves per SIMD at up to 256 VGPRs, or a 1024-thread
+// block) and its LDS state per column; gfx950 has 256 CUs with 160 KB of LDS
+// each (the residency is checked on the device before a call).
+constexpr int kCUs = 256;
+constexpr size_t kLdsPerCU = 160 * 1024;
+bool reverse_split(int prec, int cols, int rows) {
+  const size_t lds = prec == RTS_FP32 ? reverse_lds_bytes<float>(cols, false)
+                                      : reverse_lds_bytes<double>(cols, false);
+  return lds > kLdsPerCU || (rows + kRevRows - 1) / kRevRows > kCUs;
+}
+
 void build_layout(Plan& P) {
   P.tasks.clear();
   P.queue.clear();
@@ -313,9 +342,39 @@ void build_layout(Plan& P) {
     T.rows_per_strip = std::min(H, T.n_rows);
     T.strips = (T.n_rows + T.rows_per_strip - 1) / T.rows_per_strip;
     T.n_unrolled = T.z_planes ? T.n_planes : T.laps * T.n_planes;
+    T.gh_M = std::max(nx, ny);
+    T.gh_off = (int64_t)T.band * d.nrays * nz * T.gh_M;
     max_cols = std::max(max_cols, T.n_cols);
     P.tasks[t] = T;
   }
+  // scattering: the ray groups of the (single) box, from its band-0 tasks
+  P.gsg.clear();
+  if (P.gs_iter > 0)
+    for (int g = 0; g < P.boxes[0].tasks_per_band; ++g) {
+      const Task& T = P.tasks[g];
+      GsGroup G;
+      std::memset(&G, 0, sizeof(G));
+      G.axis = T.frame[2];
+      G.sa = T.sa;
+      G.ea = T.frame[0];  // (the column axis is the lower one)
+      G.eb = T.frame[1];
+      G.laps = T.laps;
+      for (int k = 0; k < kMaxRaysPerTask; ++k) {
+        const TaskRay& y = T.ray[k];
+        GsRay& z = G.ray[k];
+        z.used = y.ray >= 0 ? 1 : 0;
+        z.fa = y.f1;
+        z.fb = y.f2;
+        z.hds = y.hds;
+        z.w = y.w;
+        z.sea = k < 2 ? 1 : -1;  // (slot k: upwind column c - 1 for k < 2, row i - 1 for even k)
+        z.seb = (k & 1) == 0 ? 1 : -1;
+        z.up = y.itop >= 0 ? 1 : 0;
+        z.itop = y.itop;
+        G.wsum += y.w;
+      }
+      P.gsg.push_back(G);
+    }
   // Queue: tasks grouped by workgroup width (a workgroup has one thread per
   // padded column of the widest task it may claim, so narrow tasks in a wide
   // launch leave waves idle), widest first; inside a group the longest sweeps
@@ -403,10 +462,12 @@ void build_layout(Plan& P) {
   off = align_up(off + sizeof(Task) * P.tasks.size());
   P.off_queue = off;
   off = align_up(off + sizeof(int32_t) * P.queue.size());
-  P.off_atasks = off;
-  off = align_up(off + sizeof(AdjTask) * P.tasks.size());
+  P.off_atasks = off;  // (room for two slot-pair passes per task)
+  off = align_up(off + 2 * sizeof(AdjTask) * P.tasks.size());
   P.off_rqueue = off;
-  off = align_up(off + 2 * sizeof(int32_t) * P.tasks.size());
+  off = align_up(off + 2 * 2 * sizeof(int32_t) * P.tasks.size());
+  P.off_gsg = off;
+  off = align_up(off + sizeof(GsGroup) * P.gsg.size());
   P.off_data = off;
   for (Box& B : P.boxes) {
     const size_t arr = (size_t)B.d.nbands * B.N * esz;
@@ -442,6 +503,15 @@ void build_layout(Plan& P) {
       off = align_up(off + (T.uni ? 2 : 3) * (size_t)B.N * esz);
     }
   }
+  if (P.gs_iter > 0) {  // scattering state (double): S, J, the group contributions, L, I
+    const Box& B = P.boxes[0];
+    const size_t arr = (size_t)B.d.nbands * B.N * sizeof(double);
+    P.gs_s = (int64_t)(off / 8); off = align_up(off + arr);
+    P.gs_j = (int64_t)(off / 8); off = align_up(off + arr);
+    P.gs_p = (int64_t)(off / 8); off = align_up(off + P.gsg.size() * arr);
+    P.gs_l = (int64_t)(off / 8); off = align_up(off + arr);
+    P.gs_i = (int64_t)(off / 8); off = align_up(off + kMaxRaysPerTask * arr);
+  }
   P.total = off;
 
   // adjoint region
@@ -453,25 +523,52 @@ void build_layout(Plan& P) {
     off = align_up(off + (size_t)T.n_unrolled * kMaxRaysPerTask * pc * esz);
   }
   P.off_grads = off;
-  for (size_t t = 0; t < P.tasks.size(); ++t) {
+  // A task whose four-slot reverse state does not fit (LDS per CU, or every
+  // strip of two rows resident, one workgroup per CU) is swept in reverse as
+  // two slot-pair passes (even slots, odd slots) with taller strips: the rays
+  // of a task are independent in reverse and their gradients only add.
+  const int ntask = (int)P.tasks.size();
+  for (int t = 0; t < ntask; ++t) {
     const Task& T = P.tasks[t];
     AdjTask& AT = P.atasks[t];
-    AT.task = (int32_t)t;
+    const int cols = P.sched.single_launch ? P.threads : (T.n_cols + 63) / 64 * 64;
+    AT.task = t;
     AT.u_init = T.z_planes ? 0 : -1;
-    AT.strips = (T.n_rows + kRevRows - 1) / kRevRows;
-    AT.xbuf_off = (int64_t)(off / sizeof(uint64_t));
-    off = align_up(off + (size_t)AT.strips * 2 * 2 * 6 * T.n_cols * words * sizeof(uint64_t));
+    AT.split = P.sched.split_reverse || reverse_split(P.prec, cols, T.n_rows) ? 1 : 0;
+    AT.part = 0;
+    const int hr = AT.split ? (P.prec == RTS_FP32 ? 4 : 2) : kRevRows;
+    AT.strips = (T.n_rows + hr - 1) / hr;
+    if (AT.split) {
+      AdjTask second = AT;
+      second.part = 1;
+      P.atasks.push_back(second);
+    }
   }
-  for (size_t t = 0; t < P.tasks.size(); ++t) {
+  for (AdjTask& AT : P.atasks) {  // (every pass has its own exchange buffer)
+    const Task& T = P.tasks[AT.task];
+    AT.xbuf_off = (int64_t)(off / sizeof(uint64_t));
+    // [strip][parity][edge][slot pair][3][col][words]; a split pass depends on
+    // one neighbour only and keeps every step: [strip][step][slot pair][3][col][words]
+    const size_t depth = AT.split ? (size_t)(T.n_unrolled - AT.u_init) : 2 * 2;
+    off = align_up(off + (size_t)AT.strips * depth * 6 * T.n_cols * words * sizeof(uint64_t));
+  }
+  for (int t = 0; t < ntask; ++t) {
     const Box& B = P.boxes[P.tasks[t].box];
-    // one partial per thread of a column of the task's reverse launch
-    const int np = reverse_parts(P.sched.single_launch ? P.threads
-                                                       : (P.tasks[t].n_cols + 63) / 64 * 64);
+    // one partial per thread of a column of the task's reverse launch, or per pass
+    const int np = P.atasks[t].split ? 2
+                   : reverse_parts(P.sched.single_launch ? P.threads
+                                                         : (P.tasks[t].n_cols + 63) / 64 * 64);
     P.atasks[t].nparts = np;
     P.atasks[t].gs_off = (int64_t)(off / esz);
     off = align_up(off + np * (size_t)B.N * esz);
     P.atasks[t].gc_off = (int64_t)(off / esz);
     off = align_up(off + np * (size_t)B.N * esz);
+  }
+  for (size_t a = ntask; a < P.atasks.size(); ++a) {  // second passes share the partials
+    const AdjTask& first = P.atasks[P.atasks[a].task];
+    P.atasks[a].nparts = first.nparts;
+    P.atasks[a].gs_off = first.gs_off;
+    P.atasks[a].gc_off = first.gc_off;
   }
   P.off_grads_end = off;
   for (Box& B : P.boxes) {
@@ -480,28 +577,33 @@ void build_layout(Plan& P) {
     B.seedT_off = (int64_t)(off / esz); off = align_up(off + arr);
   }
   P.total_adj = off;
-  for (size_t t = 0; t < P.tasks.size(); ++t) {
-    const Task& T = P.tasks[t];
+  for (AdjTask& AT : P.atasks) {
+    const Task& T = P.tasks[AT.task];
     const Box& B = P.boxes[T.box];
-    P.atasks[t].seed_off = (T.transposed ? B.seedT_off : B.seed_off) + (int64_t)T.band * B.N;
+    AT.seed_off = (T.transposed ? B.seedT_off : B.seed_off) + (int64_t)T.band * B.N;
   }
-  // reverse queue: grouped by width as the forward one, longest sweeps first
-  auto rwidth = [&](int t) {
-    return P.sched.single_launch ? 0 : (P.tasks[t].n_cols + 63) / 64 * 64;
+  // reverse queue: grouped by width (and pass form) as the forward one,
+  // longest sweeps first
+  auto rwidth = [&](int a) {
+    return P.sched.single_launch ? 0 : (P.tasks[P.atasks[a].task].n_cols + 63) / 64 * 64;
   };
-  std::vector<int> rq(P.tasks.size());
+  auto split_of = [&](int a) { return P.atasks[a].split != 0; };
+  auto rlen = [&](int a) { return P.tasks[P.atasks[a].task].n_unrolled - P.atasks[a].u_init; };
+  std::vector<int> rq(P.atasks.size());
   for (size_t i = 0; i < rq.size(); ++i) rq[i] = (int)i;
   std::stable_sort(rq.begin(), rq.end(), [&](int a, int b) {
+    if (split_of(a) != split_of(b)) return split_of(a);
     if (rwidth(a) != rwidth(b)) return rwidth(a) > rwidth(b);
-    return P.tasks[a].n_unrolled - P.atasks[a].u_init > P.tasks[b].n_unrolled - P.atasks[b].u_init;
+    return rlen(a) > rlen(b);
   });
   P.rqueue.clear();
   P.rclasses.clear();
   int rticket = 0;
   for (size_t k = 0; k < rq.size(); ++k) {
     const int i = rq[k];
-    if (P.rclasses.empty() || P.rclasses.back().width != rwidth(i)) {
-      P.rclasses.push_back(Plan::WidthClass{rwidth(i), 64, (int)k, 0, 0, 1, 0, true});
+    if (P.rclasses.empty() || P.rclasses.back().width != rwidth(i) ||
+        P.rclasses.back().split != split_of(i)) {
+      P.rclasses.push_back(Plan::WidthClass{rwidth(i), 64, (int)k, 0, 0, 1, 0, true, split_of(i)});
       rticket = 0;
     }
     Plan::WidthClass& c = P.rclasses.back();
@@ -511,8 +613,9 @@ void build_layout(Plan& P) {
     c.nq += 1;
     c.strips = rticket;
     c.max_strips = std::max(c.max_strips, (int)P.atasks[i].strips);
-    c.threads = P.sched.single_launch ? P.threads
-                                      : std::max(c.threads, (P.tasks[i].n_cols + 63) / 64 * 64);
+    c.threads = P.sched.single_launch
+                    ? P.threads
+                    : std::max(c.threads, (P.tasks[P.atasks[i].task].n_cols + 63) / 64 * 64);
   }
   P.rev_blocks = 0;
   if (P.gexec) (void)hipGraphExecDestroy(P.gexec);
@@ -579,8 +682,9 @@ int occupancy_h(Plan& P) {
   }
   P.rev_blocks = 1 << 30;
   for (Plan::WidthClass& c : P.rclasses) {
-    int rc = resident_blocks(reverse_fn<Real>(c.threads), reverse_threads(c.threads),
-                             reverse_lds_bytes<Real>(c.threads), &c.blocks);
+    int rc = resident_blocks(reverse_fn<Real>(c.threads, c.split),
+                             c.split ? c.threads : reverse_threads(c.threads),
+                             reverse_lds_bytes<Real>(c.threads, c.split), &c.blocks);
     if (rc) return rc;
     P.rev_blocks = std::min(P.rev_blocks, c.blocks);
   }
@@ -631,6 +735,9 @@ int ensure_pinned(Plan& P) {
               sizeof(AdjTask) * P.atasks.size());
   std::memcpy((char*)P.pinned + (P.off_rqueue - P.off_tasks), P.rqueue.data(),
               sizeof(int32_t) * P.rqueue.size());
+  if (!P.gsg.empty())
+    std::memcpy((char*)P.pinned + (P.off_gsg - P.off_tasks), P.gsg.data(),
+                sizeof(GsGroup) * P.gsg.size());
   return RTS_OK;
 }
 
@@ -693,6 +800,55 @@ struct Marks {
   }
 };
 
+// Scattering with Gauss-Seidel source updates (rts_gs.hip): the state
+// initialisation, then per iteration and ray group its ghost plane and one
+// launch per plane of each lap, then Q, J and S.  The marks bracket the
+// iterations.
+int enqueue_gs(Plan& P, const rts_inputs* in, const rts_outputs* out, char* ws, hipStream_t st,
+               const Marks* mk) {
+  const Box& B = P.boxes[0];
+  GsArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.ws = ws;
+  a.groups = reinterpret_cast<const GsGroup*>(ws + P.off_gsg);
+  a.ngroups = (int)P.gsg.size();
+  a.nbands = B.d.nbands;
+  a.nx = B.d.g.nx; a.ny = B.d.g.ny; a.nz = B.d.g.nz;
+  a.bot = B.d.bot; a.top = B.d.top; a.ibot = B.d.i_bot;
+  a.N = B.N;
+  a.chi_off = B.chi_off;
+  a.s_off = P.gs_s; a.j_off = P.gs_j; a.p_off = P.gs_p; a.l_off = P.gs_l; a.i_off = P.gs_i;
+  a.B = reinterpret_cast<const double*>(in[0].S);
+  a.eps = reinterpret_cast<const double*>(in[0].eps);
+  for (int k = 0; k < B.d.nbands; ++k) a.qw[k] = B.qw[k];
+  a.Q = out[0].Q;
+  a.J = reinterpret_cast<double*>(out[0].J);
+  a.I_top = reinterpret_cast<double*>(out[0].I_top);
+  a.S = reinterpret_cast<double*>(out[0].S);
+  RTS_HIP(launch_gs_init(a, st));
+  int mrc = RTS_OK;
+  if (mk && (mrc = mk->mark(1, st))) return mrc;
+  const int n[3] = {a.nx, a.ny, a.nz};
+  const int G = a.ngroups;
+  for (int it = 0; it < P.gs_iter; ++it)
+    for (int g = 0; g < G; ++g) {
+      const GsGroup& gg = P.gsg[g];
+      const int na = n[gg.axis], pc = n[gg.ea] * n[gg.eb];
+      if (gg.axis != 2) RTS_HIP(launch_gs_ghost(a, g, pc, st));
+      for (int lap = 0; lap < gg.laps; ++lap) {
+        const bool last = lap == gg.laps - 1;
+        for (int t = 0; t < na; ++t) {
+          const int q = gg.sa > 0 ? t : na - 1 - t;
+          RTS_HIP(launch_gs_plane(a, g, q, last ? 1 : 0, last && g == G - 1 ? 1 : 0,
+                                  last && it == P.gs_iter - 1 ? 1 : 0, pc, st));
+        }
+      }
+    }
+  if (mk && (mrc = mk->mark(2, st))) return mrc;
+  RTS_HIP(launch_gs_finish(a, st));
+  return RTS_OK;
+}
+
 template <class Real>
 int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char* ws,
                     hipStream_t st, const Marks* mk, bool store = false) {
@@ -709,6 +865,10 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
     RTS_HIP(launch_prep<Real>(in[b].kappa, in[b].rho, in[b].S, ws, B.chi_off, B.chiT_off,
                               B.sT_off, B.d.g.nx, B.d.g.ny, B.d.g.nz, B.d.nbands, st));
   }
+  if (P.gs_iter > 0) {
+    if (!out || store || sizeof(Real) != 8) return RTS_E_UNSUPPORTED;
+    return enqueue_gs(P, in, out, ws, st, mk);
+  }
   if (P.decomposed) {
     // subdomains with lagged exchange: iteration 0's field, then one launch
     // per iteration (the launch boundary is the exchange), then the reduce
@@ -720,7 +880,7 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
     b.ntasks = (int)P.tasks.size();
     for (size_t i = 0; i < P.boxes.size(); ++i)
       b.box[i] = BoxPtrs{in[i].kappa, in[i].rho, in[i].S, out[i].Q, out[i].J, out[i].I_top,
-                         nullptr, nullptr};
+                         nullptr, nullptr, nullptr, nullptr};
     RTS_HIP(launch_block_init<Real>(b, P.max_cells, st));
     if (mk && (mrc = mk->mark(1, st))) return mrc;
     for (int it = 0; it < P.max_iter; ++it) {
@@ -737,11 +897,14 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
   a.ws = ws;
   a.tasks = reinterpret_cast<const Task*>(ws + P.off_tasks);
   a.timeout_ticks = P.timeout_ticks;
-  for (size_t b = 0; b < P.boxes.size(); ++b)
+  bool warm = false;
+  for (size_t b = 0; b < P.boxes.size(); ++b) {
     a.box[b] = out ? BoxPtrs{in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top,
-                             out[b].F, out[b].QF}
+                             out[b].F, out[b].QF, in[b].ghost, out[b].ghost}
                    : BoxPtrs{in[b].kappa, in[b].rho, in[b].S, nullptr, nullptr, nullptr, nullptr,
-                             nullptr};
+                             nullptr, nullptr, nullptr};
+    warm = warm || a.box[b].gin || a.box[b].gout;
+  }
   a.store_d = out && !store ? 0 : 1;
   a.flux = 0;
   if (out)
@@ -749,6 +912,7 @@ int enqueue_forward(Plan& P, const rts_inputs* in, const rts_outputs* out, char*
   a.ext = a.flux ? 1 : 0;
   for (const Task& T : P.tasks)
     if (T.tol > 0) a.ext = 2;
+  if (warm) a.ext = 2;  // (the warm start lives in the extended sweep)
   // One persistent launch per workgroup width, in stream order.  Every strip
   // of a task must be resident together (neighbouring strips wait on each
   // other), so a launch's grid never drops below its largest task's strip
@@ -826,7 +990,7 @@ int enqueue_adjoint(Plan& P, const rts_inputs* in, const rts_seeds* g, const rts
     a.total_strips = c.strips;
     a.wclass = (int)k;
     const int grid = std::max(1, std::min(c.blocks * P.cus, c.strips));
-    RTS_HIP(launch_reverse<Real>(a, grid, c.threads, st));
+    RTS_HIP(launch_reverse<Real>(a, grid, c.threads, c.split, st));
   }
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     const BoxGeo G = box_geo(P, b);
@@ -845,6 +1009,11 @@ int check_call(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
     // the flux vector needs the plan's flux partials; its divergence needs F
     if (out[b].F && !P->boxes[b].d.flux) return RTS_E_ARG;
     if (out[b].QF && !out[b].F) return RTS_E_ARG;
+    if (P->gs_iter > 0 && !in[b].eps) return RTS_E_ARG;
+    if ((in[b].ghost || out[b].ghost) && (P->decomposed || P->gs_iter > 0)) {
+      g_last_hip = "ghost planes (warm start) need an undivided plan without scattering";
+      return RTS_E_UNSUPPORTED;
+    }
   }
   if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 || ws_bytes < P->total)
     return RTS_E_WORKSPACE;
@@ -860,8 +1029,9 @@ int prepare(Plan* P, bool may_alloc = true) {
     rc = P->prec == RTS_FP32 ? occupancy<float>(*P) : occupancy<double>(*P);
     if (rc) return rc;
     for (const Plan::WidthClass& c : P->wclasses)
-      // (a decomposed plan has no co-resident strips: its workgroups never wait)
-      if (!P->decomposed && (c.blocks < 1 || c.blocks * P->cus < c.max_strips)) {
+      // (decomposed and scattering plans have no co-resident strips: their
+      // workgroups never wait)
+      if (!P->decomposed && P->gs_iter == 0 && (c.blocks < 1 || c.blocks * P->cus < c.max_strips)) {
         P->occupancy_blocks = 0;
         g_last_hip = "the strips of one sweep task cannot all be resident; use more rows per strip";
         return RTS_E_UNSUPPORTED;
@@ -934,8 +1104,8 @@ int solve_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* out, 
   const bool timed = ev != nullptr;
   std::vector<const void*> key{ws, reinterpret_cast<const void*>(uintptr_t(timed ? 1 : 0))};
   for (int b = 0; b < nbox; ++b) {
-    key.insert(key.end(), {in[b].kappa, in[b].rho, in[b].S, out[b].Q, out[b].J, out[b].I_top,
-                           out[b].F, out[b].QF});
+    key.insert(key.end(), {in[b].kappa, in[b].rho, in[b].S, in[b].eps, in[b].ghost, out[b].Q,
+                           out[b].J, out[b].I_top, out[b].F, out[b].QF, out[b].S, out[b].ghost});
   }
   if (!P->gexec || key != P->gkey) {
     drop_graph(P);
@@ -1061,7 +1231,7 @@ std::vector<rts_schedule> tune_candidates(const Plan& P) {
   for (int sl = sl0; sl <= sl1; ++sl)
     for (int i = 0; i < nh; ++i)
       for (int order = 0; order < 2; ++order)
-        c.push_back(rts_schedule{hs[i], 0, order, P.sched.use_graph, sl});
+        c.push_back(rts_schedule{hs[i], 0, order, P.sched.use_graph, sl, P.sched.split_reverse});
   return c;
 }
 
@@ -1119,8 +1289,9 @@ int autotune_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* ou
   if (rc) return rc;
   if ((rc = dev_init(*P))) return rc;
   *tried = 0;
-  // a decomposed plan has no strip schedule to choose: its launches do not depend on it
-  if (P->decomposed) return RTS_OK;
+  // a decomposed or scattering plan has no strip schedule to choose: its
+  // launches do not depend on it
+  if (P->decomposed || P->gs_iter > 0) return RTS_OK;
   const std::string key = tune_key(*P, P->device);
   rts_schedule cached;
   if (tune_lookup(key, &cached)) {
@@ -1192,8 +1363,14 @@ int rts_plan_create(const rts_desc* descs, int32_t nbox, void** out) {
         g_last_hip = "a plan's boxes are all decomposed into subdomains or none";
         return RTS_E_UNSUPPORTED;
       }
+    for (int b = 0; b < nbox; ++b)
+      if (descs[b].gs_iter > 0 && nbox > 1) {
+        g_last_hip = "a scattering plan (gs_iter > 0) has one box";
+        return RTS_E_UNSUPPORTED;
+      }
     Plan* P = new Plan();
     P->prec = descs[0].prec;
+    P->gs_iter = descs[0].gs_iter;
     P->decomposed = decomposed(descs[0]);
     P->esz = P->prec == RTS_FP32 ? 4 : 8;
     P->sched.rows_per_strip = P->prec == RTS_FP32 ? 4 : 2;  // measured best on MI355X
@@ -1231,11 +1408,11 @@ int rts_plan_create(const rts_desc* descs, int32_t nbox, void** out) {
       }
       // with a tolerance the rays of a group stop together: one sweep task each
       // (a decomposed box stops all its rays together)
-      if (B.d.tol > 0 && !decomposed(B.d))
+      if ((B.d.tol > 0 && !decomposed(B.d)) || B.d.gs_iter > 0)
         for (auto& k : keys)
-          if (k.first != 2 && grp[k].size() > 1) {
-            g_last_hip = "tol > 0 needs at most four rays per dominant axis and direction, "
-                         "one per in-plane sign pattern";
+          if ((k.first != 2 || B.d.gs_iter > 0) && grp[k].size() > 1) {
+            g_last_hip = "tol > 0 and gs_iter > 0 need at most four rays per dominant axis and "
+                         "direction, one per in-plane sign pattern";
             delete P;
             return RTS_E_UNSUPPORTED;
           }
@@ -1313,8 +1490,13 @@ int adjoint_checks(Plan* P, int32_t nbox, const rts_inputs* in, void* ws, size_t
   if (nbox != (int)P->boxes.size() || !in) return RTS_E_ARG;
   for (int b = 0; b < nbox; ++b)
     if (!in[b].kappa || !in[b].rho || !in[b].S) return RTS_E_ARG;
-  if (P->decomposed) {
-    g_last_hip = "no adjoint of a solve decomposed into subdomains";
+  for (int b = 0; b < nbox; ++b)
+    if (in[b].ghost) {  // (the reverse sweep replays the cold start's ghost planes)
+      g_last_hip = "the adjoint starts from the cold ghost planes (rts_inputs.ghost = NULL)";
+      return RTS_E_UNSUPPORTED;
+    }
+  if (P->decomposed || P->gs_iter > 0) {
+    g_last_hip = "no adjoint of a solve decomposed into subdomains or of a scattering solve";
     return RTS_E_UNSUPPORTED;
   }
   for (int b = 0; b < nbox; ++b)
@@ -1331,6 +1513,14 @@ int adjoint_checks(Plan* P, int32_t nbox, const rts_inputs* in, void* ws, size_t
       g_last_hip = "the strips of one reverse sweep task cannot all be resident";
       return RTS_E_UNSUPPORTED;
     }
+  for (const AdjTask& AT : P->atasks) {  // (the kernel's exchange offsets are 32-bit)
+    const Task& T = P->tasks[AT.task];
+    const int64_t depth = AT.split ? T.n_unrolled - AT.u_init : 4;
+    if ((int64_t)AT.strips * depth * 6 * T.n_cols * (P->prec == RTS_FP32 ? 1 : 2) >= (1ll << 31)) {
+      g_last_hip = "the exchange buffer of a reverse sweep pass exceeds 2^31 words";
+      return RTS_E_UNSUPPORTED;
+    }
+  }
   return RTS_OK;
 }
 }  // namespace
@@ -1428,7 +1618,8 @@ int rts_plan_set_schedule(void* plan, const rts_schedule* s) {
   const int h = s->rows_per_strip;
   const bool ok = P->prec == RTS_FP32 ? (h == 2 || h == 4 || h == 6 || h == 8) : (h == 2 || h == 4);
   if (!ok || s->max_workgroups < 0 || (s->order != 0 && s->order != 1) ||
-      (s->single_launch != 0 && s->single_launch != 1))
+      (s->single_launch != 0 && s->single_launch != 1) ||
+      (s->split_reverse != 0 && s->split_reverse != 1))
     return RTS_E_ARG;
   try {
     set_sched(P, *s);

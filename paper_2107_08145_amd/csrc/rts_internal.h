@@ -61,7 +61,7 @@ struct Task {
   int64_t dstore_off;      // element offset of the stored D of every plane [u][slot][row][col]
   int32_t n_unrolled;      // planes u of the unrolled sweep (u = 0 first plane after the ghost,
                            // or the boundary plane when planes are z)
-  int32_t pad;
+  int32_t gh_M;            // warm start: max(nx, ny), the row length of a ghost plane
   int32_t nblk[3];         // subdomain decomposition: blocks along cols, rows and planes (all 1
                            // when the box is not divided)
   int32_t iters;           // decomposed box: its iteration count (n_iter)
@@ -69,6 +69,8 @@ struct Task {
                            // cell for the two iteration parities [2][slot][plane][row][col]
   int64_t btol_off;        // decomposed box with tol: 64-bit word offset of the box's per-
                            // iteration maxima [iterations][2] (change, intensity)
+  int64_t gh_off;          // warm start: element offset of this band's ghost planes
+                           // (band * nrays * nz * gh_M); a slot's ray r adds r * nz * gh_M
   double pl_a, pl_b;       // boundary-plane value D = pl_a * S + pl_b (z_planes)
   double bu_a, bu_b;       // boundary row 0 of even slots (rows are z, mu_z > 0)
   double bd_a, bd_b;       // boundary row n_rows-1 of odd slots (rows are z, mu_z < 0)
@@ -79,10 +81,14 @@ struct Task {
 // the forward one, planes in reverse order, kRevRows rows per strip.
 constexpr int kRevRows = 2;
 struct AdjTask {
-  int32_t task;       // index into the Task table (AdjTask i belongs to Task i)
+  int32_t task;       // index into the Task table (AdjTask i < ntasks belongs to Task i; a
+                      // task reversed in two passes has its second pass after the ntasks)
   int32_t u_init;     // last unrolled plane of the reverse: -1 (ghost plane) or 0
-  int32_t strips;     // strips of kRevRows rows
-  int32_t nparts;     // gradient partials per quantity (threads per column of its reverse launch)
+  int32_t strips;     // strips of kRevRows rows (split passes: rows of their launch)
+  int32_t nparts;     // gradient partials per quantity (threads per column of its reverse
+                      // launch, or 2 for a task reversed in two passes)
+  int32_t split;      // 1: reversed as two slot-pair passes, one workgroup per strip and pass
+  int32_t part;       // split: this pass's slot parity (slots part and part + 2)
   int64_t xbuf_off;   // 64-bit word offset of the exchange buffer [strip][parity][edge][2][3][col][words]
   int64_t gs_off;     // Real offset of this task's dL/dS partial (task array layout)
   int64_t gc_off;     // Real offset of this task's dL/dchi partial (task array layout)
@@ -112,6 +118,8 @@ struct BoxPtrs {
   void* I_top;
   double* F;   // [3][N] flux vector, or null
   double* QF;  // [N] its divergence heating, or null
+  const void* gin;  // warm start: initial ghost planes [nbands][nrays][nz][max(nx, ny)], or null
+  void* gout;       // the final ghost planes (same layout), or null
 };
 
 // Per-box geometry for the prep and reduce kernels.
@@ -136,13 +144,59 @@ constexpr int kMaxWidths = kMaxCols / 64;
 
 // Workspace header (first 256 bytes).
 struct WsHeader {
-  int32_t status;                 // 0, or 1 after a neighbour-wait timeout
+  int32_t status;                 // 0, or after a wait timed out: 1 forward neighbour, 2 reverse neighbour, 3 lap end
   int32_t pad0[3];
   int32_t ticket[kMaxWidths];     // work-queue counter of each forward sweep launch
   int32_t ticket_rev[kMaxWidths]; // work-queue counter of each reverse sweep launch
   int32_t pad[28];
 };
 static_assert(sizeof(WsHeader) == 256, "workspace header is 256 bytes");
+
+// Scattering with Gauss-Seidel source updates (rts_gs_*): one group of rays
+// sharing the dominant axis and its direction (one sweep task), in the natural
+// [z][y][x] layout.  Slot k's upwind corners are offset by -sea along the
+// first in-plane axis ea and by -seb along the second, eb (ea < eb).
+struct GsRay {
+  double fa, fb;    // upwind fractions along ea and eb
+  double hds;       // ds / 2
+  double w;         // quadrature weight (0 for an unused slot)
+  int32_t sea, seb; // +1 / -1
+  int32_t up;       // mu_z > 0
+  int32_t itop;     // index among the rays with mu_z > 0, or -1
+  int32_t used;     // a ray occupies the slot
+  int32_t pad;
+};
+struct GsGroup {
+  int32_t axis, sa; // dominant axis and direction
+  int32_t ea, eb;   // in-plane axes
+  int32_t laps;     // n_iter for x or y, 1 for z
+  int32_t pad;
+  double wsum;      // sum of the group's weights
+  GsRay ray[kMaxRaysPerTask];
+};
+struct GsArgs {
+  char* ws;
+  const GsGroup* groups;  // in the workspace
+  int32_t ngroups, nbands;
+  int32_t nx, ny, nz;
+  int32_t bot, top;       // rts_bot_bc, rts_top_bc
+  int32_t pad;
+  double ibot;
+  int64_t N;
+  int64_t chi_off;        // workspace element offsets (double): chi [B][N]
+  int64_t s_off;          // S state [B][N]
+  int64_t j_off;          // J state [B][N]
+  int64_t p_off;          // group contributions [G][B][N]
+  int64_t l_off;          // local operator [B][N]
+  int64_t i_off;          // the current group's intensities [slot][B][N]
+  const double* B;        // thermal source [B][N] (the caller's S input)
+  const double* eps;      // [B][N]
+  double qw[16];          // band weights of Q
+  double* Q;
+  double* J;              // or null
+  double* I_top;          // or null
+  double* S;              // final source function, or null
+};
 
 // One iteration of a decomposed solve (rts_block_sweep): every (task, block).
 struct BlockArgs {

@@ -58,24 +58,27 @@ __device__ inline double rts_dcw(double x, double e, double c) {
 
 typedef const AdjTask RTS_CONST CAdjTask;
 
-template <class Real, int H>
+template <class Real, int H, int RL = kMaxRaysPerTask>
 struct RevStrip {
   // LDS per column: chi and S of the upwind plane u-1, rows -1..H (index
   // 0..H+1); its D per slot, rows -1..H; the downwind state A, B, G per slot
-  // of the strip's rows; the two halo rows of that state (side 0: the lower
+  // of the strip's rows; the halo rows of that state (side 0: the lower
   // neighbour's last row, odd slots 1 and 3; side 1: the upper neighbour's
-  // first row, even slots 0 and 2).  [column][NQP], NQP odd.
-  static constexpr int R = kMaxRaysPerTask;
-  static constexpr int NQ = (2 + R) * (H + 2) + 3 * R * H + 12;
+  // first row, even slots 0 and 2).  [column][NQP], NQP odd.  RL = 4 holds
+  // every slot; RL = 2 one slot pair of one parity (slots h and h + 2, at
+  // index r >> 1), whose halo is one side only.
+  static constexpr int R = RL;
+  static constexpr int NQ = (2 + R) * (H + 2) + 3 * R * H + 3 * R;
   static constexpr int NQP = NQ | 1;
+  __device__ static constexpr int li(int r) { return R == 4 ? r : (r >> 1); }
   __device__ static constexpr int qc(int j) { return j; }
   __device__ static constexpr int qs(int j) { return H + 2 + j; }
-  __device__ static constexpr int qd(int j, int r) { return 2 * (H + 2) + R * j + r; }
+  __device__ static constexpr int qd(int j, int r) { return 2 * (H + 2) + R * j + li(r); }
   __device__ static constexpr int qw(int i, int r, int m) {
-    return (2 + R) * (H + 2) + 3 * (R * i + r) + m;
+    return (2 + R) * (H + 2) + 3 * (R * i + li(r)) + m;
   }
   __device__ static constexpr int qh(int side, int s2, int m) {
-    return (2 + R) * (H + 2) + 3 * R * H + 6 * side + 3 * s2 + m;
+    return (2 + R) * (H + 2) + 3 * R * H + (R == 4 ? 6 * side : 0) + 3 * s2 + m;
   }
 };
 
@@ -83,19 +86,23 @@ struct RevStrip {
 // threads share a column; part h takes slots h, h + NH, ... (with NH = 2 the
 // even slots, which read the upper halo and publish the strip's first row,
 // and the odd slots, lower halo and last row).  Threads of one part form
-// whole waves, so the part is wave-uniform.
-template <class Real, int H, bool FULL, int SP>
+// whole waves, so the part is wave-uniform.  SPLIT: the two parts are two
+// passes in different workgroups (the adjoint task's `part`), one thread per
+// column, and the LDS holds only the pass's slot pair.
+template <class Real, int H, bool FULL, int SP, bool SPLIT>
 __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTask& AT,
                                               const int strip, Real* lds) {
-  using ST = RevStrip<Real, H>;
+  using ST = RevStrip<Real, H, SPLIT ? 2 : kMaxRaysPerTask>;
   constexpr int R = kMaxRaysPerTask;
-  constexpr int NH = R / SP;  // threads per column
+  static_assert(!SPLIT || SP == 2, "a split pass holds one slot pair");
+  constexpr int NH = SPLIT ? 1 : R / SP;  // threads per column
+  constexpr int PS = SPLIT ? 2 : NH;      // slot stride of a thread's slots
   using TG = Tagged<Real>;
   constexpr int NW = TG::WORDS;
   const int W = T.n_cols, nr = T.n_rows;
   const int ncol = blockDim.x / NH;  // padded columns of the block
   const int c = threadIdx.x % ncol;
-  const int h = NH == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / ncol);
+  const int h = SPLIT ? AT.part : NH == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x / ncol);
   const bool act = c < W;
   const int cc = act ? c : W - 1;
   const int cm = cc > 0 ? cc - 1 : W - 1, cp1 = cc + 1 < W ? cc + 1 : 0;
@@ -115,7 +122,7 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
   const int last_from = zp ? 0 : (T.laps - 1) * na;
   auto plane_of = [&](int u) { return u < 0 ? q_last : q0 + T.sa * (zp ? u : u % na); };
   // this thread's slots
-  auto slot = [&](int s) { return NH * s + h; };
+  auto slot = [&](int s) { return PS * s + h; };
   Real f1[SP], f2[SP], hds[SP], wgt[SP];
   int itop[SP];
 #pragma unroll
@@ -239,7 +246,9 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
       // without a neighbour the strip reads its own words (ignored): no branch
       const int nb = side == 0 ? st_lo : st_hi;
       const int edge = side == 0 ? 1 : 0;
-      const int xoff = ((nb * 2 + par) * 2 + edge) * xstride;
+      // (a split pass keeps every step's words: its strips depend on one
+      // neighbour only, so a neighbour may run more than a step ahead)
+      const int xoff = SPLIT ? (nb * K + (k - 1)) * xstride : ((nb * 2 + par) * 2 + edge) * xstride;
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
         const uint64_t* rowp = urow(X, xoff + ((r >> 1) * 3 + m) * W * NW);
@@ -268,7 +277,7 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
         if (__ballot(!all_fresh()) == 0) break;
         if (__builtin_amdgcn_readfirstlane(ld_dev(status)) != 0) break;
         if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > A.timeout_ticks) {
-          st_dev(status, 1);
+          st_dev(status, 2);  // (2: a reverse-sweep wait)
           break;
         }
       }
@@ -386,7 +395,7 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
         if (i == top) do_row(i);
     }
     if (act && k + 1 < K) {
-      const int xe = ((strip * 2 + (k & 1)) * 2) * xstride;
+      const int xe = SPLIT ? (strip * K + k) * xstride : ((strip * 2 + (k & 1)) * 2) * xstride;
       const uint32_t tag = (uint32_t)(k + 1);
 #pragma unroll
       for (int s = 0; s < SP; ++s) {
@@ -402,7 +411,8 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
               if (i == top) v[m] = nst[i][s][m];
           }
           // edge 0: first row, even slots; edge 1: last row, odd slots
-          TG::put(lane_at(urow(X, xe + (even ? 0 : xstride) + ((r >> 1) * 3 + m) * W * NW), xb), v[m], tag);
+          TG::put(lane_at(urow(X, xe + (even || SPLIT ? 0 : xstride) + ((r >> 1) * 3 + m) * W * NW), xb),
+                  v[m], tag);
         }
       }
     }
@@ -430,15 +440,17 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
   }
 }
 
-// MAXT: the block-size bound; SP: slots per thread (2: two threads per column)
-template <class Real, int MAXT, int SP>
-__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(1, 1024 / MAXT * 2)))
+// MAXT: the block-size bound; SP: slots per thread (2: two threads per
+// column, or one slot pair of a split pass); H: rows per strip; SPLIT: the
+// adjoint tasks are slot-pair passes.  WMIN, WMAX: waves per SIMD (a split
+// block of up to 768 threads, one per CU, needs three).
+template <class Real, int MAXT, int SP, int H, bool SPLIT, int WMIN, int WMAX>
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(WMIN, WMAX)))
 void rts_reverse(RevArgs A) {
   extern __shared__ char smem_raw[];
   Real* lds = reinterpret_cast<Real*>(smem_raw);
   __shared__ int sh_ticket;
   WsHeader* hdr = reinterpret_cast<WsHeader*>(A.ws);
-  constexpr int H = kRevRows;
   for (;;) {
     if (threadIdx.x == 0) sh_ticket = atomicAdd(&hdr->ticket_rev[A.wclass], 1);
     __syncthreads();
@@ -452,8 +464,8 @@ void rts_reverse(RevArgs A) {
     CAdjTask& AT = ((CAdjTask*)(uintptr_t)A.atasks)[ai];
     CTask& T = ((CTask*)(uintptr_t)A.tasks)[AT.task];
     const int strip = tk - queue[2 * qi];
-    if ((strip + 1) * H <= T.n_rows) run_rev_strip<Real, H, true, SP>(A, T, AT, strip, lds);
-    else run_rev_strip<Real, H, false, SP>(A, T, AT, strip, lds);
+    if ((strip + 1) * H <= T.n_rows) run_rev_strip<Real, H, true, SP, SPLIT>(A, T, AT, strip, lds);
+    else run_rev_strip<Real, H, false, SP, SPLIT>(A, T, AT, strip, lds);
   }
 }
 
@@ -463,36 +475,59 @@ void rts_reverse(RevArgs A) {
 // up to 512 columns, one thread per column (four slots) in 512 threads; above,
 // one thread per column in 1024 threads.  A block bound of 512 allows 256
 // VGPRs per lane, which the four-slot state nearly fills; 1024 allows 128 and
-// spills.
+// spills.  Split passes (tasks too wide or too tall for the four-slot LDS
+// state of two-row strips with every strip resident): one thread per column,
+// one slot pair, strips of rev_rows(true) rows (four in FP32, two in FP64),
+// blocks of at most 768 threads.
 template <class Real>
-size_t reverse_lds_bytes(int cols) {
-  return (size_t)RevStrip<Real, kRevRows>::NQP * cols * sizeof(Real);
+constexpr int rev_rows(bool split) {
+  return split ? (sizeof(Real) == 4 ? 4 : 2) : kRevRows;
+}
+
+template <class Real>
+size_t reverse_lds_bytes(int cols, bool split) {
+  const int np = split ? RevStrip<Real, rev_rows<Real>(true), 2>::NQP
+                       : RevStrip<Real, kRevRows>::NQP;
+  return (size_t)np * cols * sizeof(Real);
 }
 
 int reverse_parts(int cols);    // (rts_misc.hip)
 int reverse_threads(int cols);
 
+// split passes: up to 512 columns in a 512-thread bound (256 VGPRs), above
+// in a 768-thread one (three waves per SIMD: 168 VGPRs)
+#define RTS_REV_SPLIT(Real) rts_reverse<Real, 768, 2, rev_rows<Real>(true), true, 3, 3>
+#define RTS_REV_SPLIT_N(Real) rts_reverse<Real, 512, 2, rev_rows<Real>(true), true, 1, 4>
+
 template <class Real>
-const void* reverse_fn(int cols) {
-  if (cols <= 256) return reinterpret_cast<const void*>(&rts_reverse<Real, 512, 2>);
-  if (cols <= 512) return reinterpret_cast<const void*>(&rts_reverse<Real, 512, 4>);
-  return reinterpret_cast<const void*>(&rts_reverse<Real, 1024, 4>);
+const void* reverse_fn(int cols, bool split) {
+  if (split && cols <= 512) return reinterpret_cast<const void*>(&RTS_REV_SPLIT_N(Real));
+  if (split) return reinterpret_cast<const void*>(&RTS_REV_SPLIT(Real));
+  if (cols <= 256) return reinterpret_cast<const void*>(&rts_reverse<Real, 512, 2, kRevRows, false, 1, 4>);
+  if (cols <= 512) return reinterpret_cast<const void*>(&rts_reverse<Real, 512, 4, kRevRows, false, 1, 4>);
+  return reinterpret_cast<const void*>(&rts_reverse<Real, 1024, 4, kRevRows, false, 1, 2>);
 }
 
 template <class Real>
-hipError_t launch_reverse(const RevArgs& a, int grid, int cols, hipStream_t st) {
-  const size_t lds = reverse_lds_bytes<Real>(cols);
+hipError_t launch_reverse(const RevArgs& a, int grid, int cols, bool split, hipStream_t st) {
+  const size_t lds = reverse_lds_bytes<Real>(cols, split);
+  if (split) {
+    if (cols > 768) return hipErrorInvalidValue;
+    if (cols <= 512) RTS_REV_SPLIT_N(Real)<<<dim3(grid), dim3(cols), lds, st>>>(a);
+    else RTS_REV_SPLIT(Real)<<<dim3(grid), dim3(cols), lds, st>>>(a);
+    return hipGetLastError();
+  }
   const dim3 b(reverse_threads(cols));
-  if (cols <= 256) rts_reverse<Real, 512, 2><<<dim3(grid), b, lds, st>>>(a);
-  else if (cols <= 512) rts_reverse<Real, 512, 4><<<dim3(grid), b, lds, st>>>(a);
-  else rts_reverse<Real, 1024, 4><<<dim3(grid), b, lds, st>>>(a);
+  if (cols <= 256) rts_reverse<Real, 512, 2, kRevRows, false, 1, 4><<<dim3(grid), b, lds, st>>>(a);
+  else if (cols <= 512) rts_reverse<Real, 512, 4, kRevRows, false, 1, 4><<<dim3(grid), b, lds, st>>>(a);
+  else rts_reverse<Real, 1024, 4, kRevRows, false, 1, 2><<<dim3(grid), b, lds, st>>>(a);
   return hipGetLastError();
 }
 
 
 #define RTS_REV_INST(Real)                                                          \
-  template size_t reverse_lds_bytes<Real>(int);                                     \
-  template const void* reverse_fn<Real>(int);                                       \
-  template hipError_t launch_reverse<Real>(const RevArgs&, int, int, hipStream_t);
+  template size_t reverse_lds_bytes<Real>(int, bool);                               \
+  template const void* reverse_fn<Real>(int, bool);                                 \
+  template hipError_t launch_reverse<Real>(const RevArgs&, int, int, bool, hipStream_t);
 
 }  // namespace rts

@@ -115,7 +115,7 @@ __device__ __noinline__ bool lap_end_stop(char* ws, int64_t timeout_ticks, doubl
         __builtin_amdgcn_s_sleep(2);
         if (ld_dev(status) != 0) { ok = false; break; }
         if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > timeout_ticks) {
-          st_dev(status, 1);
+          st_dev(status, 3);  // (3: a lap-end wait)
           ok = false;
           break;
         }
@@ -305,6 +305,14 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
       for (int r = 0; r < R; ++r) lc[ST::qd(i, r)] = Dn[i][r];
   };
 
+  // warm start (the extended sweep only): the caller's initial ghost planes,
+  // I of slot r at (row, column) of the task's plane
+  const Real* gin = EXT == 2 && !zp ? reinterpret_cast<const Real*>(A.box[T.box].gin) : nullptr;
+  const bool warm = gin != nullptr;
+  auto ghost_in = [&](int r, int row, int col) __attribute__((always_inline)) {
+    return gptr(gin)[T.gh_off + ((int64_t)T.ray[r].ray * T.n_rows + row) * T.gh_M + col];
+  };
+
   // ---- first upwind plane: the boundary layer (planes are z) or the ghost plane
   {
     load_plane(plane_of(-1));
@@ -319,6 +327,8 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
         const int br = up ? bc_up : bc_dn;
         D0[i][r] = zp ? fmad(pa, nsx[i + 1], pb)
                       : ((r0 + i == br) ? fmad(up ? ua : da, nsx[i + 1], up ? ub : db) : Real(0));
+        if (EXT == 2 && warm && r0 + i != br && T.ray[r].ray >= 0)  // the given ghost intensity
+          D0[i][r] = ghost_in(r, FULL || i < hr ? r0 + i : r0, cc) - nsx[i + 1];
       }
     lds_barrier();  // the previous strip of this workgroup has finished with the LDS
     store_plane(D0);
@@ -467,6 +477,11 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
           h.d[r] = !has ? Real(0)
                         : zp ? fmad(pa, h.s[v], pb)
                              : (hrow_g == br ? fmad(up ? ua : da, h.s[v], up ? ub : db) : Real(0));
+          // warm start: the given ghost intensities, interpolated along the
+          // columns, minus the interpolated S (the interpolation is linear)
+          if (EXT == 2 && warm && has && hrow_g != br && T.ray[r].ray >= 0)
+            h.d[r] = lerp(ghost_in(r, hrow_g, cc), ghost_in(r, hrow_g, r < 2 ? cm : cp1), f1[r]) -
+                     h.s[v];
         }
         return;
       }
@@ -554,10 +569,21 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
     }
     lds_barrier();  // the new plane is complete
   }
+  // the final ghost planes (the outflow plane, in LDS after the last step), as I
+  if (EXT == 2 && !zp && A.box[T.box].gout && act) {
+    Real* go = gptr(reinterpret_cast<Real*>(A.box[T.box].gout));
+    for (int i = 0; i < hr; ++i)
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (T.ray[r].ray >= 0)
+          go[T.gh_off + ((int64_t)T.ray[r].ray * T.n_rows + r0 + i) * T.gh_M + c] =
+              lc[ST::qd(i, r)] + lc[ST::qs(i + 1)];
+  }
 }
 
 // EXT: 0 the plain sweep; 1 also the flux partials (A.flux); 2 also
-// tolerance-driven laps (T.tol > 0).  Separate instantiations, so that each
+// tolerance-driven laps (T.tol > 0) and the warm start (given initial ghost
+// planes, final ones out).  Separate instantiations, so that each
 // keeps its own register allocation.
 template <class Real, int H, bool UNI, int EXT>
 __global__ __launch_bounds__(1024) void rts_sweep(SweepArgs A) {

@@ -50,16 +50,18 @@ class Desc(ctypes.Structure):
                 ("qweight", ctypes.POINTER(ctypes.c_double)), ("bot", ctypes.c_int32),
                 ("top", ctypes.c_int32), ("i_bot", ctypes.c_double), ("n_iter", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("flux", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("sub", ctypes.c_int32 * 3)]
+                ("sub", ctypes.c_int32 * 3), ("gs_iter", ctypes.c_int32)]
 
 
 class Inputs(ctypes.Structure):
-    _fields_ = [("kappa", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("S", ctypes.c_void_p)]
+    _fields_ = [("kappa", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("S", ctypes.c_void_p),
+                ("eps", ctypes.c_void_p), ("ghost", ctypes.c_void_p)]
 
 
 class Outputs(ctypes.Structure):
     _fields_ = [("Q", ctypes.c_void_p), ("J", ctypes.c_void_p), ("I_top", ctypes.c_void_p),
-                ("F", ctypes.c_void_p), ("QF", ctypes.c_void_p)]
+                ("F", ctypes.c_void_p), ("QF", ctypes.c_void_p), ("S", ctypes.c_void_p),
+                ("ghost", ctypes.c_void_p)]
 
 
 def _ptr_or_none(t):
@@ -67,14 +69,16 @@ def _ptr_or_none(t):
 
 
 def _marshal(ins, outs):
-    """C arrays of rts_inputs / rts_outputs; outs entries are (Q, J, I_top) or
-    (Q, J, I_top, F, QF), any but Q may be None."""
+    """C arrays of rts_inputs / rts_outputs; ins entries are (kappa, rho, S[, eps[, ghost]]);
+    outs entries are (Q, J, I_top[, F, QF[, S[, ghost]]]); any but Q and the inputs may be
+    None."""
     n = len(ins)
     ci = (Inputs * n)()
     co = (Outputs * n)()
-    for i, ((k, r, s), o) in enumerate(zip(ins, outs)):
-        ci[i] = Inputs(k.data_ptr(), r.data_ptr(), s.data_ptr())
-        o = tuple(o) + (None,) * (5 - len(o))
+    for i, (inp, o) in enumerate(zip(ins, outs)):
+        inp = tuple(inp) + (None,) * (5 - len(inp))
+        ci[i] = Inputs(*(_ptr_or_none(t) for t in inp))
+        o = tuple(o) + (None,) * (7 - len(o))
         co[i] = Outputs(*(_ptr_or_none(t) for t in o))
     return ci, co
 
@@ -90,7 +94,7 @@ class Grads(ctypes.Structure):
 class Schedule(ctypes.Structure):
     _fields_ = [("rows_per_strip", ctypes.c_int32), ("max_workgroups", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("single_launch", ctypes.c_int32)]
+                ("single_launch", ctypes.c_int32), ("split_reverse", ctypes.c_int32)]
 
 
 class RTSError(RuntimeError):
@@ -163,7 +167,8 @@ def _stream_ptr(stream=None):
 class Plan:
     """A librts plan for one or more boxes (paper_2107_08145_amd.inputs.Problem)."""
 
-    def __init__(self, problems, prec: int = RTS_FP64, flux=False, tol: float = 0.0, sub=None):
+    def __init__(self, problems, prec: int = RTS_FP64, flux=False, tol: float = 0.0, sub=None,
+                 gs_iter: int = 0):
         """flux: bool, or one bool per box (desc.flux: room for the flux vector);
         tol: desc.tol of every box (0: n_iter sweeps; > 0: tolerance-driven);
         sub: desc.sub, (mx, my, mz) subdomains with lagged exchange, or None (undivided),
@@ -189,6 +194,7 @@ class Plan:
             d.bot, d.top, d.i_bot, d.n_iter, d.prec = p.bot, p.top, p.i_bot, p.n_iter, prec
             d.flux = 1 if flags[i] else 0
             d.tol = float(tol)
+            d.gs_iter = int(gs_iter)
             sb = sub[i] if isinstance(sub, list) else sub
             if sb is not None:
                 d.sub[0], d.sub[1], d.sub[2] = (int(v) for v in sb)
@@ -375,6 +381,40 @@ def solve(p, prec: int = RTS_FP64, plan: Plan | None = None, flux: bool = False,
     plan.check_status()
     torch.cuda.synchronize()
     return tuple(o.double().cpu().numpy() for o in outs)
+
+
+def solve_warm(p, prec: int, ghost_in=None, tol: float = 0.0, plan: Plan | None = None):
+    """Forward solve from given initial ghost planes (rts_inputs.ghost, warm start;
+    None: cold) that also returns the final ghost planes: numpy (Q, J, I_top, ghost_out),
+    ghost arrays [B, R, nz, max(nx, ny)] in the plan's precision."""
+    import torch
+    plan = plan or Plan(p, prec, tol=tol)
+    k, r, s = plan.device_inputs(p)
+    shape = (p.nbands, p.nrays, p.nz, max(p.nx, p.ny))
+    gi = None if ghost_in is None else torch.as_tensor(
+        np.ascontiguousarray(ghost_in)).to("cuda", plan.dtype).contiguous()
+    go = torch.zeros(shape, dtype=plan.dtype, device="cuda")
+    Q, J, It = plan.new_outputs(p)
+    plan.solve_into([(k, r, s, None, gi)], [(Q, J, It, None, None, None, go)])
+    plan.check_status()
+    torch.cuda.synchronize()
+    return tuple(o.double().cpu().numpy() for o in (Q, J, It, go))
+
+
+def solve_gs(p, eps, gs_iter: int, plan: Plan | None = None):
+    """Scattering solve (desc.gs_iter > 0, FP64) of one problem on the current GPU:
+    p.S is the thermal source B, eps [B,nz,ny,nx] the photon destruction
+    probability.  Returns numpy (Q, J, I_top, S)."""
+    import torch
+    plan = plan or Plan(p, RTS_FP64, gs_iter=gs_iter)
+    k, r, s = plan.device_inputs(p)
+    e = torch.as_tensor(np.ascontiguousarray(eps, dtype=np.float64)).to("cuda")
+    Q, J, It = plan.new_outputs(p)
+    S = torch.empty_like(J)
+    plan.solve_into([(k, r, s, e)], [(Q, J, It, None, None, S)])
+    plan.check_status()
+    torch.cuda.synchronize()
+    return tuple(o.double().cpu().numpy() for o in (Q, J, It, S))
 
 
 def adjoint(p, prec: int = RTS_FP64, gQ=None, gJ=None, gItop=None, plan: Plan | None = None):

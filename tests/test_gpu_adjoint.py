@@ -115,11 +115,51 @@ def test_adjoint_wide_planes(prec, shape):
 
 
 def test_adjoint_fp64_plane_beyond_lds_is_unsupported():
-    # 520 FP64 columns need more LDS per reverse strip than a CU has
-    p = inputs.random_problem(520, 6, 4, seed=3)
-    print("case adjoint fp64 520 columns", flush=True)
+    # 600 FP64 columns (640 padded) need more LDS per reverse strip than a CU
+    # has even for one slot pair
+    p = inputs.random_problem(600, 6, 4, seed=3)
+    print("case adjoint fp64 600 columns", flush=True)
     with pytest.raises(rts.RTSError, match="UNSUPPORTED"):
         rts.adjoint(p, rts.RTS_FP64, *_seeds(p, 9))
+
+
+# Split reverse passes: a task reversed as two slot-pair passes (even slots,
+# odd slots) in separate workgroups, each with its own gradient partial.
+# Forced on small problems (schedule split_reverse = 1), and taken by the
+# library itself where the four-slot form does not fit: 520 FP64 columns
+# (LDS), a 576 x 576 plane (576 rows: 288 two-row strips, more than one per CU).
+@pytest.mark.parametrize("case", [
+    dict(prec=rts.RTS_FP64, shape=(20, 13, 11), seed=51),
+    dict(prec=rts.RTS_FP64, shape=(24, 20, 14), seed=52, bot=1, top=1, i_bot=1.7, n_iter=3),
+    dict(prec=rts.RTS_FP64, shape=(33, 9, 17), seed=53, bands=2, top=0, n_iter=4),
+    dict(prec=rts.RTS_FP32, shape=(40, 36, 30), seed=54, lo=1e-3, hi=1e3),
+    dict(prec=rts.RTS_FP32, shape=(300, 20, 9), seed=55, bands=2),
+])
+def test_adjoint_split_passes_match_oracle(case):
+    c = dict(case)
+    prec, shape, seed = c.pop("prec"), c.pop("shape"), c.pop("seed")
+    p = inputs.random_problem(*shape, seed=seed, **c)
+    pp = p.astype(np.float32) if prec == rts.RTS_FP32 else p
+    pl = rts.Plan(pp, prec)
+    pl.set_schedule(split_reverse=1)
+    print("case adjoint split", prec, shape, flush=True)
+    tol = 1e-10 if prec == rts.RTS_FP64 else 2e-4
+    gQ, gJ, gI = _seeds(p, seed)
+    got = rts.adjoint(pp, prec, gQ, gJ, gI, plan=pl)
+    ref = oracle.adjoint(pp.astype(np.float64), gQ, gJ.astype(pp.S.dtype).astype(np.float64),
+                         gI.astype(pp.S.dtype).astype(np.float64), threads=8)
+    e = _cmp(got, ref, tol)
+    print(f"adjoint split {shape}: {e:.2e}")
+
+
+@pytest.mark.parametrize("prec,shape", [(rts.RTS_FP64, (520, 6, 4)),
+                                        (rts.RTS_FP32, (576, 576, 5))])
+def test_adjoint_split_where_four_slots_do_not_fit(prec, shape):
+    p = inputs.random_problem(*shape, seed=shape[0] + shape[2], bands=1)
+    print("case adjoint split automatic", prec, shape, flush=True)
+    tol = 1e-10 if prec == rts.RTS_FP64 else 2e-4
+    e = _run(p, prec, _seeds(p, 10), tol, threads=16)
+    print(f"adjoint split automatic {shape}: {e:.2e}")
 
 
 def test_adjoint128_fp32_small_matches_oracle():

@@ -198,3 +198,81 @@ def test_adjoint128_finite_differences_64_cells():
     print(f"adjoint128 finite differences: worst |fd - ad| / bound {worst:.3f}; "
           f"|fd - ad| / |ad| median {np.median(rel):.1e} max {max(rel):.1e}; "
           f"noise bound / |ad| median {np.median(nrel):.1e} max {max(nrel):.1e}", flush=True)
+
+
+def _boxes6_loss64(p64, seeds, rho_scale=1.0):
+    q = p64 if rho_scale == 1.0 else p64.astype(np.float64)
+    if rho_scale != 1.0:
+        q.rho = p64.rho * rho_scale
+    pl = rts.Plan(q, rts.RTS_FP64)
+    pl.set_schedule(rows_per_strip=4)  # (576 rows: every strip of a z sweep resident)
+    Q, J, It = rts.solve(q, rts.RTS_FP64, plan=pl)
+    gQ, gJ, gI = seeds
+    return float((gQ * Q).sum()) + float((gJ * J).sum()) + float((gI * It).sum())
+
+
+@pytest.fixture(scope="module")
+def boxes6_adjoint():
+    """One batched FP32 rts_adjoint over the six uneven boxes at full size (the
+    576^2 x 192 box's z sweeps take the two-pass reverse); U(0,1) seeds: gQ
+    (FP64), gJ and gItop (FP32-representable).  Returns the FP32 problems, the
+    seeds and the gradients (float64 on the host)."""
+    import torch
+    ps = [p.astype(np.float32) for p in inputs.workload("boxes6")]
+    pl = rts.Plan(ps, rts.RTS_FP32)
+    ins = [pl.device_inputs(p) for p in ps]
+    host, seeds, grads = [], [], []
+    for i, p in enumerate(ps):
+        r = np.random.default_rng(7000 + i)
+        gQ = r.random((p.nz, p.ny, p.nx))
+        gJ = r.random(p.S.shape).astype(np.float32).astype(np.float64)
+        gI = r.random((p.nbands, p.n_up, p.ny, p.nx)).astype(np.float32).astype(np.float64)
+        host.append((gQ, gJ, gI))
+        seeds.append((torch.as_tensor(gQ, device="cuda"),
+                      torch.as_tensor(gJ.astype(np.float32), device="cuda"),
+                      torch.as_tensor(gI.astype(np.float32), device="cuda")))
+        grads.append((torch.empty(p.S.shape, dtype=torch.float32, device="cuda"),
+                      torch.empty(p.S.shape, dtype=torch.float32, device="cuda")))
+    print("case full size boxes6 adjoint", pl.workspace_bytes(rts.RTS_OP_ADJOINT), flush=True)
+    pl.adjoint_into(ins, seeds, grads)
+    pl.check_status()
+    torch.cuda.synchronize()
+    got = [tuple(t.double().cpu().numpy() for t in g) for g in grads]
+    del grads, seeds, ins, pl
+    torch.cuda.empty_cache()
+    return ps, host, got
+
+
+@pytest.mark.parametrize("box", range(6))
+def test_full_size_boxes6_adjoint_fp32(boxes6_adjoint, box):
+    """Box by box, of the one batched adjoint (fixture):
+    * at any size: L is linear in S (bottom I = S, top I = 0), so
+      <dL/dS, S> = L, with L from the FP64 forward on the same FP32-rounded
+      inputs: |<dS, S> - L| <= 1e-5 sum|dS S|; and scaling rho by 1 +- h
+      (h = 1e-3, every band's chi) gives the central difference
+      dL/dh = sum_b <dL/dchi_b, chi_b> to 1e-4 sum|dchi chi| (truncation
+      ~ h^2, FP64 rounding ~ 1e-13 / h);
+    * the 64^3 box also against the oracle's reverse mode per array (2e-4 of
+      max, as the other FP32 adjoint tests; the bench's --errors adds the
+      96^2 x 512 box)."""
+    ps, host, got = boxes6_adjoint
+    p, sd, (dS, dchi) = ps[box], host[box], got[box]
+    name = f"{p.nx}x{p.ny}x{p.nz}"
+    p64 = p.astype(np.float64)
+    L0 = _boxes6_loss64(p64, sd)
+    sS = float((dS * p64.S).sum())
+    aS = float(np.abs(dS * p64.S).sum())
+    h = 1e-3
+    fd = (_boxes6_loss64(p64, sd, 1 + h) - _boxes6_loss64(p64, sd, 1 - h)) / (2 * h)
+    chi = oracle.chi_of(p64)
+    ad = float((dchi * chi).sum())
+    ac = float(np.abs(dchi * chi).sum())
+    print(f"boxes6 adjoint {name}: <dS,S> - L {abs(sS - L0) / aS:.2e} of sum|dS S|, "
+          f"d/drho {abs(fd - ad) / ac:.2e} of sum|dchi chi|", flush=True)
+    assert abs(sS - L0) <= 1e-5 * aS, (name, sS, L0)
+    assert abs(fd - ad) <= 1e-4 * ac, (name, fd, ad)
+    if name == "64x64x64":
+        ref = oracle.adjoint(p64, sd[0], sd[1], sd[2], threads=THREADS)
+        e = _errs((dS, dchi), ref)
+        print(f"boxes6 adjoint {name} vs oracle: dS {e[0]:.2e} dchi {e[1]:.2e}", flush=True)
+        assert max(e) <= 2e-4, (name, e)
