@@ -60,6 +60,7 @@ extern "C" {
 #define RTS_E_HIP (-4)         /* a HIP runtime call failed                                */
 #define RTS_E_DEADLOCK (-5)    /* the sweep's neighbour wait timed out (device status)     */
 #define RTS_E_NOT_BUILT (-6)   /* no device code for the current GPU                       */
+#define RTS_E_NONFINITE (-7)   /* an input holds a NaN or an infinity (rts_check_inputs)     */
 
 typedef enum { RTS_FP64 = 0, RTS_FP32 = 1 } rts_precision;
 /* Vertical boundaries (x and y are always periodic). */
@@ -280,8 +281,17 @@ int rts_adjoint_from_solve(void* plan, int32_t nbox, const rts_inputs* in, const
  * workspace exceeds ws_bytes, or whose strips cannot all be resident, are
  * skipped; rts_workspace_bytes(RTS_OP_AUTOTUNE) covers every candidate.
  * Synchronous.  The choice is cached per process by problem shape and
- * device: a later call on an equal problem applies it without timing.
- * Outputs hold the result of the last timed call. */
+ * device: a later call on an equal problem applies it without timing (and
+ * leaves the outputs untouched).  When the environment variable
+ * RTS_TUNE_CACHE names a file, that file is the cache instead, shared by
+ * processes and runs: it is read on each call, keyed by the device's
+ * architecture name, its compute-unit count and the problem (precision; per
+ * box grid, bands, sweep tasks, sweeps and ray grouping), and each new choice
+ * is appended as one text line "<key> <rows_per_strip> <order>
+ * <single_launch>" (the last valid line of a key wins; lines that do not
+ * parse or name no candidate schedule of the plan are ignored; a missing or
+ * unwritable file only means no hit and no record).  Otherwise outputs hold
+ * the result of the last timed call. */
 int rts_plan_autotune(void* plan, int32_t nbox, const rts_inputs* in, const rts_outputs* out,
                       void* ws, size_t ws_bytes, void* hip_stream, int32_t reps,
                       rts_schedule* chosen);
@@ -311,6 +321,22 @@ int rts_plan_autotune(void* plan, int32_t nbox, const rts_inputs* in, const rts_
  *     word the last call left in the array. */
 #define RTS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
 int rts_solve_static(void* plan, int32_t nbox, const rts_inputs* in, const rts_outputs* out,
+                     void* hip_stream);
+
+/* Optional input check, for callers that want non-finite inputs reported
+ * rather than propagated (the solve itself does not test its inputs: a NaN
+ * in chi or S spreads along the rays through every later plane and lap).
+ * Scans every box's kappa [nbands][N], rho [N], S [nbands][N] and, for a
+ * plan with desc.gs_iter > 0, eps [nbands][N] on the device, in the plan's
+ * element type, for NaNs and infinities; the ghost planes are not scanned
+ * (they may hold anything where they are not read).  Uses one status word
+ * of `ws` (256-byte aligned, at least 256 bytes; the plan's solve workspace
+ * will do, but not while a call of this plan is in flight on it), then
+ * synchronises `hip_stream`.  Returns RTS_OK, RTS_E_NONFINITE, RTS_E_ARG
+ * (null plan or inputs, nbox not the plan's, eps missing), RTS_E_WORKSPACE,
+ * or a device error.  Reads each input once (at full HBM rate, about 0.2 ms
+ * for five FP32 bands at 288^3). */
+int rts_check_inputs(void* plan, int32_t nbox, const rts_inputs* in, void* ws, size_t ws_bytes,
                      void* hip_stream);
 
 /* Synchronise `hip_stream` and read the device status word left in `ws` by

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -39,6 +40,8 @@ template <class Real, int H, bool UNI>
 hipError_t launch_sweep_h(const SweepArgs&, int, int, hipStream_t);
 template <class Real>
 hipError_t launch_reduce(const char*, const Task*, const BoxGeo&, const BoxPtrs&, hipStream_t);
+template <class Real>
+hipError_t launch_scan_nonfinite(const void*, int64_t, int*, int, hipStream_t);
 
 hipError_t launch_gs_init(const GsArgs&, hipStream_t);
 hipError_t launch_gs_ghost(const GsArgs&, int, int, hipStream_t);
@@ -170,6 +173,7 @@ struct Plan {
   // device-dependent state, filled on first use
   bool dev_ready = false;
   int device = -1, cus = 0, occupancy_blocks = 0;
+  std::string arch;  // the device's architecture name, e.g. gfx950:sramecc+:xnack-
   int64_t timeout_ticks = 0;
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
@@ -637,6 +641,7 @@ int dev_init(Plan& P) {
   }
   P.device = dev;
   P.cus = prop.multiProcessorCount;
+  P.arch = prop.gcnArchName;
   int clk_khz = 0;
   if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
       clk_khz <= 0)
@@ -1235,8 +1240,10 @@ std::vector<rts_schedule> tune_candidates(const Plan& P) {
   return c;
 }
 
-std::string tune_key(const Plan& P, int device) {
-  std::string k = std::to_string(device) + "/" + std::to_string(P.prec);
+// The problem part of a tuning key: precision and, per box, grid, bands,
+// tasks, sweeps and ray grouping.
+std::string tune_problem(const Plan& P) {
+  std::string k = std::to_string(P.prec);
   for (const Box& B : P.boxes) {
     k += "|" + std::to_string(B.d.g.nx) + "x" + std::to_string(B.d.g.ny) + "x" +
          std::to_string(B.d.g.nz) + "b" + std::to_string(B.d.nbands) + "t" +
@@ -1247,7 +1254,8 @@ std::string tune_key(const Plan& P, int device) {
   return k;
 }
 
-// The process-wide cache of tuned schedules (plans of several threads share it).
+// The process-wide cache of tuned schedules (plans of several threads share
+// it), keyed by device index and problem.
 std::mutex& tune_mutex() {
   static std::mutex m;
   return m;
@@ -1256,16 +1264,71 @@ std::map<std::string, rts_schedule>& tune_cache() {
   static std::map<std::string, rts_schedule> m;
   return m;
 }
-bool tune_lookup(const std::string& key, rts_schedule* s) {
+
+// The persisted cache: a text file named by the environment variable
+// RTS_TUNE_CACHE, one line per tuning run,
+//   <arch>/<compute units>/<problem> <rows_per_strip> <order> <single_launch>
+// (the key has no blanks).  When the variable is set the file is the cache:
+// it is read on every tuning call (the last valid line of a key wins) and
+// each new choice is appended.  Lines that do not parse, or whose schedule is
+// not a candidate of the plan, are ignored.
+const char* tune_file() {
+  const char* f = std::getenv("RTS_TUNE_CACHE");
+  return (f && *f) ? f : nullptr;
+}
+std::string tune_file_key(const Plan& P) {
+  std::string a = P.arch;
+  for (char& c : a)
+    if (c == ' ' || c == '\t' || c == '\n') c = '_';
+  return a + "/" + std::to_string(P.cus) + "/" + tune_problem(P);
+}
+
+bool same_choice(const rts_schedule& a, const rts_schedule& b) {
+  return a.rows_per_strip == b.rows_per_strip && a.order == b.order &&
+         a.single_launch == b.single_launch;
+}
+
+bool tune_lookup(const Plan& P, rts_schedule* s) {
   std::lock_guard<std::mutex> lk(tune_mutex());
-  auto hit = tune_cache().find(key);
+  if (const char* path = tune_file()) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    const std::string want = tune_file_key(P);
+    const std::vector<rts_schedule> cands = tune_candidates(P);
+    bool found = false;
+    std::vector<char> line(1 << 16);
+    while (std::fgets(line.data(), (int)line.size(), f)) {
+      const char* sp = std::strchr(line.data(), ' ');
+      if (!sp || (size_t)(sp - line.data()) != want.size() ||
+          std::strncmp(line.data(), want.data(), want.size()) != 0)
+        continue;
+      int h = 0, order = 0, sl = 0;
+      if (std::sscanf(sp, " %d %d %d", &h, &order, &sl) != 3) continue;
+      for (const rts_schedule& c : cands)
+        if (same_choice(c, rts_schedule{h, 0, order, 0, sl, 0})) {
+          *s = c;
+          found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+  }
+  auto hit = tune_cache().find(std::to_string(P.device) + "/" + tune_problem(P));
   if (hit == tune_cache().end()) return false;
   *s = hit->second;
   return true;
 }
-void tune_store(const std::string& key, const rts_schedule& s) {
+
+void tune_store(const Plan& P, const rts_schedule& s) {
   std::lock_guard<std::mutex> lk(tune_mutex());
-  tune_cache()[key] = s;
+  tune_cache()[std::to_string(P.device) + "/" + tune_problem(P)] = s;
+  if (const char* path = tune_file()) {
+    if (FILE* f = std::fopen(path, "a")) {
+      std::fprintf(f, "%s %d %d %d\n", tune_file_key(P).c_str(), s.rows_per_strip, s.order,
+                   s.single_launch);
+      std::fclose(f);
+    }
+  }
 }
 
 void set_sched(Plan* P, const rts_schedule& s) {
@@ -1292,9 +1355,8 @@ int autotune_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* ou
   // a decomposed or scattering plan has no strip schedule to choose: its
   // launches do not depend on it
   if (P->decomposed || P->gs_iter > 0) return RTS_OK;
-  const std::string key = tune_key(*P, P->device);
   rts_schedule cached;
-  if (tune_lookup(key, &cached)) {
+  if (tune_lookup(*P, &cached)) {
     set_sched(P, cached);
     return RTS_OK;
   }
@@ -1339,7 +1401,7 @@ int autotune_impl(Plan* P, int nbox, const rts_inputs* in, const rts_outputs* ou
   (void)hipEventDestroy(e1);
   if (status == RTS_OK && *tried == 0) status = RTS_E_WORKSPACE;
   set_sched(P, status == RTS_OK ? best : orig);
-  if (status == RTS_OK) tune_store(key, best);
+  if (status == RTS_OK) tune_store(*P, best);
   return status;
 }
 
@@ -1591,6 +1653,44 @@ int rts_plan_autotune(void* plan, int32_t nbox, const rts_inputs* in, const rts_
   }
 }
 
+int rts_check_inputs(void* plan, int32_t nbox, const rts_inputs* in, void* ws, size_t ws_bytes,
+                     void* hip_stream) {
+  if (!plan || !in) return RTS_E_ARG;
+  Plan* P = static_cast<Plan*>(plan);
+  if (nbox != (int)P->boxes.size()) return RTS_E_ARG;
+  for (int b = 0; b < nbox; ++b) {
+    if (!in[b].kappa || !in[b].rho || !in[b].S) return RTS_E_ARG;
+    if (P->gs_iter > 0 && !in[b].eps) return RTS_E_ARG;
+  }
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0 || ws_bytes < sizeof(WsHeader))
+    return RTS_E_WORKSPACE;
+  try {
+    int rc = dev_init(*P);
+    if (rc) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    int* flag = &reinterpret_cast<WsHeader*>(ws)->nonfinite;
+    RTS_HIP(launch_zero(flag, 1, st));
+    auto scan = [&](const void* v, int64_t n) {
+      return P->prec == RTS_FP32 ? launch_scan_nonfinite<float>(v, n, flag, P->cus, st)
+                                 : launch_scan_nonfinite<double>(v, n, flag, P->cus, st);
+    };
+    for (int b = 0; b < nbox; ++b) {
+      const rts_desc& d = P->boxes[b].d;
+      const int64_t N = (int64_t)d.g.nx * d.g.ny * d.g.nz, nb = d.nbands;
+      RTS_HIP(scan(in[b].kappa, nb * N));
+      RTS_HIP(scan(in[b].rho, N));
+      RTS_HIP(scan(in[b].S, nb * N));
+      if (P->gs_iter > 0) RTS_HIP(scan(in[b].eps, nb * N));
+    }
+    RTS_HIP(hipStreamSynchronize(st));
+    int32_t bad = 0;
+    RTS_HIP(hipMemcpy(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost));
+    return bad ? RTS_E_NONFINITE : RTS_OK;
+  } catch (...) {
+    return RTS_E_HIP;
+  }
+}
+
 int rts_check_status(void* plan, const void* ws, void* hip_stream) {
   if (!plan) return RTS_E_ARG;
   if (!ws) {  // the array of rts_solve_static on the current device
@@ -1685,6 +1785,7 @@ const char* rts_status_string(int status) {
       return s.c_str();
     }
     case RTS_E_DEADLOCK: return "RTS_E_DEADLOCK: a sweep neighbour wait timed out";
+    case RTS_E_NONFINITE: return "RTS_E_NONFINITE: an input holds a NaN or an infinity";
     case RTS_E_NOT_BUILT: {
       static thread_local std::string s;
       s = "RTS_E_NOT_BUILT: " + g_last_hip;

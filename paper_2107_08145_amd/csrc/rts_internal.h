@@ -145,7 +145,8 @@ constexpr int kMaxWidths = kMaxCols / 64;
 // Workspace header (first 256 bytes).
 struct WsHeader {
   int32_t status;                 // 0, or after a wait timed out: 1 forward neighbour, 2 reverse neighbour, 3 lap end
-  int32_t pad0[3];
+  int32_t nonfinite;              // set by rts_check_inputs' scan when an input is not finite
+  int32_t pad0[2];
   int32_t ticket[kMaxWidths];     // work-queue counter of each forward sweep launch
   int32_t ticket_rev[kMaxWidths]; // work-queue counter of each reverse sweep launch
   int32_t pad[28];

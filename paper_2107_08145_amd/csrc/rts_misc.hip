@@ -51,6 +51,25 @@ __global__ void rts_zero_ints(int* p, int64_t n) {
 }
 
 
+// Sets *flag when any of the n values is a NaN or an infinity (all exponent
+// bits set).  Reads the values once, coalesced; a finding is one atomic OR.
+template <class Real>
+__global__ __launch_bounds__(256) void rts_scan_nonfinite(const Real* __restrict__ v, int64_t n,
+                                                          int* flag) {
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if constexpr (sizeof(Real) == 4) {
+      const uint32_t u = __float_as_uint((float)v[i]);
+      bad |= (u & 0x7f800000u) == 0x7f800000u;
+    } else {
+      const uint64_t u = (uint64_t)__double_as_longlong((double)v[i]);
+      bad |= (u & 0x7ff0000000000000ull) == 0x7ff0000000000000ull;
+    }
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
 // ---------------------------------------------------------------------------
 // Radiative flux vector F = sum_b qweight_b 4 pi (sum_tasks flux partial +
 // S_b sum_r w_r mu_r) in FP64, fixed order; partials of transposed tasks
@@ -592,6 +611,16 @@ hipError_t launch_zero(int* p, int64_t n, hipStream_t st) {
 
 
 template <class Real>
+hipError_t launch_scan_nonfinite(const void* v, int64_t n, int* flag, int cus, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  blocks = blocks > 8 * (int64_t)cus ? 8 * (int64_t)cus : blocks;  // grid-stride beyond that
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(rts_scan_nonfinite<Real>, dim3((unsigned)blocks), dim3(256), 0, st,
+                     (const Real*)v, n, flag);
+  return hipGetLastError();
+}
+
+template <class Real>
 hipError_t launch_reduce(const char* ws, const Task* tasks, const BoxGeo& g, const BoxPtrs& p,
                          hipStream_t st) {
   dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, g.nz);
@@ -654,6 +683,8 @@ template hipError_t launch_prep<float>(const void*, const void*, const void*, vo
                                        int64_t, int64_t, int, int, int, int, hipStream_t);
 template hipError_t launch_prep<double>(const void*, const void*, const void*, void*, int64_t,
                                         int64_t, int64_t, int, int, int, int, hipStream_t);
+template hipError_t launch_scan_nonfinite<float>(const void*, int64_t, int*, int, hipStream_t);
+template hipError_t launch_scan_nonfinite<double>(const void*, int64_t, int*, int, hipStream_t);
 template hipError_t launch_reduce<float>(const char*, const Task*, const BoxGeo&, const BoxPtrs&,
                                          hipStream_t);
 template hipError_t launch_reduce<double>(const char*, const Task*, const BoxGeo&, const BoxPtrs&,

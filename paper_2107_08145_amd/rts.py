@@ -23,6 +23,7 @@ RTS_E_WORKSPACE = -3
 RTS_E_HIP = -4
 RTS_E_DEADLOCK = -5
 RTS_E_NOT_BUILT = -6
+RTS_E_NONFINITE = -7
 RTS_FP64 = 0
 RTS_FP32 = 1
 RTS_OP_SOLVE = 0
@@ -34,7 +35,8 @@ SYMBOLS = ("rts_plan_create", "rts_workspace_bytes", "rts_solve", "rts_solve_bat
            "rts_adjoint", "rts_solve_for_adjoint", "rts_adjoint_from_solve", "rts_plan_autotune",
            "rts_check_status", "rts_plan_get_schedule", "rts_plan_set_schedule",
            "rts_plan_enable_timing", "rts_plan_last_timing",
-           "rts_plan_destroy", "rts_status_string", "rts_version", "rts_solve_static")
+           "rts_plan_destroy", "rts_status_string", "rts_version", "rts_solve_static",
+           "rts_check_inputs")
 # rts_solve_static's fixed device array (bytes)
 RTS_STATIC_SCRATCH_BYTES = 64 << 20
 
@@ -129,6 +131,7 @@ def lib():
         L.rts_plan_autotune.argtypes = [vp, i32, ctypes.POINTER(Inputs), ctypes.POINTER(Outputs),
                                          vp, sz, vp, i32, ctypes.POINTER(Schedule)]
         L.rts_check_status.argtypes = [vp, vp, vp]
+        L.rts_check_inputs.argtypes = [vp, i32, ctypes.POINTER(Inputs), vp, sz, vp]
         L.rts_plan_get_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
         L.rts_plan_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
         L.rts_plan_enable_timing.argtypes = [vp, i32]
@@ -143,6 +146,7 @@ def lib():
         for f in ("rts_plan_create", "rts_workspace_bytes", "rts_solve", "rts_solve_batched",
                   "rts_adjoint", "rts_solve_for_adjoint", "rts_adjoint_from_solve",
                   "rts_plan_autotune", "rts_check_status", "rts_plan_get_schedule", "rts_solve_static",
+                  "rts_check_inputs",
                   "rts_plan_set_schedule", "rts_plan_enable_timing", "rts_plan_last_timing"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -355,6 +359,15 @@ class Plan:
         ws, nbytes = self.workspace(RTS_OP_ADJOINT)
         _check(lib().rts_adjoint(self.handle, n, ci, cs, cg, ctypes.c_void_p(ws), nbytes,
                                  _stream_ptr(stream)), "rts_adjoint")
+
+    def check_inputs(self, ins, stream=None):
+        """rts_check_inputs: raise RTSError(RTS_E_NONFINITE) if any box's kappa, rho, S (or
+        eps) holds a NaN or an infinity; uses the plan's own workspace."""
+        n = len(ins)
+        ci, _ = _marshal(ins, [(None,)] * n)
+        ws, nbytes = self.workspace()
+        _check(lib().rts_check_inputs(self.handle, n, ci, ctypes.c_void_p(ws), nbytes,
+                                      _stream_ptr(stream)), "rts_check_inputs")
 
     def check_status(self, stream=None, ws=None):
         """rts_check_status: synchronise the stream and raise RTSError if the last call on the

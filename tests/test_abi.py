@@ -30,8 +30,8 @@ def test_every_declared_symbol_is_exported():
 def test_version_and_status_strings():
     L = rts.lib()
     assert b"gfx950" in L.rts_version()
-    for code in (0, -1, -2, -3, -4, -5, -6):
-        assert rts.status_string(code)
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert rts.status_string(code) != "unknown status"
     assert rts.status_string(-3).startswith("RTS_E_WORKSPACE")
 
 
@@ -194,6 +194,27 @@ def test_autotune_workspace_and_errors():
     assert L.rts_plan_autotune(pl.handle, 1, ctypes.byref(ci), ctypes.byref(co),
                                ctypes.c_void_p(100), n_tune, None, 1,
                                ctypes.byref(sch)) == rts.RTS_E_WORKSPACE
+
+
+def test_input_check_argument_errors():
+    # rts_check_inputs validates its arguments before any device call
+    p = inputs.workload("grey32", size=16)
+    pl = rts.Plan(p, rts.RTS_FP32)
+    L = rts.lib()
+    ok = rts.Inputs(256, 256, 256)
+    ws = ctypes.c_void_p(256)
+    assert L.rts_check_inputs(None, 1, ctypes.byref(ok), ws, 256, None) == rts.RTS_E_ARG
+    assert L.rts_check_inputs(pl.handle, 1, None, ws, 256, None) == rts.RTS_E_ARG
+    assert L.rts_check_inputs(pl.handle, 2, ctypes.byref(ok), ws, 256, None) == rts.RTS_E_ARG
+    for bad in (rts.Inputs(None, 256, 256), rts.Inputs(256, None, 256), rts.Inputs(256, 256, None)):
+        assert L.rts_check_inputs(pl.handle, 1, ctypes.byref(bad), ws, 256, None) == rts.RTS_E_ARG
+    assert L.rts_check_inputs(pl.handle, 1, ctypes.byref(ok), None, 256, None) == rts.RTS_E_WORKSPACE
+    assert L.rts_check_inputs(pl.handle, 1, ctypes.byref(ok), ctypes.c_void_p(100), 256,
+                              None) == rts.RTS_E_WORKSPACE
+    assert L.rts_check_inputs(pl.handle, 1, ctypes.byref(ok), ws, 255, None) == rts.RTS_E_WORKSPACE
+    # a scattering plan needs eps
+    gs = rts.Plan(inputs.random_problem(6, 5, 4, seed=1), rts.RTS_FP64, gs_iter=2)
+    assert L.rts_check_inputs(gs.handle, 1, ctypes.byref(ok), ws, 256, None) == rts.RTS_E_ARG
 
 
 def test_size_limits_rejected():

@@ -232,6 +232,85 @@ def test_autotune_keeps_results():
     assert pl2.autotune([ins], [outs], reps=1) == chosen
 
 
+def test_autotune_persisted_cache(tmp_path, monkeypatch):
+    # RTS_TUNE_CACHE names a file that is the cache: a tuning run appends one line
+    # "<key> <rows> <order> <single_launch>"; a later call (a fresh plan, or another
+    # process) whose key has a valid line applies it without timing
+    import torch
+    p = _rand_problem(52, 33, 21, seed=6).astype(np.float32)
+    ref = rts.solve(p, rts.RTS_FP32)
+    first = tmp_path / "a.txt"
+    monkeypatch.setenv("RTS_TUNE_CACHE", str(first))
+    pl = rts.Plan(p, rts.RTS_FP32)
+    ins = pl.device_inputs(p)
+    chosen = pl.autotune([ins], [pl.new_outputs(p)], reps=1)
+    lines = first.read_text().splitlines()
+    assert len(lines) == 1, lines
+    key, *vals = lines[0].split(" ")
+    assert key.startswith("gfx950") and [int(v) for v in vals] == [
+        chosen["rows_per_strip"], chosen["order"], chosen["single_launch"]]
+    # another file: a different valid schedule for this key, between lines to ignore
+    h = 2 if chosen["rows_per_strip"] != 2 else 6
+    second = tmp_path / "b.txt"
+    text = "\n".join([f"{key} 5 0 0", "garbage", f"{key} {h} {1 - chosen['order']} 0",
+                      f"{key}x 8 1 0", f"{key} 4 x 0"]) + "\n"
+    second.write_text(text)
+    monkeypatch.setenv("RTS_TUNE_CACHE", str(second))
+    pl2 = rts.Plan(p, rts.RTS_FP32)
+    outs = pl2.new_outputs(p)
+    for t in outs:
+        t.fill_(float("nan"))
+    got = pl2.autotune([ins], [outs], reps=1)
+    torch.cuda.synchronize()
+    assert (got["rows_per_strip"], got["order"], got["single_launch"]) == (
+        h, 1 - chosen["order"], 0)
+    assert all(bool(torch.isnan(t).all()) for t in outs)   # applied without a timed call
+    assert second.read_text() == text                       # a hit records nothing
+    for a, b in zip(ref, rts.solve(p, rts.RTS_FP32, plan=pl2)):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [rts.RTS_FP32, rts.RTS_FP64])
+def test_input_check_finds_nonfinite_values(prec):
+    # rts_check_inputs scans kappa, rho and S of every box (and eps of a scattering plan)
+    import torch
+    boxes = [_rand_problem(19, 11, 7, seed=21, bands=3), _rand_problem(9, 30, 12, seed=22),
+             _rand_problem(33, 5, 9, seed=23, bands=2)]
+    pl = rts.Plan(boxes, prec)
+    ins = [pl.device_inputs(b) for b in boxes]
+    print("case input check", prec, flush=True)
+    big = 3e38 if prec == rts.RTS_FP32 else 1e308
+    ins[1][2].view(-1)[5] = big                      # large and tiny finite values pass
+    ins[1][2].view(-1)[6] = 1e-40 if prec == rts.RTS_FP32 else 1e-310
+    pl.check_inputs(ins)
+    rng = np.random.default_rng(5)
+    for box, arr, val in ((2, 2, float("nan")), (0, 1, float("inf")), (1, 0, -float("inf")),
+                          (2, 2, float("-nan")), (0, 0, float("nan"))):
+        t = ins[box][arr].view(-1)
+        for k in (int(rng.integers(t.numel())), t.numel() - 1):   # anywhere, and the last value
+            keep = t[k].item()
+            t[k] = val
+            with pytest.raises(rts.RTSError) as e:
+                pl.check_inputs(ins)
+            assert e.value.status == rts.RTS_E_NONFINITE, (box, arr, k)
+            t[k] = keep
+            pl.check_inputs(ins)
+    torch.cuda.synchronize()
+
+
+def test_input_check_scans_eps_of_a_scattering_plan():
+    import torch
+    p = _rand_problem(8, 7, 6, seed=24)
+    pl = rts.Plan(p, rts.RTS_FP64, gs_iter=2)
+    kap, rho, S = pl.device_inputs(p)
+    eps = torch.full(S.shape, 0.5, dtype=torch.float64, device="cuda")
+    pl.check_inputs([(kap, rho, S, eps)])
+    eps.view(-1)[100] = float("nan")
+    with pytest.raises(rts.RTSError) as e:
+        pl.check_inputs([(kap, rho, S, eps)])
+    assert e.value.status == rts.RTS_E_NONFINITE
+
+
 def test_max_columns_and_extreme_opacity():
     # 1024 columns (the largest supported row), 16 + 1 threads' waves per strip;
     # opacities from 1e-6 (optically thin: x << 0.1, the series branch) to 1e4
