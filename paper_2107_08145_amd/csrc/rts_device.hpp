@@ -120,6 +120,33 @@ __device__ inline const T* lane_at(const T* row, uint32_t boff) {
   return reinterpret_cast<const T*>(reinterpret_cast<const char*>(row) + boff);
 }
 
+// Raw buffer access: a uniform 128-bit resource for a base address (4 GiB
+// range, 32-bit data format), a per-lane 32-bit byte offset and a uniform
+// byte offset.  No per-lane 64-bit address is formed or kept, so a load costs
+// one VGPR for its data (global instructions with a per-lane address let the
+// compiler hoist a 64-bit address pair per array and per row out of a loop).
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ inline Rsrc rts_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, -1, 0x00020000);
+}
+__device__ inline float buf_ld(Rsrc r, float*, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ inline double buf_ld(Rsrc r, double*, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <class Real>
+__device__ inline Real buf_load(Rsrc r, uint32_t voff, uint32_t soff) {
+  return buf_ld(r, (Real*)nullptr, voff, soff);
+}
+__device__ inline void buf_store(Rsrc r, uint32_t voff, uint32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+}
+__device__ inline void buf_store(Rsrc r, uint32_t voff, uint32_t soff, double v) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
 // Workgroup barrier for LDS traffic only: waits for this wave's LDS accesses,
 // not for its outstanding global stores (the sweep's global stores are read by
 // other workgroups through tags, never by this one).

@@ -54,13 +54,13 @@ template <class Real>
 hipError_t launch_block_sweep(const BlockArgs&, int, hipStream_t);
 
 template <class Real>
-size_t reverse_lds_bytes(int, bool);
+size_t reverse_lds_bytes(int);
 template <class Real>
-const void* reverse_fn(int cols, bool split);
-int reverse_threads(int cols);
-int reverse_parts(int cols);
+const void* reverse_fn(int cols);
 template <class Real>
-hipError_t launch_reverse(const RevArgs&, int, int, bool, hipStream_t);
+int reverse_rows(int cols);
+template <class Real>
+hipError_t launch_reverse(const RevArgs&, int, int, hipStream_t);
 template <class Real>
 hipError_t launch_adj_seed(const void*, const void*, const double*, const void*, void*, void*,
                            double, int, int, int, hipStream_t);
@@ -135,8 +135,9 @@ struct Plan {
   size_t off_flags = 0, off_tasks = 0, off_queue = 0, off_atasks = 0, off_rqueue = 0,
          off_data = 0, total = 0;
   // adjoint: the solve layout, then stored D planes, the reverse sweep's
-  // exchange buffers and gradient partials [off_grads, off_grads_end), seeds
-  size_t off_grads = 0, off_grads_end = 0, total_adj = 0;
+  // reverse exchange rings [off_grads, off_xrev_end) (cleared per call), gradient
+  // partials [off_xrev_end, off_grads_end), seeds
+  size_t off_grads = 0, off_xrev_end = 0, off_grads_end = 0, total_adj = 0;
   std::vector<AdjTask> atasks;
   std::vector<int32_t> rqueue;
   int rev_blocks = 0;
@@ -154,7 +155,6 @@ struct Plan {
     int max_strips;  // strips of its largest task
     int blocks;      // resident workgroups per CU
     bool uni;        // every task of the launch has four uniform slots
-    bool split;      // reverse: the launch runs slot-pair passes (AdjTask::part)
   };
   std::vector<WidthClass> wclasses;
   std::vector<WidthClass> rclasses;  // the same for the reverse sweep (threads: padded columns)
@@ -237,19 +237,6 @@ int validate_desc(const rts_desc& d) {
 }
 
 // Build every task of every box and the workspace layout for the current schedule.
-// The reverse sweep of a task runs as two slot-pair passes when its four-slot
-// form cannot have every two-row strip resident: that form takes one
-// workgroup per CU (two waves per SIMD at up to 256 VGPRs, or a 1024-thread
-// block) and its LDS state per column; gfx950 has 256 CUs with 160 KB of LDS
-// each (the residency is checked on the device before a call).
-constexpr int kCUs = 256;
-constexpr size_t kLdsPerCU = 160 * 1024;
-bool reverse_split(int prec, int cols, int rows) {
-  const size_t lds = prec == RTS_FP32 ? reverse_lds_bytes<float>(cols, false)
-                                      : reverse_lds_bytes<double>(cols, false);
-  return lds > kLdsPerCU || (rows + kRevRows - 1) / kRevRows > kCUs;
-}
-
 void build_layout(Plan& P) {
   P.tasks.clear();
   P.queue.clear();
@@ -527,50 +514,43 @@ void build_layout(Plan& P) {
     off = align_up(off + (size_t)T.n_unrolled * kMaxRaysPerTask * pc * esz);
   }
   P.off_grads = off;
-  // A task whose four-slot reverse state does not fit (LDS per CU, or every
-  // strip of two rows resident, one workgroup per CU) is swept in reverse as
-  // two slot-pair passes (even slots, odd slots) with taller strips: the rays
-  // of a task are independent in reverse and their gradients only add.
+  // Every task is reversed as two slot-pair passes (slots 0, 2 and 1, 3: the
+  // rays of a task are independent in reverse and their gradients only add),
+  // each with strips of the reverse launch's rows for its width class.
   const int ntask = (int)P.tasks.size();
   for (int t = 0; t < ntask; ++t) {
     const Task& T = P.tasks[t];
     AdjTask& AT = P.atasks[t];
     const int cols = P.sched.single_launch ? P.threads : (T.n_cols + 63) / 64 * 64;
+    const int hr = P.prec == RTS_FP32 ? reverse_rows<float>(cols) : reverse_rows<double>(cols);
     AT.task = t;
     AT.u_init = T.z_planes ? 0 : -1;
-    AT.split = P.sched.split_reverse || reverse_split(P.prec, cols, T.n_rows) ? 1 : 0;
     AT.part = 0;
-    const int hr = AT.split ? (P.prec == RTS_FP32 ? 4 : 2) : kRevRows;
     AT.strips = (T.n_rows + hr - 1) / hr;
-    if (AT.split) {
-      AdjTask second = AT;
-      second.part = 1;
-      P.atasks.push_back(second);
-    }
+    AT.nparts = 2;
+    AdjTask second = AT;
+    second.part = 1;
+    P.atasks.push_back(second);
   }
-  for (AdjTask& AT : P.atasks) {  // (every pass has its own exchange buffer)
+  // exchange rings and progress words of every pass (cleared by every call)
+  for (AdjTask& AT : P.atasks) {
     const Task& T = P.tasks[AT.task];
     AT.xbuf_off = (int64_t)(off / sizeof(uint64_t));
-    // [strip][parity][edge][slot pair][3][col][words]; a split pass depends on
-    // one neighbour only and keeps every step: [strip][step][slot pair][3][col][words]
-    const size_t depth = AT.split ? (size_t)(T.n_unrolled - AT.u_init) : 2 * 2;
-    off = align_up(off + (size_t)AT.strips * depth * 6 * T.n_cols * words * sizeof(uint64_t));
+    off = align_up(off + (size_t)rev_ring_words(AT.strips, T.n_cols, (int)words) * sizeof(uint64_t) +
+                   (size_t)AT.strips * sizeof(int32_t));
   }
+  P.off_xrev_end = off;
+  // gradient partials, one per pass (each pass writes every cell at its first
+  // visit, so they are not cleared)
   for (int t = 0; t < ntask; ++t) {
     const Box& B = P.boxes[P.tasks[t].box];
-    // one partial per thread of a column of the task's reverse launch, or per pass
-    const int np = P.atasks[t].split ? 2
-                   : reverse_parts(P.sched.single_launch ? P.threads
-                                                         : (P.tasks[t].n_cols + 63) / 64 * 64);
-    P.atasks[t].nparts = np;
     P.atasks[t].gs_off = (int64_t)(off / esz);
-    off = align_up(off + np * (size_t)B.N * esz);
+    off = align_up(off + 2 * (size_t)B.N * esz);
     P.atasks[t].gc_off = (int64_t)(off / esz);
-    off = align_up(off + np * (size_t)B.N * esz);
+    off = align_up(off + 2 * (size_t)B.N * esz);
   }
   for (size_t a = ntask; a < P.atasks.size(); ++a) {  // second passes share the partials
     const AdjTask& first = P.atasks[P.atasks[a].task];
-    P.atasks[a].nparts = first.nparts;
     P.atasks[a].gs_off = first.gs_off;
     P.atasks[a].gc_off = first.gc_off;
   }
@@ -591,12 +571,10 @@ void build_layout(Plan& P) {
   auto rwidth = [&](int a) {
     return P.sched.single_launch ? 0 : (P.tasks[P.atasks[a].task].n_cols + 63) / 64 * 64;
   };
-  auto split_of = [&](int a) { return P.atasks[a].split != 0; };
   auto rlen = [&](int a) { return P.tasks[P.atasks[a].task].n_unrolled - P.atasks[a].u_init; };
   std::vector<int> rq(P.atasks.size());
   for (size_t i = 0; i < rq.size(); ++i) rq[i] = (int)i;
   std::stable_sort(rq.begin(), rq.end(), [&](int a, int b) {
-    if (split_of(a) != split_of(b)) return split_of(a);
     if (rwidth(a) != rwidth(b)) return rwidth(a) > rwidth(b);
     return rlen(a) > rlen(b);
   });
@@ -605,9 +583,8 @@ void build_layout(Plan& P) {
   int rticket = 0;
   for (size_t k = 0; k < rq.size(); ++k) {
     const int i = rq[k];
-    if (P.rclasses.empty() || P.rclasses.back().width != rwidth(i) ||
-        P.rclasses.back().split != split_of(i)) {
-      P.rclasses.push_back(Plan::WidthClass{rwidth(i), 64, (int)k, 0, 0, 1, 0, true, split_of(i)});
+    if (P.rclasses.empty() || P.rclasses.back().width != rwidth(i)) {
+      P.rclasses.push_back(Plan::WidthClass{rwidth(i), 64, (int)k, 0, 0, 1, 0, true});
       rticket = 0;
     }
     Plan::WidthClass& c = P.rclasses.back();
@@ -687,9 +664,12 @@ int occupancy_h(Plan& P) {
   }
   P.rev_blocks = 1 << 30;
   for (Plan::WidthClass& c : P.rclasses) {
-    int rc = resident_blocks(reverse_fn<Real>(c.threads, c.split),
-                             c.split ? c.threads : reverse_threads(c.threads),
-                             reverse_lds_bytes<Real>(c.threads, c.split), &c.blocks);
+    const void* fn = reverse_fn<Real>(c.threads);
+    if (!fn) {  // (wider than the reverse sweep supports: no resident block)
+      c.blocks = 0;
+      continue;
+    }
+    int rc = resident_blocks(fn, c.threads, reverse_lds_bytes<Real>(c.threads), &c.blocks);
     if (rc) return rc;
     P.rev_blocks = std::min(P.rev_blocks, c.blocks);
   }
@@ -963,7 +943,7 @@ int enqueue_adjoint(Plan& P, const rts_inputs* in, const rts_seeds* g, const rts
     RTS_HIP(upload_tables(P, ws, st));
   }
   RTS_HIP(launch_zero(reinterpret_cast<int*>(ws + P.off_grads),
-                      (int64_t)((P.off_grads_end - P.off_grads) / sizeof(int32_t)), st));
+                      (int64_t)((P.off_xrev_end - P.off_grads) / sizeof(int32_t)), st));
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     const Box& B = P.boxes[b];
     Real* base = reinterpret_cast<Real*>(ws);
@@ -995,7 +975,7 @@ int enqueue_adjoint(Plan& P, const rts_inputs* in, const rts_seeds* g, const rts
     a.total_strips = c.strips;
     a.wclass = (int)k;
     const int grid = std::max(1, std::min(c.blocks * P.cus, c.strips));
-    RTS_HIP(launch_reverse<Real>(a, grid, c.threads, c.split, st));
+    RTS_HIP(launch_reverse<Real>(a, grid, c.threads, st));
   }
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     const BoxGeo G = box_geo(P, b);
@@ -1575,14 +1555,6 @@ int adjoint_checks(Plan* P, int32_t nbox, const rts_inputs* in, void* ws, size_t
       g_last_hip = "the strips of one reverse sweep task cannot all be resident";
       return RTS_E_UNSUPPORTED;
     }
-  for (const AdjTask& AT : P->atasks) {  // (the kernel's exchange offsets are 32-bit)
-    const Task& T = P->tasks[AT.task];
-    const int64_t depth = AT.split ? T.n_unrolled - AT.u_init : 4;
-    if ((int64_t)AT.strips * depth * 6 * T.n_cols * (P->prec == RTS_FP32 ? 1 : 2) >= (1ll << 31)) {
-      g_last_hip = "the exchange buffer of a reverse sweep pass exceeds 2^31 words";
-      return RTS_E_UNSUPPORTED;
-    }
-  }
   return RTS_OK;
 }
 }  // namespace

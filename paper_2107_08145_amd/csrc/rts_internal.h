@@ -77,21 +77,27 @@ struct Task {
   TaskRay ray[kMaxRaysPerTask];
 };
 
-// Reverse sweep of one task, for the adjoint: a persistent strip sweep like
-// the forward one, planes in reverse order, kRevRows rows per strip.
-constexpr int kRevRows = 2;
+// Reverse sweep of one task, for the adjoint: two slot-pair passes (slots 0,
+// 2 and slots 1, 3), each a persistent strip sweep like the forward one,
+// planes in reverse order.  A pass's strips exchange their edge rows through
+// a ring of kRevRing steps per strip: ring[strip][kRevRing][2 slots][3][col]
+// [64-bit words], followed by one progress word (int32) per strip.
+constexpr int kRevRing = 8;
+constexpr int64_t rev_ring_words(int strips, int cols, int words) {
+  return (int64_t)strips * kRevRing * 6 * cols * words;
+}
+
 struct AdjTask {
-  int32_t task;       // index into the Task table (AdjTask i < ntasks belongs to Task i; a
-                      // task reversed in two passes has its second pass after the ntasks)
+  int32_t task;       // index into the Task table (AdjTask i < ntasks is the first pass of
+                      // Task i; the second passes follow the ntasks)
   int32_t u_init;     // last unrolled plane of the reverse: -1 (ghost plane) or 0
-  int32_t strips;     // strips of kRevRows rows (split passes: rows of their launch)
-  int32_t nparts;     // gradient partials per quantity (threads per column of its reverse
-                      // launch, or 2 for a task reversed in two passes)
-  int32_t split;      // 1: reversed as two slot-pair passes, one workgroup per strip and pass
-  int32_t part;       // split: this pass's slot parity (slots part and part + 2)
-  int64_t xbuf_off;   // 64-bit word offset of the exchange buffer [strip][parity][edge][2][3][col][words]
-  int64_t gs_off;     // Real offset of this task's dL/dS partial (task array layout)
-  int64_t gc_off;     // Real offset of this task's dL/dchi partial (task array layout)
+  int32_t strips;     // strips of the reverse launch's rows (rev_rows of its width)
+  int32_t nparts;     // gradient partials per quantity: 2, one per pass
+  int32_t part;       // this pass's slot parity (slots part and part + 2)
+  int32_t pad;
+  int64_t xbuf_off;   // 64-bit word offset of the pass's exchange ring and progress words
+  int64_t gs_off;     // Real offset of this task's dL/dS partials [part][task array layout]
+  int64_t gc_off;     // Real offset of this task's dL/dchi partials [part][task array layout]
   int64_t seed_off;   // Real offset of the band's seed in the task array layout
 };
 

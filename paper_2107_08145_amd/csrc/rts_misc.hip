@@ -674,9 +674,6 @@ hipError_t launch_adj_reduce(const char* ws, const Task* tasks, const AdjTask* a
 }
 
 
-// Reverse sweep launch shape (see rts_reverse.hpp): partials per column and threads.
-int reverse_parts(int cols) { return cols <= 256 ? 2 : 1; }
-int reverse_threads(int cols) { return reverse_parts(cols) * cols; }
 
 // explicit instantiations
 template hipError_t launch_prep<float>(const void*, const void*, const void*, void*, int64_t,

@@ -602,7 +602,10 @@ __global__ __launch_bounds__(1024) void rts_sweep(SweepArgs A) {
     while (qi + 1 < A.ntasks && queue[2 * (qi + 1)] <= tk) ++qi;
     CTask& T = ((CTask*)(uintptr_t)A.tasks)[queue[2 * qi + 1]];
     const int strip = tk - queue[2 * qi];
-    if ((strip + 1) * T.rows_per_strip <= T.n_rows) run_strip<Real, H, UNI, true, EXT>(A, T, strip, lds);
+    // a full strip has the template's H rows (a task with fewer rows than H has
+    // one strip of all its rows: not full)
+    if (T.rows_per_strip == H && (strip + 1) * H <= T.n_rows)
+      run_strip<Real, H, UNI, true, EXT>(A, T, strip, lds);
     else run_strip<Real, H, UNI, false, EXT>(A, T, strip, lds);
   }
 }

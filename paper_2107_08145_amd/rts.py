@@ -114,6 +114,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"librts.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        try:
+            # torch ships its own HIP runtime under the same soname: loaded first, it is the
+            # one librts binds to (loaded after librts, it would be a second runtime in the
+            # process and find no GPU)
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
         L.rts_plan_create.argtypes = [ctypes.POINTER(Desc), i32, ctypes.POINTER(vp)]

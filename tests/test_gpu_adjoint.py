@@ -100,66 +100,73 @@ def test_adjoint_fp32_matches_oracle():
     print(f"adjoint fp32: {e:.2e}")
 
 
-# Planes wider than 256 columns take the one-thread-per-column reverse shapes:
-# a 512-thread block up to 512 columns, a 1024-thread block above.
+# Every task is reversed as two slot-pair passes, one thread per column, with
+# strips as tall as each width class allows (FP32: 6 rows up to 512 padded
+# columns, 3 up to 768, 2 up to 1024; FP64: 2 rows up to 512, 1 up to 768):
+# one case per class, with partial last strips and exchange rings that wrap.
 @pytest.mark.parametrize("prec,shape", [(rts.RTS_FP32, (300, 20, 9)),
                                         (rts.RTS_FP64, (300, 12, 8)),
-                                        (rts.RTS_FP32, (520, 10, 6))])
+                                        (rts.RTS_FP32, (520, 10, 6)),
+                                        (rts.RTS_FP32, (700, 9, 5)),
+                                        (rts.RTS_FP32, (900, 7, 5)),
+                                        (rts.RTS_FP64, (600, 7, 4))])
 def test_adjoint_wide_planes(prec, shape):
     nx, ny, nz = shape
     p = inputs.random_problem(nx, ny, nz, seed=nx + ny, bands=2)
     print("case adjoint wide", prec, shape, flush=True)
     tol = 1e-10 if prec == rts.RTS_FP64 else 2e-4
-    e = _run(p, prec, _seeds(p, 8), tol)
+    e = _run(p, prec, _seeds(p, 8), tol, threads=16)
     print(f"adjoint wide {shape}: {e:.2e}")
 
 
-def test_adjoint_fp64_plane_beyond_lds_is_unsupported():
-    # 600 FP64 columns (640 padded) need more LDS per reverse strip than a CU
-    # has even for one slot pair
-    p = inputs.random_problem(600, 6, 4, seed=3)
-    print("case adjoint fp64 600 columns", flush=True)
+def test_adjoint_fp64_plane_beyond_the_reverse_shapes_is_unsupported():
+    # FP64 reverse strips are at most 768 columns wide
+    p = inputs.random_problem(800, 6, 4, seed=3)
+    print("case adjoint fp64 800 columns", flush=True)
     with pytest.raises(rts.RTSError, match="UNSUPPORTED"):
         rts.adjoint(p, rts.RTS_FP64, *_seeds(p, 9))
 
 
-# Split reverse passes: a task reversed as two slot-pair passes (even slots,
-# odd slots) in separate workgroups, each with its own gradient partial.
-# Forced on small problems (schedule split_reverse = 1), and taken by the
-# library itself where the four-slot form does not fit: 520 FP64 columns
-# (LDS), a 576 x 576 plane (576 rows: 288 two-row strips, more than one per CU).
+# Strip chains: periodic rows (z planes), bounded rows (x and y planes) with
+# partial last strips, one-strip tasks, and the schedule's split_reverse flag
+# (accepted, no effect: results are bitwise those of the default).
 @pytest.mark.parametrize("case", [
     dict(prec=rts.RTS_FP64, shape=(20, 13, 11), seed=51),
     dict(prec=rts.RTS_FP64, shape=(24, 20, 14), seed=52, bot=1, top=1, i_bot=1.7, n_iter=3),
     dict(prec=rts.RTS_FP64, shape=(33, 9, 17), seed=53, bands=2, top=0, n_iter=4),
     dict(prec=rts.RTS_FP32, shape=(40, 36, 30), seed=54, lo=1e-3, hi=1e3),
-    dict(prec=rts.RTS_FP32, shape=(300, 20, 9), seed=55, bands=2),
+    dict(prec=rts.RTS_FP32, shape=(17, 5, 3), seed=56, n_iter=2),
+    dict(prec=rts.RTS_FP32, shape=(64, 64, 61), seed=57, bands=2),
 ])
-def test_adjoint_split_passes_match_oracle(case):
+def test_adjoint_strip_chains_match_oracle(case):
     c = dict(case)
     prec, shape, seed = c.pop("prec"), c.pop("shape"), c.pop("seed")
     p = inputs.random_problem(*shape, seed=seed, **c)
     pp = p.astype(np.float32) if prec == rts.RTS_FP32 else p
-    pl = rts.Plan(pp, prec)
-    pl.set_schedule(split_reverse=1)
-    print("case adjoint split", prec, shape, flush=True)
+    print("case adjoint strips", prec, shape, flush=True)
     tol = 1e-10 if prec == rts.RTS_FP64 else 2e-4
     gQ, gJ, gI = _seeds(p, seed)
-    got = rts.adjoint(pp, prec, gQ, gJ, gI, plan=pl)
+    got = rts.adjoint(pp, prec, gQ, gJ, gI)
     ref = oracle.adjoint(pp.astype(np.float64), gQ, gJ.astype(pp.S.dtype).astype(np.float64),
                          gI.astype(pp.S.dtype).astype(np.float64), threads=8)
     e = _cmp(got, ref, tol)
-    print(f"adjoint split {shape}: {e:.2e}")
+    print(f"adjoint strips {shape}: {e:.2e}")
+    pl = rts.Plan(pp, prec)
+    pl.set_schedule(split_reverse=1)
+    again = rts.adjoint(pp, prec, gQ, gJ, gI, plan=pl)
+    for a, b in zip(got, again):
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("prec,shape", [(rts.RTS_FP64, (520, 6, 4)),
                                         (rts.RTS_FP32, (576, 576, 5))])
-def test_adjoint_split_where_four_slots_do_not_fit(prec, shape):
+def test_adjoint_wide_and_tall_planes(prec, shape):
+    # 520 FP64 columns; a 576 x 576 z plane (192 strips of 3 rows per pass)
     p = inputs.random_problem(*shape, seed=shape[0] + shape[2], bands=1)
-    print("case adjoint split automatic", prec, shape, flush=True)
+    print("case adjoint wide and tall", prec, shape, flush=True)
     tol = 1e-10 if prec == rts.RTS_FP64 else 2e-4
     e = _run(p, prec, _seeds(p, 10), tol, threads=16)
-    print(f"adjoint split automatic {shape}: {e:.2e}")
+    print(f"adjoint wide and tall {shape}: {e:.2e}")
 
 
 def test_adjoint128_fp32_small_matches_oracle():

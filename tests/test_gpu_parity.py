@@ -311,6 +311,24 @@ def test_input_check_scans_eps_of_a_scattering_plan():
     assert e.value.status == rts.RTS_E_NONFINITE
 
 
+@pytest.mark.parametrize("rows", [4, 6, 8])
+@pytest.mark.parametrize("shape", [(17, 5, 3), (9, 2, 7), (6, 3, 2)])
+def test_tasks_with_fewer_rows_than_a_strip(rows, shape):
+    # a task whose plane has fewer rows than the strip height is one strip of
+    # all its rows (the x and y sweeps of a 3-layer box, the z sweeps of a box
+    # 2 or 3 cells deep in y)
+    p = _rand_problem(*shape, seed=rows + shape[2], bands=2, n_iter=2)
+    p32 = p.astype(np.float32)
+    pl = rts.Plan(p32, rts.RTS_FP32)
+    pl.set_schedule(rows_per_strip=rows)
+    print("case few rows", shape, rows, flush=True)
+    _check32(p32, rts.solve(p32, rts.RTS_FP32, plan=pl), oracle.solve(p32.astype(np.float64)))
+    if rows == 4:
+        pl64 = rts.Plan(p, rts.RTS_FP64)
+        pl64.set_schedule(rows_per_strip=4)
+        _check64(p, rts.solve(p, rts.RTS_FP64, plan=pl64), oracle.solve(p))
+
+
 def test_max_columns_and_extreme_opacity():
     # 1024 columns (the largest supported row), 16 + 1 threads' waves per strip;
     # opacities from 1e-6 (optically thin: x << 0.1, the series branch) to 1e4
