@@ -150,6 +150,25 @@ def trace_summary(d, by_workgroup=False):
     return out
 
 
+def counter_summary(dirs, key):
+    """Per kernel whose name contains `key`: dispatches and the mean per dispatch of
+    every counter in the rocprofv3 --pmc databases under `dirs` (instances summed)."""
+    import sqlite3
+    per = {}
+    for d in dirs:
+        for f in _db_files(d):
+            c = sqlite3.connect(f)
+            q = ("select k.name, p.dispatch_id, p.counter_name, sum(p.counter_value) from pmc_events p "
+                 "join kernels k on p.dispatch_id = k.dispatch_id group by p.dispatch_id, p.counter_name")
+            for name, disp, ctr, v in c.execute(q).fetchall():
+                if key in name:
+                    per.setdefault(name, {}).setdefault(ctr, []).append(float(v))
+    out = {}
+    for name, ctrs in per.items():
+        out[name] = {ctr: {"dispatches": len(v), "mean": sum(v) / len(v)} for ctr, v in sorted(ctrs.items())}
+    return out
+
+
 def pmc_summary(workload, rows, fetch_dir, write_dir, cfetch_dir, cwrite_dir):
     """HBM bytes per sweep launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch)
     scaled by the same counters' reading for the plain copy kernel.  Merged
@@ -643,7 +662,14 @@ def main():
                          "plan's choice, and the other form timed beside it)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs into profiles/")
+    ap.add_argument("--counter-summary", nargs="+", metavar="PMC_DIR",
+                    help="print the mean per dispatch of every counter of rocprofv3 --pmc runs "
+                         "for the kernels named by --kernel")
+    ap.add_argument("--kernel", default="rts_", help="with --counter-summary: kernel name substring")
     args = ap.parse_args()
+    if args.counter_summary:
+        print(json.dumps(counter_summary(args.counter_summary, args.kernel), indent=1))
+        return
     if args.calibrate_copy:
         calibrate_copy()
         return

@@ -114,7 +114,9 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
   const int U = T.n_unrolled, u_init = AT.u_init;
   const int K = U - u_init;
   const int last_from = zp ? 0 : (T.laps - 1) * na;
-  auto plane_of = [&](int u) { return u < 0 ? q_last : q0 + T.sa * (zp ? u : u % na); };
+  // the plane before plane q in the sweep (planes of unrolled u-1 from u; a
+  // periodic sweep's first plane is preceded by its last, the ghost plane)
+  auto prev_plane = [&](int q) { return (!zp && q == q0) ? q_last : q - T.sa; };
   Real f1[2], f2[2], hds[2], wgt[2];
   int itop[2];
 #pragma unroll
@@ -172,10 +174,11 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
   for (int i = 0; i < H; ++i) {  // (a ghost or boundary step reads them unused)
     dq[i][0] = dq[i][1] = sdv[i] = gsv[i] = gcv[i] = cpv[i] = spv[i] = Real(0);
   }
-  auto load_up = [&](int k) __attribute__((always_inline)) {
+  // (k: the step; q: the plane the loads are of)
+  auto load_up = [&](int k, int q) __attribute__((always_inline)) {
     const int u = U - 1 - k;
     if (k < K && u >= 0 && !(zp && u == 0)) {
-      const int qo = plane_of(u - 1) * ps;
+      const int qo = q * ps;
 #pragma unroll
       for (int j = 0; j < H + 2; ++j) {
         const int o = qo + up_row(j) * rs;
@@ -184,11 +187,11 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
       }
     }
   };
-  auto load_own = [&](int k, int i) __attribute__((always_inline)) {
+  auto load_own = [&](int k, int i, int q) __attribute__((always_inline)) {
     const int u = U - 1 - k;
     if (k >= K || u < 0) return;  // (the ghost plane is not in the last lap: no seed)
     const int gi = own_row(i);
-    const int o = plane_of(u) * ps + gi * rs;
+    const int o = q * ps + gi * rs;
     if (u >= last_from) sdv[i] = buf_load<Real>(rSeed, cb, (uint32_t)o * sizeof(Real));
     if (zp && u == 0) return;  // the boundary plane: no recompute
     const Rsrc rD = rts_rsrc(Dst + (int64_t)u * R * pc);
@@ -196,10 +199,10 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
     for (int s = 0; s < 2; ++s)
       dq[i][s] = buf_load<Real>(rD, cb, (uint32_t)(((part + 2 * s) * nr + gi) * W) * sizeof(Real));
   };
-  auto load_part = [&](int k, int i) __attribute__((always_inline)) {
+  auto load_part = [&](int k, int i, int q) __attribute__((always_inline)) {
     const int u = U - 1 - k;
     if (k >= K || u >= last_from) return;  // the first visit of a cell writes its partial
-    const int o = plane_of(u) * ps + own_row(i) * rs;
+    const int o = q * ps + own_row(i) * rs;
     gsv[i] = buf_load<Real>(rGS, cb, (uint32_t)o * sizeof(Real));
     gcv[i] = buf_load<Real>(rGC, cb, (uint32_t)o * sizeof(Real));
   };
@@ -277,11 +280,13 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
     for (int m = 0; m < 3; ++m) lc[ST::qh(s, m)] = Real(0);
 
   const int top = FULL ? H - 1 : hr - 1;
+  // the plane of the first step (unrolled plane U-1)
+  int qp = q0 + T.sa * (zp ? U - 1 : (U - 1) % na);
   // first step: its own rows' chi and S from memory
   {
     const int u = U - 1;
     if (u >= 0 && !(zp && u == 0)) {
-      const int qo = plane_of(u) * ps;
+      const int qo = qp * ps;
 #pragma unroll
       for (int i = 0; i < H; ++i) {
         const int o = qo + own_row(i) * rs;
@@ -290,16 +295,16 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
       }
     }
   }
-  load_up(0);
+  load_up(0, prev_plane(qp));
 #pragma unroll
   for (int i = 0; i < H; ++i) {
-    load_own(0, i);
-    load_part(0, i);
+    load_own(0, i, qp);
+    load_part(0, i, qp);
   }
 
   for (int k = 0; k < K; ++k) {
     const int u = U - 1 - k;
-    const int qp = plane_of(u);
+    const int qn = prev_plane(qp);  // the plane of u - 1 (the next step's)
     const bool ghost = u < 0;
     const bool bcplane = zp && u == 0;
     const bool last_lap = u >= last_from;
@@ -311,7 +316,7 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
         lc[ST::qs(j)] = ups[j];
       }
     }
-    load_up(k + 1);  // in flight during this step
+    load_up(k + 1, prev_plane(qn));  // in flight during this step
     lds_barrier();   // halo row, upwind plane and downwind state complete
     // every wave has its copy of ring entry k: the producer may reuse it
     if (k > 0 && threadIdx.x == 0) st_dev(progress + strip, k);
@@ -380,8 +385,8 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
         buf_store(rGC, cb, (uint32_t)o * sizeof(Real), last_lap ? gc : gcv[i] + gc);
       }
       // this row's registers are free: the next step's own-row loads
-      load_own(k + 1, i);
-      load_part(k + 1, i);
+      load_own(k + 1, i, qn);
+      load_part(k + 1, i, qn);
       __builtin_amdgcn_sched_barrier(0);
     };
     // the published edge row first (even pass: the first row; odd: the last), then the rest
@@ -437,6 +442,7 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
       }
     }
     if (k + 1 < K) halo_issue(k + 1);
+    qp = qn;
   }
 }
 
