@@ -205,13 +205,9 @@ typedef struct {
                              identical; adjoint gradients differ by rounding only (a task's
                              slot contributions are summed over as many partials as its
                              reverse launch has threads per column). */
-  int32_t split_reverse;  /* 0: the adjoint's reverse sweep takes a task's four ray slots in one
-                             workgroup per strip, except for tasks whose strips could not all be
-                             resident that way (planes wider than about 670 columns in FP32 or
-                             330 in FP64, or more than 512 rows), which are reversed as two
-                             slot-pair passes (even slots, odd slots; strips of 4 rows in FP32,
-                             2 in FP64); 1: every task as two passes.  Gradients differ by
-                             rounding only. */
+  int32_t split_reverse;  /* accepted (0 or 1) and without effect: the adjoint's reverse sweep
+                             always takes a task as two slot-pair passes (kept so that
+                             schedules written for earlier versions stay valid) */
 } rts_schedule;
 
 /* Create a plan for `nbox` boxes (host only; validates every field; the
@@ -245,10 +241,14 @@ int rts_solve_batched(void* plan, int32_t nbox, const rts_inputs* in, const rts_
  * "Summary of the Radiation Transport Solver" section as implemented by
  * rts_solve): the call re-runs the forward sweep, storing D of every plane
  * and lap in the workspace, then sweeps the transposed recursion downwind to
- * upwind in one persistent launch per workgroup width (strips of two rows
- * exchanging edge rows, like the forward sweep), recomputing the exp and interpolation weights from
- * the stored upwind D.  Returns RTS_E_UNSUPPORTED if a box has tol > 0, or if the strips of one task
- * cannot all be resident.  Seeds may be NULL (zero).  dS and dchi are
+ * upwind in one persistent launch per workgroup width: every task as two
+ * slot-pair passes (slots 0, 2 and 1, 3), strips of rows exchanging edge rows
+ * with the one neighbour they depend on, recomputing the exp and
+ * interpolation weights from chi and S and the upwind D from the cell's own
+ * stored D.  Returns RTS_E_UNSUPPORTED if a box has tol > 0, for sweep planes
+ * wider than 768 padded columns in FP64 (1024 in FP32), or if the strips of
+ * one pass cannot all be resident (one workgroup per strip, at most one or
+ * two per CU).  Seeds may be NULL (zero).  dS and dchi are
  * overwritten; chi = kappa * rho, so dL/dkappa_b = rho dL/dchi_b and
  * dL/drho = sum_b kappa_b dL/dchi_b.  Per-task partials are summed in a
  * fixed order in FP64: results are bitwise reproducible for a fixed plan. */

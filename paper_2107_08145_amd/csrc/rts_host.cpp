@@ -522,7 +522,9 @@ void build_layout(Plan& P) {
     const Task& T = P.tasks[t];
     AdjTask& AT = P.atasks[t];
     const int cols = P.sched.single_launch ? P.threads : (T.n_cols + 63) / 64 * 64;
-    const int hr = P.prec == RTS_FP32 ? reverse_rows<float>(cols) : reverse_rows<double>(cols);
+    // (0 for a width the reverse sweep does not support: refused at the call)
+    const int hr = std::max(1, P.prec == RTS_FP32 ? reverse_rows<float>(cols)
+                                                  : reverse_rows<double>(cols));
     AT.task = t;
     AT.u_init = T.z_planes ? 0 : -1;
     AT.part = 0;

@@ -479,63 +479,98 @@ void rts_reverse(RevArgs A) {
 }
 
 
-// Launch shape of the reverse sweep for `cols` padded columns: one thread
-// per column, strips of rev_rows rows, as tall as the registers of a block of
-// that many waves allow without spilling (the LDS state of every column,
-// RevStrip, fits with room to spare):
-//   FP32: up to 256 columns 6 rows (two blocks per CU), 512: 6, 768: 3, 1024: 2.
-//   FP64: up to 256 columns 2 rows (two blocks per CU), 512: 2, 768: 1 (wider: not supported).
-template <class Real>
-constexpr int rev_rows(int cols) {
-  return sizeof(Real) == 4 ? (cols <= 512 ? 6 : cols <= 768 ? 3 : 2)
-                           : (cols <= 512 ? 2 : 1);
+// Launch shapes of the reverse sweep by padded width (classes up to 128, 256,
+// 512, 768 and 1024 columns): one thread per column, strips of H rows, as tall
+// as the registers of a block of that many waves allow without spilling (the
+// LDS state of every column, RevStrip, fits with room to spare), with the
+// waves-per-SIMD bounds (W0, W1) of the kernel:
+//   FP32: 4 rows up to 128 columns (three waves per SIMD; a few registers
+//         spill), 6 up to 512, 3 up to 768, 2 up to 1024;
+//   FP64: 2 rows up to 512 columns, 1 up to 768 (wider: not supported).
+// Taller strips amortise a step's fixed costs (barriers, the exchange, the
+// loads' latency) over more cells; on planes of up to 128 columns the extra
+// resident waves of 4-row strips win over 6 rows (measured on the 96^2 x 512
+// box and at 128^3; 3 and 4 rows lose to 6 from 192 columns on).
+template <class Real, int C>
+struct RevShape;
+template <> struct RevShape<float, 0> { static constexpr int H = 4, T = 128, W0 = 3, W1 = 3; };
+template <> struct RevShape<float, 1> { static constexpr int H = 6, T = 256, W0 = 2, W1 = 2; };
+template <> struct RevShape<float, 2> { static constexpr int H = 6, T = 512, W0 = 1, W1 = 2; };
+template <> struct RevShape<float, 3> { static constexpr int H = 3, T = 768, W0 = 3, W1 = 3; };
+template <> struct RevShape<float, 4> { static constexpr int H = 2, T = 1024, W0 = 4, W1 = 4; };
+template <> struct RevShape<double, 0> { static constexpr int H = 2, T = 128, W0 = 2, W1 = 2; };
+template <> struct RevShape<double, 1> { static constexpr int H = 2, T = 256, W0 = 2, W1 = 2; };
+template <> struct RevShape<double, 2> { static constexpr int H = 2, T = 512, W0 = 1, W1 = 2; };
+template <> struct RevShape<double, 3> { static constexpr int H = 1, T = 768, W0 = 3, W1 = 3; };
+
+constexpr int rev_class(int cols) {
+  return cols <= 128 ? 0 : cols <= 256 ? 1 : cols <= 512 ? 2 : cols <= 768 ? 3 : 4;
 }
 template <class Real>
-constexpr int rev_max_cols() {
-  return sizeof(Real) == 4 ? 1024 : 768;
+constexpr int rev_classes() {
+  return sizeof(Real) == 4 ? 5 : 4;
+}
+template <class Real, int C>
+using RevSh = RevShape<Real, C>;
+template <class Real, int C>
+constexpr const void* rev_kernel() {
+  using S = RevSh<Real, C>;
+  return reinterpret_cast<const void*>(&rts_reverse<Real, S::H, S::T, S::W0, S::W1>);
 }
 
-template <class Real, int H>
-constexpr size_t rev_lds(int cols) {
-  return (size_t)RevStrip<Real, H>::NQP * cols * sizeof(Real);
+// Calls f(shape) for the class of `cols` (false when the class is not built).
+template <class Real, class F>
+bool rev_dispatch(int cols, F&& f) {
+  switch (rev_class(cols)) {
+    case 0: f(RevSh<Real, 0>{}); return true;
+    case 1: f(RevSh<Real, 1>{}); return true;
+    case 2: f(RevSh<Real, 2>{}); return true;
+    case 3: f(RevSh<Real, 3>{}); return true;
+    case 4:
+      if constexpr (rev_classes<Real>() > 4) {
+        f(RevSh<Real, 4>{});
+        return true;
+      }
+      return false;
+  }
+  return false;
 }
+
 template <class Real>
 size_t reverse_lds_bytes(int cols) {
-  switch (rev_rows<Real>(cols)) {
-    case 6: return rev_lds<Real, 6>(cols);
-    case 3: return rev_lds<Real, 3>(cols);
-    case 2: return rev_lds<Real, 2>(cols);
-    default: return rev_lds<Real, 1>(cols);
-  }
+  size_t b = 0;
+  rev_dispatch<Real>(cols, [&](auto S) {
+    b = (size_t)RevStrip<Real, decltype(S)::H>::NQP * cols * sizeof(Real);
+  });
+  return b;
 }
 
 template <class Real>
 const void* reverse_fn(int cols) {
-  if (cols <= 256) return reinterpret_cast<const void*>(&rts_reverse<Real, rev_rows<Real>(256), 256, 2, 2>);
-  if (cols <= 512) return reinterpret_cast<const void*>(&rts_reverse<Real, rev_rows<Real>(512), 512, 1, 2>);
-  if (cols <= 768) return reinterpret_cast<const void*>(&rts_reverse<Real, rev_rows<Real>(768), 768, 3, 3>);
-  if constexpr (sizeof(Real) == 4)
-    return reinterpret_cast<const void*>(&rts_reverse<Real, rev_rows<Real>(1024), 1024, 4, 4>);
-  return nullptr;
+  const void* fn = nullptr;
+  rev_dispatch<Real>(cols, [&](auto S) {
+    using Sh = decltype(S);
+    fn = reinterpret_cast<const void*>(&rts_reverse<Real, Sh::H, Sh::T, Sh::W0, Sh::W1>);
+  });
+  return fn;
 }
 
 template <class Real>
 hipError_t launch_reverse(const RevArgs& a, int grid, int cols, hipStream_t st) {
-  if (cols > rev_max_cols<Real>()) return hipErrorInvalidValue;
   const size_t lds = reverse_lds_bytes<Real>(cols);
-  const dim3 g(grid), b(cols);
-  if (cols <= 256) rts_reverse<Real, rev_rows<Real>(256), 256, 2, 2><<<g, b, lds, st>>>(a);
-  else if (cols <= 512) rts_reverse<Real, rev_rows<Real>(512), 512, 1, 2><<<g, b, lds, st>>>(a);
-  else if (cols <= 768) rts_reverse<Real, rev_rows<Real>(768), 768, 3, 3><<<g, b, lds, st>>>(a);
-  else if constexpr (sizeof(Real) == 4)
-    rts_reverse<Real, rev_rows<Real>(1024), 1024, 4, 4><<<g, b, lds, st>>>(a);
-  return hipGetLastError();
+  const bool ok = rev_dispatch<Real>(cols, [&](auto S) {
+    using Sh = decltype(S);
+    rts_reverse<Real, Sh::H, Sh::T, Sh::W0, Sh::W1><<<dim3(grid), dim3(cols), lds, st>>>(a);
+  });
+  return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
-// the host's view of the launch shape
+// the host's view of the launch shape: rows per strip (0: not supported)
 template <class Real>
 int reverse_rows(int cols) {
-  return rev_rows<Real>(cols);
+  int h = 0;
+  rev_dispatch<Real>(cols, [&](auto S) { h = decltype(S)::H; });
+  return h;
 }
 
 #define RTS_REV_INST(Real)                                                 \
