@@ -208,25 +208,20 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
     return base + __builtin_amdgcn_readfirstlane(off);
   };
 
-  // buffer resources of the arrays read and written per row (raw buffer
-  // accesses: a uniform resource, a per-lane 32-bit offset and a uniform one)
-  const Rsrc rC = rts_rsrc(chi), rS = rts_rsrc(Sv), rP = rts_rsrc(P);
-  constexpr uint32_t ES = sizeof(Real);
   // chi and S of a plane, rows -1..H (index 0..H+1)
   Real ncx[H + 2], nsx[H + 2];
   auto load_plane = [&](int q) __attribute__((always_inline)) {
     const int qo = q * ps;
 #pragma unroll
     for (int i = 0; i < H; ++i) {
-      const uint32_t o = (uint32_t)(qo + (r0 + (FULL || i < hr ? i : 0)) * rs) * ES;
-      ncx[i + 1] = buf_load<Real>(rC, cb, o) * csc;
-      nsx[i + 1] = buf_load<Real>(rS, cb, o);
+      const int o = qo + (r0 + (FULL || i < hr ? i : 0)) * rs;
+      ncx[i + 1] = *lane_at(urow(chi, o), cb) * csc;
+      nsx[i + 1] = *lane_at(urow(Sv, o), cb);
     }
-    const uint32_t ol = (uint32_t)(qo + lrow * rs) * ES, oh = (uint32_t)(qo + hrow * rs) * ES;
-    ncx[0] = buf_load<Real>(rC, cb, ol) * csc;
-    nsx[0] = buf_load<Real>(rS, cb, ol);
-    ncx[H + 1] = buf_load<Real>(rC, cb, oh) * csc;
-    nsx[H + 1] = buf_load<Real>(rS, cb, oh);
+    ncx[0] = *lane_at(urow(chi, qo + lrow * rs), cb) * csc;
+    nsx[0] = *lane_at(urow(Sv, qo + lrow * rs), cb);
+    ncx[H + 1] = *lane_at(urow(chi, qo + hrow * rs), cb) * csc;
+    nsx[H + 1] = *lane_at(urow(Sv, qo + hrow * rs), cb);
   };
   // outputs of plane q from the new D and S: the pairwise sum of w_r D_r over
   // the task's four slots (the sums over tasks and bands are FP64) and I_top
@@ -242,7 +237,7 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
       } else {
         sum = fmad(wgt[1], Dn[i][1], wgt[0] * Dn[i][0]) + fmad(wgt[3], Dn[i][3], wgt[2] * Dn[i][2]);
       }
-      buf_store(rP, ub, (uint32_t)(qo + (r0 + i) * rs) * ES, sum);
+      *lane_at(urow(P, qo + (r0 + i) * rs), ub) = sum;
     }
     if (EXT >= 1 && A.flux && T.flux_off >= 0) {  // (a box without flux partials writes none)
       // flux partials sum_r (w mu_k)_r D_r along k = cols, rows (and the plane
@@ -289,12 +284,12 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
   // D of unrolled plane u, kept for the adjoint's reverse sweep
   auto store_d = [&](int u, const Real (&Dn)[H][R]) __attribute__((always_inline)) {
     if (!A.store_d || !act) return;
-    const Rsrc rD = rts_rsrc(reinterpret_cast<Real*>(A.ws) + T.dstore_off + (int64_t)u * R * T.n_rows * W);
+    Real* ds = gptr(reinterpret_cast<Real*>(A.ws) + T.dstore_off + (int64_t)u * R * T.n_rows * W);
 #pragma unroll
     for (int i = 0; i < H; ++i) {
       if (!FULL && i >= hr) break;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf_store(rD, ub, (uint32_t)((r * T.n_rows + r0 + i) * W) * ES, Dn[i][r]);
+      for (int r = 0; r < R; ++r) *lane_at(urow(ds, (r * T.n_rows + r0 + i) * W), ub) = Dn[i][r];
     }
   };
   // store the plane (ncx, nsx, Dn) as the next step's old plane
