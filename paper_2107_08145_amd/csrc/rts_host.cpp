@@ -54,13 +54,13 @@ template <class Real>
 hipError_t launch_block_sweep(const BlockArgs&, int, hipStream_t);
 
 template <class Real>
-size_t reverse_lds_bytes(int);
+size_t reverse_lds_bytes(int, bool);
 template <class Real>
-const void* reverse_fn(int cols);
+const void* reverse_fn(int cols, bool small);
 template <class Real>
-int reverse_rows(int cols);
+int reverse_rows(int cols, bool small);
 template <class Real>
-hipError_t launch_reverse(const RevArgs&, int, int, hipStream_t);
+hipError_t launch_reverse(const RevArgs&, int, int, bool, hipStream_t);
 template <class Real>
 hipError_t launch_adj_seed(const void*, const void*, const double*, const void*, void*, void*,
                            double, int, int, int, hipStream_t);
@@ -158,6 +158,7 @@ struct Plan {
   };
   std::vector<WidthClass> wclasses;
   std::vector<WidthClass> rclasses;  // the same for the reverse sweep (threads: padded columns)
+  std::map<int, bool> rev_small;     // reverse launch width -> short strips (small problems)
   int threads = 64;
   bool uni = true;  // every task's four slots share f1, f2, ds and w
   // subdomain decomposition: every box of the plan is divided (rts_desc.sub)
@@ -518,13 +519,30 @@ void build_layout(Plan& P) {
   // rays of a task are independent in reverse and their gradients only add),
   // each with strips of the reverse launch's rows for its width class.
   const int ntask = (int)P.tasks.size();
+  auto rev_cols = [&](const Task& T) {
+    return P.sched.single_launch ? P.threads : (T.n_cols + 63) / 64 * 64;
+  };
+  auto rev_rows = [&](int cols, bool small) {
+    // (0 for a width the reverse sweep does not support: refused at the call)
+    return std::max(1, P.prec == RTS_FP32 ? reverse_rows<float>(cols, small)
+                                          : reverse_rows<double>(cols, small));
+  };
+  // Per launch width, the tall strips, or the short ones where the tall
+  // strips' workgroups would give the 256 CUs fewer than two waves per SIMD
+  // (a small grid: its passes' strip chains are the only parallelism).
+  constexpr int64_t kRevMinWaves = 2 * 4 * 256;
+  std::map<int, int64_t> tall_waves;
+  for (const Task& T : P.tasks) {
+    const int cols = rev_cols(T), h = rev_rows(cols, false);
+    tall_waves[cols] += 2 * (int64_t)((T.n_rows + h - 1) / h) * ((cols + 63) / 64);
+  }
+  P.rev_small.clear();
+  for (const auto& kv : tall_waves) P.rev_small[kv.first] = kv.second < kRevMinWaves;
   for (int t = 0; t < ntask; ++t) {
     const Task& T = P.tasks[t];
     AdjTask& AT = P.atasks[t];
-    const int cols = P.sched.single_launch ? P.threads : (T.n_cols + 63) / 64 * 64;
-    // (0 for a width the reverse sweep does not support: refused at the call)
-    const int hr = std::max(1, P.prec == RTS_FP32 ? reverse_rows<float>(cols)
-                                                  : reverse_rows<double>(cols));
+    const int cols = rev_cols(T);
+    const int hr = rev_rows(cols, P.rev_small[cols]);
     AT.task = t;
     AT.u_init = T.z_planes ? 0 : -1;
     AT.part = 0;
@@ -666,12 +684,13 @@ int occupancy_h(Plan& P) {
   }
   P.rev_blocks = 1 << 30;
   for (Plan::WidthClass& c : P.rclasses) {
-    const void* fn = reverse_fn<Real>(c.threads);
+    const bool small = P.rev_small.count(c.threads) && P.rev_small.at(c.threads);
+    const void* fn = reverse_fn<Real>(c.threads, small);
     if (!fn) {  // (wider than the reverse sweep supports: no resident block)
       c.blocks = 0;
       continue;
     }
-    int rc = resident_blocks(fn, c.threads, reverse_lds_bytes<Real>(c.threads), &c.blocks);
+    int rc = resident_blocks(fn, c.threads, reverse_lds_bytes<Real>(c.threads, small), &c.blocks);
     if (rc) return rc;
     P.rev_blocks = std::min(P.rev_blocks, c.blocks);
   }
@@ -977,7 +996,8 @@ int enqueue_adjoint(Plan& P, const rts_inputs* in, const rts_seeds* g, const rts
     a.total_strips = c.strips;
     a.wclass = (int)k;
     const int grid = std::max(1, std::min(c.blocks * P.cus, c.strips));
-    RTS_HIP(launch_reverse<Real>(a, grid, c.threads, st));
+    const bool small = P.rev_small.count(c.threads) && P.rev_small.at(c.threads);
+    RTS_HIP(launch_reverse<Real>(a, grid, c.threads, small, st));
   }
   for (size_t b = 0; b < P.boxes.size(); ++b) {
     const BoxGeo G = box_geo(P, b);

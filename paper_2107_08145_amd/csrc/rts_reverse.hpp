@@ -491,7 +491,7 @@ void rts_reverse(RevArgs A) {
 // loads' latency) over more cells; on planes of up to 128 columns the extra
 // resident waves of 4-row strips win over 6 rows (measured on the 96^2 x 512
 // box and at 128^3; 3 and 4 rows lose to 6 from 192 columns on).
-template <class Real, int C>
+template <class Real, int C, bool SMALL = false>
 struct RevShape;
 template <> struct RevShape<float, 0> { static constexpr int H = 4, T = 128, W0 = 3, W1 = 3; };
 template <> struct RevShape<float, 1> { static constexpr int H = 6, T = 256, W0 = 2, W1 = 2; };
@@ -502,33 +502,39 @@ template <> struct RevShape<double, 0> { static constexpr int H = 2, T = 128, W0
 template <> struct RevShape<double, 1> { static constexpr int H = 2, T = 256, W0 = 2, W1 = 2; };
 template <> struct RevShape<double, 2> { static constexpr int H = 2, T = 512, W0 = 1, W1 = 2; };
 template <> struct RevShape<double, 3> { static constexpr int H = 1, T = 768, W0 = 3, W1 = 3; };
+// Small problems (a launch whose tall strips would leave the SIMDs with
+// fewer than two waves each): FP32 planes up to 256 columns in 2-row strips
+// (126 VGPRs, four waves per SIMD), so that there are twice or thrice as many.
+template <> struct RevShape<float, 0, true> { static constexpr int H = 2, T = 128, W0 = 4, W1 = 4; };
+template <> struct RevShape<float, 1, true> { static constexpr int H = 2, T = 256, W0 = 4, W1 = 4; };
 
 constexpr int rev_class(int cols) {
   return cols <= 128 ? 0 : cols <= 256 ? 1 : cols <= 512 ? 2 : cols <= 768 ? 3 : 4;
 }
-template <class Real>
-constexpr int rev_classes() {
-  return sizeof(Real) == 4 ? 5 : 4;
-}
-template <class Real, int C>
-using RevSh = RevShape<Real, C>;
-template <class Real, int C>
-constexpr const void* rev_kernel() {
-  using S = RevSh<Real, C>;
-  return reinterpret_cast<const void*>(&rts_reverse<Real, S::H, S::T, S::W0, S::W1>);
-}
 
-// Calls f(shape) for the class of `cols` (false when the class is not built).
+// Calls f(shape) for the shape of `cols` (the small one if asked and there is
+// one); false when the width is not supported.
 template <class Real, class F>
-bool rev_dispatch(int cols, F&& f) {
+bool rev_dispatch(int cols, bool small, F&& f) {
+  constexpr bool f32 = sizeof(Real) == 4;
   switch (rev_class(cols)) {
-    case 0: f(RevSh<Real, 0>{}); return true;
-    case 1: f(RevSh<Real, 1>{}); return true;
-    case 2: f(RevSh<Real, 2>{}); return true;
-    case 3: f(RevSh<Real, 3>{}); return true;
+    case 0:
+      if constexpr (f32) {
+        if (small) { f(RevShape<Real, 0, true>{}); return true; }
+      }
+      f(RevShape<Real, 0>{});
+      return true;
+    case 1:
+      if constexpr (f32) {
+        if (small) { f(RevShape<Real, 1, true>{}); return true; }
+      }
+      f(RevShape<Real, 1>{});
+      return true;
+    case 2: f(RevShape<Real, 2>{}); return true;
+    case 3: f(RevShape<Real, 3>{}); return true;
     case 4:
-      if constexpr (rev_classes<Real>() > 4) {
-        f(RevSh<Real, 4>{});
+      if constexpr (f32) {
+        f(RevShape<Real, 4>{});
         return true;
       }
       return false;
@@ -537,18 +543,18 @@ bool rev_dispatch(int cols, F&& f) {
 }
 
 template <class Real>
-size_t reverse_lds_bytes(int cols) {
+size_t reverse_lds_bytes(int cols, bool small) {
   size_t b = 0;
-  rev_dispatch<Real>(cols, [&](auto S) {
+  rev_dispatch<Real>(cols, small, [&](auto S) {
     b = (size_t)RevStrip<Real, decltype(S)::H>::NQP * cols * sizeof(Real);
   });
   return b;
 }
 
 template <class Real>
-const void* reverse_fn(int cols) {
+const void* reverse_fn(int cols, bool small) {
   const void* fn = nullptr;
-  rev_dispatch<Real>(cols, [&](auto S) {
+  rev_dispatch<Real>(cols, small, [&](auto S) {
     using Sh = decltype(S);
     fn = reinterpret_cast<const void*>(&rts_reverse<Real, Sh::H, Sh::T, Sh::W0, Sh::W1>);
   });
@@ -556,9 +562,9 @@ const void* reverse_fn(int cols) {
 }
 
 template <class Real>
-hipError_t launch_reverse(const RevArgs& a, int grid, int cols, hipStream_t st) {
-  const size_t lds = reverse_lds_bytes<Real>(cols);
-  const bool ok = rev_dispatch<Real>(cols, [&](auto S) {
+hipError_t launch_reverse(const RevArgs& a, int grid, int cols, bool small, hipStream_t st) {
+  const size_t lds = reverse_lds_bytes<Real>(cols, small);
+  const bool ok = rev_dispatch<Real>(cols, small, [&](auto S) {
     using Sh = decltype(S);
     rts_reverse<Real, Sh::H, Sh::T, Sh::W0, Sh::W1><<<dim3(grid), dim3(cols), lds, st>>>(a);
   });
@@ -567,16 +573,16 @@ hipError_t launch_reverse(const RevArgs& a, int grid, int cols, hipStream_t st) 
 
 // the host's view of the launch shape: rows per strip (0: not supported)
 template <class Real>
-int reverse_rows(int cols) {
+int reverse_rows(int cols, bool small) {
   int h = 0;
-  rev_dispatch<Real>(cols, [&](auto S) { h = decltype(S)::H; });
+  rev_dispatch<Real>(cols, small, [&](auto S) { h = decltype(S)::H; });
   return h;
 }
 
 #define RTS_REV_INST(Real)                                                 \
-  template size_t reverse_lds_bytes<Real>(int);                            \
-  template const void* reverse_fn<Real>(int);                              \
-  template int reverse_rows<Real>(int);                                    \
-  template hipError_t launch_reverse<Real>(const RevArgs&, int, int, hipStream_t);
+  template size_t reverse_lds_bytes<Real>(int, bool);                      \
+  template const void* reverse_fn<Real>(int, bool);                        \
+  template int reverse_rows<Real>(int, bool);                              \
+  template hipError_t launch_reverse<Real>(const RevArgs&, int, int, bool, hipStream_t);
 
 }  // namespace rts
