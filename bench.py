@@ -74,12 +74,14 @@ def task_list(p):
     return tasks * p.nbands
 
 
-def kernel_hash():
-    """Hash of the device sources (every .hip / .hpp file and the shared structures)."""
+def kernel_hash(prefix="rts_sweep"):
+    """Hash of a kernel's device sources (the files named prefix*, the device helpers and
+    the shared structures; rts_sweep: the forward sweep, rts_reverse: the adjoint's reverse
+    sweep): its counter summaries hold while it is unchanged."""
     d = os.path.join(ROOT, "paper_2107_08145_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")) or f == "rts_internal.h":
+        if f.startswith(prefix) or f in ("rts_device.hpp", "rts_internal.h"):
             h.update(f.encode())
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
@@ -556,8 +558,7 @@ def bench_batched(args):
     if other:
         out["other_launch_form"] = other
     if args.adjoint:
-        # one rts_adjoint call over every box (the z sweeps of the 576^2 x 192
-        # box are reversed as two slot-pair passes)
+        # one rts_adjoint call over every box
         fwd_ms = ms
         seeds, grads, host = [], [], []
         for i, p in enumerate(ps):
@@ -582,6 +583,10 @@ def bench_batched(args):
             # oracle's reverse mode (it keeps every sweep)
             import oracle
             got = [tuple(t.double().cpu().numpy() for t in g) for g in grads]
+            # (the adjoint workspace fills most of HBM: the checks' own plans need it back)
+            plan.release_workspace()
+            del grads
+            torch.cuda.empty_cache()
             errs = []
             for n, (p, pd, gq) in enumerate(zip(ps, pds, host)):
                 q = pd.astype(np.float64)
@@ -666,7 +671,12 @@ def main():
                     help="print the mean per dispatch of every counter of rocprofv3 --pmc runs "
                          "for the kernels named by --kernel")
     ap.add_argument("--kernel", default="rts_", help="with --counter-summary: kernel name substring")
+    ap.add_argument("--source-hash", metavar="PREFIX",
+                    help="print the hash of the device sources of a kernel (rts_sweep, rts_reverse)")
     args = ap.parse_args()
+    if args.source_hash:
+        print(kernel_hash(args.source_hash))
+        return
     if args.counter_summary:
         print(json.dumps(counter_summary(args.counter_summary, args.kernel), indent=1))
         return

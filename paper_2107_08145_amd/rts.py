@@ -246,6 +246,10 @@ class Plan:
                "rts_plan_last_timing")
         return a.value, b.value
 
+    def release_workspace(self):
+        """Drop the plan's own workspace (the next call allocates one again)."""
+        self._ws = None
+
     def workspace(self, op: int = RTS_OP_SOLVE):
         import torch
         need = self.workspace_bytes(op)
