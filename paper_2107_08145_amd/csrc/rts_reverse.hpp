@@ -174,37 +174,42 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
   for (int i = 0; i < H; ++i) {  // (a ghost or boundary step reads them unused)
     dq[i][0] = dq[i][1] = sdv[i] = gsv[i] = gcv[i] = cpv[i] = spv[i] = Real(0);
   }
-  // (k: the step; q: the plane the loads are of)
+  // (k: the step; q: the plane the loads are of).  Branch-free: a load that a
+  // step does not need (beyond the last step, the ghost or boundary plane, a
+  // seed outside the last lap, a partial at its first visit) reads row 0 of
+  // its array instead (in cache after the first time) and is not used; the
+  // branches would split the step into small blocks that each reload the
+  // buffer resources from spilled SGPRs.
+  constexpr uint32_t ES = sizeof(Real);
   auto load_up = [&](int k, int q) __attribute__((always_inline)) {
     const int u = U - 1 - k;
-    if (k < K && u >= 0 && !(zp && u == 0)) {
-      const int qo = q * ps;
+    const bool live = k < K && u >= 0 && !(zp && u == 0);
+    const int qo = live ? q * ps : 0;
 #pragma unroll
-      for (int j = 0; j < H + 2; ++j) {
-        const int o = qo + up_row(j) * rs;
-        upc[j] = buf_load<Real>(rC, cb, (uint32_t)o * sizeof(Real));
-        ups[j] = buf_load<Real>(rS, cb, (uint32_t)o * sizeof(Real));
-      }
+    for (int j = 0; j < H + 2; ++j) {
+      const uint32_t o = live ? (uint32_t)(qo + up_row(j) * rs) * ES : 0u;
+      upc[j] = buf_load<Real>(rC, cb, o);
+      ups[j] = buf_load<Real>(rS, cb, o);
     }
   };
   auto load_own = [&](int k, int i, int q) __attribute__((always_inline)) {
     const int u = U - 1 - k;
-    if (k >= K || u < 0) return;  // (the ghost plane is not in the last lap: no seed)
+    const bool live = k < K && u >= 0;  // (the ghost plane is not in the last lap: no seed)
+    const bool dlive = live && !(zp && u == 0);  // (the boundary plane: no recompute)
     const int gi = own_row(i);
-    const int o = q * ps + gi * rs;
-    if (u >= last_from) sdv[i] = buf_load<Real>(rSeed, cb, (uint32_t)o * sizeof(Real));
-    if (zp && u == 0) return;  // the boundary plane: no recompute
-    const Rsrc rD = rts_rsrc(Dst + (int64_t)u * R * pc);
+    const uint32_t o = (uint32_t)(q * ps + gi * rs) * ES;
+    sdv[i] = buf_load<Real>(rSeed, cb, live && u >= last_from ? o : 0u);
+    const Rsrc rD = rts_rsrc(Dst + (int64_t)(dlive ? u : 0) * R * pc);
 #pragma unroll
     for (int s = 0; s < 2; ++s)
-      dq[i][s] = buf_load<Real>(rD, cb, (uint32_t)(((part + 2 * s) * nr + gi) * W) * sizeof(Real));
+      dq[i][s] = buf_load<Real>(rD, cb, dlive ? (uint32_t)(((part + 2 * s) * nr + gi) * W) * ES : 0u);
   };
   auto load_part = [&](int k, int i, int q) __attribute__((always_inline)) {
     const int u = U - 1 - k;
-    if (k >= K || u >= last_from) return;  // the first visit of a cell writes its partial
-    const int o = q * ps + own_row(i) * rs;
-    gsv[i] = buf_load<Real>(rGS, cb, (uint32_t)o * sizeof(Real));
-    gcv[i] = buf_load<Real>(rGC, cb, (uint32_t)o * sizeof(Real));
+    const bool live = k < K && u < last_from;  // the first visit of a cell writes its partial
+    const uint32_t o = live ? (uint32_t)(q * ps + own_row(i) * rs) * ES : 0u;
+    gsv[i] = buf_load<Real>(rGS, cb, o);
+    gcv[i] = buf_load<Real>(rGC, cb, o);
   };
 
   // the neighbour's edge words of the downwind state, published at its step k-1 (tag k)
