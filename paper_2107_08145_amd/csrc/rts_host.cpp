@@ -46,6 +46,7 @@ hipError_t launch_scan_nonfinite(const void*, int64_t, int*, int, hipStream_t);
 hipError_t launch_gs_init(const GsArgs&, hipStream_t);
 hipError_t launch_gs_ghost(const GsArgs&, int, int, hipStream_t);
 hipError_t launch_gs_plane(const GsArgs&, int, int, int, int, int, int, hipStream_t);
+hipError_t launch_gs_step(const GsArgs&, int, int, int, hipStream_t);
 hipError_t launch_gs_finish(const GsArgs&, hipStream_t);
 
 template <class Real>
@@ -502,7 +503,7 @@ void build_layout(Plan& P) {
     P.gs_j = (int64_t)(off / 8); off = align_up(off + arr);
     P.gs_p = (int64_t)(off / 8); off = align_up(off + P.gsg.size() * arr);
     P.gs_l = (int64_t)(off / 8); off = align_up(off + arr);
-    P.gs_i = (int64_t)(off / 8); off = align_up(off + kMaxRaysPerTask * arr);
+    P.gs_i = (int64_t)(off / 8); off = align_up(off + P.gsg.size() * kMaxRaysPerTask * arr);
   }
   P.total = off;
 
@@ -824,6 +825,7 @@ int enqueue_gs(Plan& P, const rts_inputs* in, const rts_outputs* out, char* ws, 
   a.N = B.N;
   a.chi_off = B.chi_off;
   a.s_off = P.gs_s; a.j_off = P.gs_j; a.p_off = P.gs_p; a.l_off = P.gs_l; a.i_off = P.gs_i;
+  a.chit_off = B.chiT_off; a.st_off = B.sT_off;
   a.B = reinterpret_cast<const double*>(in[0].S);
   a.eps = reinterpret_cast<const double*>(in[0].eps);
   for (int k = 0; k < B.d.nbands; ++k) a.qw[k] = B.qw[k];
@@ -836,20 +838,34 @@ int enqueue_gs(Plan& P, const rts_inputs* in, const rts_outputs* out, char* ws, 
   if (mk && (mrc = mk->mark(1, st))) return mrc;
   const int n[3] = {a.nx, a.ny, a.nz};
   const int G = a.ngroups;
-  for (int it = 0; it < P.gs_iter; ++it)
+  // per iteration: the ghost planes; every group's laps with the iteration's S
+  // (all but the last group's last lap), one launch per step over the groups;
+  // then the last group's last lap, plane by plane, updating S
+  int steps = 0, pcmax = 0;
+  for (int g = 0; g < G; ++g) {
+    const GsGroup& gg = P.gsg[g];
+    steps = std::max(steps, (g == G - 1 ? gg.laps - 1 : gg.laps) * n[gg.axis]);
+    pcmax = std::max(pcmax, n[gg.ea] * n[gg.eb]);
+  }
+  const GsGroup& gl = P.gsg[G - 1];
+  const int nal = n[gl.axis], pcl = n[gl.ea] * n[gl.eb];
+  for (int it = 0; it < P.gs_iter; ++it) {
+    const int top = it == P.gs_iter - 1 ? 1 : 0;
+    // the [x][z][y] copy of the iteration's S for the x-dominant groups (and chi
+    // again, the same values)
+    if (it > 0)
+      RTS_HIP(launch_prep<double>(in[0].kappa, in[0].rho, ws + P.gs_s * sizeof(double), ws,
+                                  B.chi_off, B.chiT_off, B.sT_off, a.nx, a.ny, a.nz, a.nbands, st));
     for (int g = 0; g < G; ++g) {
       const GsGroup& gg = P.gsg[g];
-      const int na = n[gg.axis], pc = n[gg.ea] * n[gg.eb];
-      if (gg.axis != 2) RTS_HIP(launch_gs_ghost(a, g, pc, st));
-      for (int lap = 0; lap < gg.laps; ++lap) {
-        const bool last = lap == gg.laps - 1;
-        for (int t = 0; t < na; ++t) {
-          const int q = gg.sa > 0 ? t : na - 1 - t;
-          RTS_HIP(launch_gs_plane(a, g, q, last ? 1 : 0, last && g == G - 1 ? 1 : 0,
-                                  last && it == P.gs_iter - 1 ? 1 : 0, pc, st));
-        }
-      }
+      if (gg.axis != 2) RTS_HIP(launch_gs_ghost(a, g, n[gg.ea] * n[gg.eb], st));
     }
+    for (int t = 0; t < steps; ++t) RTS_HIP(launch_gs_step(a, t, top, pcmax, st));
+    for (int t = 0; t < nal; ++t) {
+      const int q = gl.sa > 0 ? t : nal - 1 - t;
+      RTS_HIP(launch_gs_plane(a, G - 1, q, 1, 1, top, pcl, st));
+    }
+  }
   if (mk && (mrc = mk->mark(2, st))) return mrc;
   RTS_HIP(launch_gs_finish(a, st));
   return RTS_OK;

@@ -195,7 +195,10 @@ struct GsArgs {
   int64_t j_off;          // J state [B][N]
   int64_t p_off;          // group contributions [G][B][N]
   int64_t l_off;          // local operator [B][N]
-  int64_t i_off;          // the current group's intensities [slot][B][N]
+  int64_t i_off;          // every group's intensities [group][slot][B][N], each [N] block in the
+                          // group's plane layout [plane][eb][ea]
+  int64_t chit_off;       // chi and the iteration's S in the [x][z][y] layout [B][N] (the
+  int64_t st_off;         // x-dominant groups read these: their planes are contiguous there)
   const double* B;        // thermal source [B][N] (the caller's S input)
   const double* eps;      // [B][N]
   double qw[16];          // band weights of Q
