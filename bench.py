@@ -422,8 +422,9 @@ def bench_gs(args):
     """Scattering with Gauss-Seidel source updates (FP64): the benchmark
     atmosphere (at --size, default 128^3) with a seeded photon destruction
     probability per cell, log-uniform in [1e-3, 1e-1], and --gs iterations.
-    Timed eagerly and as graph replays (one launch per plane of every group's
-    laps); `value` counts the cell-ray-band updates of the iterations."""
+    Timed eagerly and as graph replays (per iteration one launch per step over
+    the groups, then one per plane of the last group's last lap); `value`
+    counts the cell-ray-band updates of the iterations."""
     import torch
     from paper_2107_08145_amd import inputs, rts
     size = args.size or 128
@@ -462,6 +463,52 @@ def bench_gs(args):
         ref = oracle.solve_gs(p, eps, args.gs)
         out["errors_vs_oracle"] = {n: float(np.abs(g - o).max() / np.abs(o).max())
                                    for n, g, o in zip(("Q", "J", "I_top", "S"), got, ref)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_sub(args):
+    """The subdomain decomposition with lagged exchange (the paper's domain-
+    decomposed solver, emulated on one GPU): the benchmark workload cut into
+    --sub MX MY MZ blocks, n_iter iterations (or until --tol), graph replay;
+    the undivided solve of the same plan precision timed beside it.  `value`
+    counts the nominal cell-ray-band updates per solve, as the headline."""
+    import torch
+    from paper_2107_08145_amd import inputs, rts
+    p = inputs.workload(args.workload, size=args.size)
+    prec = rts.RTS_FP32 if args.prec == "fp32" else rts.RTS_FP64
+    pd = p.astype(np.float32 if prec == rts.RTS_FP32 else np.float64)
+    torch.cuda.set_device(0)
+    sub = tuple(args.sub)
+    plan = rts.Plan(pd, prec, sub=sub, tol=args.tol)
+    plan.set_schedule(use_graph=1)
+    ins = plan.device_inputs(pd)
+    outs = plan.new_outputs(pd)
+    plan.enable_timing(True)
+    ms = _time_calls(lambda: plan.solve_into([ins], [outs]), args.steps, args.warmup)
+    iter_ms, call_ms = plan.last_timing()
+    plan.enable_timing(False)
+    plan.check_status()
+    whole = rts.Plan(pd, prec)
+    whole.set_schedule(use_graph=1)
+    w_ms = _time_calls(lambda: whole.solve_into([ins], [whole.new_outputs(pd)]), args.steps, args.warmup)
+    nominal = p.ncells * p.nrays * p.nbands
+    out = {"metric": f"cell-ray-band updates/sec (RTS, {sub[0]}x{sub[1]}x{sub[2]} subdomains with "
+                     "lagged exchange)",
+           "value": nominal / (ms * 1e-3), "unit": "cell-ray-band updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if prec == rts.RTS_FP32 else "f64", "data": "synthetic",
+           "graph_replay": True, "iterations_ms": round(iter_ms, 4),
+           "executed_updates_per_s": nominal * p.n_iter / (iter_ms * 1e-3),
+           "undivided_ms_per_step": round(w_ms, 4),
+           "config": {"workload": f"{args.workload}: {p.nx}x{p.ny}x{p.nz}, {p.nbands} bands, "
+                                  f"{p.nrays} rays, n_iter {p.n_iter}", "sub": list(sub),
+                      "tol": args.tol}}
+    if args.errors:
+        import oracle
+        got = [t.double().cpu().numpy() for t in outs]
+        ref = oracle.solve_sub(pd.astype(np.float64), sub, tol=args.tol, threads=16)
+        out["errors_vs_oracle"] = error_report(got, ref[:3])
     print(json.dumps(out), flush=True)
 
 
@@ -641,6 +688,8 @@ def main():
     ap.add_argument("--warm", action="store_true",
                     help="with --tol: successive calls on 1 %% perturbed atmospheres, cold against "
                          "warm-started from the previous call's final ghost planes")
+    ap.add_argument("--sub", type=int, nargs=3, metavar=("MX", "MY", "MZ"),
+                    help="subdomains with lagged exchange: blocks along x, y, z")
     ap.add_argument("--gs", type=int, default=0,
                     help="scattering with Gauss-Seidel source updates: this many iterations "
                          "(FP64; default size 128)")
@@ -711,6 +760,9 @@ def main():
         return
     if args.gs:
         bench_gs(args)
+        return
+    if args.sub:
+        bench_sub(args)
         return
     if args.warm:
         if not args.tol > 0:
