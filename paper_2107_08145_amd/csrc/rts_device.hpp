@@ -190,24 +190,27 @@ struct Tagged<double> {
 
 
 // c = (1 - e)/x of the linear-source step, e = exp(-x), by its closed form
-// or by its power series (x < 0.1, where 1 - e cancels).  FP32 takes
-// xs = x log2(e) (the factor is folded into the scaled opacities) so that e is
-// one v_exp_f32; its series has 5 terms (truncation 1.4e-8 relative).  FP64
-// takes xs = x and 11 terms.
+// or by its power series where 1 - e cancels.  FP32 takes xs = x log2(e) (the
+// factor is folded into the scaled opacities) so that e is one v_exp_f32; the
+// switch is at x = 0.094, where the closed form's error from the rounding of
+// e (one ulp of e over 1 - e, 6.6e-7 relative) and the truncation of a series
+// of four terms (x^4/120, 6.5e-7) balance.  FP64 takes xs = x, the switch at
+// 0.1 and 11 terms.
 __device__ inline float rts_exp_step(float xs) { return __builtin_amdgcn_exp2f(-xs); }
 __device__ inline double rts_exp_step(double x) { return exp(-x); }
-__device__ inline bool rts_small_step(float xs) { return xs < 0.1f * 1.4426950408889634f; }
+__device__ inline bool rts_small_step(float xs) { return xs < 0.094f * 1.4426950408889634f; }
 __device__ inline bool rts_small_step(double x) { return x < 0.1; }
 __device__ inline float rts_c_closed(float xs, float e) {
-  return (1.f - e) * (__builtin_amdgcn_rcpf(xs) * 1.4426950408889634f);
+  // (1 - e) log2(e) / xs, the factor taken into one fma
+  constexpr float l2e = 1.4426950408889634f;
+  return fmaf(-l2e, e, l2e) * __builtin_amdgcn_rcpf(xs);
 }
 __device__ inline double rts_c_closed(double x, double e) { return (1.0 - e) / x; }
 __device__ inline float rts_c_series(float xs) {
-  // sum_{n=0}^{4} (-x)^n / (n+1)!  with x = xs ln2
+  // sum_{n=0}^{3} (-x)^n / (n+1)!  with x = xs ln2
   constexpr float ln2 = 0.69314718055994531f;
-  constexpr float a1 = -ln2 / 2.f, a2 = ln2 * ln2 / 6.f, a3 = -ln2 * ln2 * ln2 / 24.f,
-                  a4 = ln2 * ln2 * ln2 * ln2 / 120.f;
-  return fmaf(fmaf(fmaf(fmaf(xs, a4, a3), xs, a2), xs, a1), xs, 1.f);
+  constexpr float a1 = -ln2 / 2.f, a2 = ln2 * ln2 / 6.f, a3 = -ln2 * ln2 * ln2 / 24.f;
+  return fmaf(fmaf(fmaf(xs, a3, a2), xs, a1), xs, 1.f);
 }
 __device__ inline double rts_c_series(double x) {
   double s = 1.0 / 39916800.0;  // 1/11!

@@ -429,24 +429,50 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
         for (int r = 0; r < R; ++r) o.d[r] = Real(0);
       }
     };
-    // the formal solution of row i from the interpolated old rows i-1, i, i+1
-    auto solve_row = [&](int i, const LR& lp, const LR& lk, const LR& ln, Real* out)
-        __attribute__((always_inline)) {
+    // the formal solution of row i from the interpolated old rows i-1, i, i+1.
+    // With UNI the four slots share f2, and the row interpolations of chi and
+    // S are taken as lk + f2 (lp - lk) or lk + f2 (ln - lk) with the current
+    // cell's chi added to (S subtracted from) lk once per column direction;
+    // du holds lp - lk of chi (both column directions) and S, dn receives
+    // ln - lk, which is the next row's du negated.
+    auto solve_row = [&](int i, const LR& lp, const LR& lk, const LR& ln, const Real (&du)[4],
+                         Real (&dn)[4], Real* out) __attribute__((always_inline)) {
       const Real cpv = ncx[i + 1], spv = nsx[i + 1];
+      if constexpr (UNI) {
+        Real tc[2], ts[2];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int v = UNI ? (r < 2 ? 0 : 1) : r;
-        const bool up = (r & 1) == 0;
-        const Real bc = lerp(lk.c[v], up ? lp.c[v] : ln.c[v], f2[r]);
-        const Real bs = lerp(lk.s[v], up ? lp.s[v] : ln.s[v], f2[r]);
-        const Real bd = lerp(lk.d[r], up ? lp.d[r] : ln.d[r], f2[r]);
-        // UNI: chi is stored pre-scaled by ds/2 (and log2 e in FP32)
-        const Real xs = UNI ? cpv + bc : hds[r] * (cpv + bc);
-        // both forms, then a select (a branch here costs registers)
-        const Real e = rts_exp_step(xs);
-        const Real c_ser = rts_c_series(xs), c_cl = rts_c_closed(xs, e);
-        const Real cw = rts_small_step(xs) ? c_ser : c_cl;
-        out[r] = fmad(e, bd, cw * (bs - spv));
+        for (int v = 0; v < 2; ++v) {
+          tc[v] = cpv + lk.c[v];  // chi is stored pre-scaled by ds/2 (and log2 e in FP32)
+          ts[v] = lk.s[v] - spv;
+          dn[v] = ln.c[v] - lk.c[v];
+          dn[2 + v] = ln.s[v] - lk.s[v];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int v = r < 2 ? 0 : 1;
+          const bool up = (r & 1) == 0;
+          const Real xs = fmad(f2[0], up ? du[v] : dn[v], tc[v]);
+          const Real bsd = fmad(f2[0], up ? du[2 + v] : dn[2 + v], ts[v]);  // B(S) - S
+          const Real bd = lerp(lk.d[r], up ? lp.d[r] : ln.d[r], f2[0]);
+          // both forms, then a select (a branch here costs registers)
+          const Real e = rts_exp_step(xs);
+          const Real c_ser = rts_c_series(xs), c_cl = rts_c_closed(xs, e);
+          const Real cw = rts_small_step(xs) ? c_ser : c_cl;
+          out[r] = fmad(e, bd, cw * bsd);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const bool up = (r & 1) == 0;
+          const Real bc = lerp(lk.c[r], up ? lp.c[r] : ln.c[r], f2[r]);
+          const Real bs = lerp(lk.s[r], up ? lp.s[r] : ln.s[r], f2[r]);
+          const Real bd = lerp(lk.d[r], up ? lp.d[r] : ln.d[r], f2[r]);
+          const Real xs = hds[r] * (cpv + bc);
+          const Real e = rts_exp_step(xs);
+          const Real c_ser = rts_c_series(xs), c_cl = rts_c_closed(xs, e);
+          const Real cw = rts_small_step(xs) ? c_ser : c_cl;
+          out[r] = fmad(e, bd, cw * (bs - spv));
+        }
       }
       const int gr = r0 + i;  // boundary rows (rows are z): set, not integrated
       if (gr == bc_up) {
@@ -493,10 +519,37 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
       }
     };
 
+    // lp - lk of chi (both column directions) and S (UNI only)
+    auto row_diff = [&](const LR& lp, const LR& lk, Real (&du)[4]) __attribute__((always_inline)) {
+      if constexpr (UNI) {
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          du[v] = lp.c[v] - lk.c[v];
+          du[2 + v] = lp.s[v] - lk.s[v];
+        }
+      }
+    };
+
     Real Dn[H][R];
-    // ---- edge rows first, published for the neighbouring strips
+    // ---- edge rows first, published for the neighbouring strips: the top
+    // row (of a strip of more than one row), then row 0.  (The interior rows
+    // interpolate rows 1 and 2 again: keeping row 0's copies across the
+    // publication measured slower, by the register allocation it leads to.)
+#pragma unroll
+    for (int i = 1; i < H; ++i) {
+      if (!(FULL ? (i == H - 1) : (i == hr - 1))) continue;
+      LR lp, lk, up_;
+      Real du[4], dn[4];
+      interp(i, true, lp);
+      interp(i + 1, true, lk);
+      interp(H + 1, false, up_);
+      halo_d(false, up_);
+      row_diff(lp, lk, du);
+      solve_row(i, lp, lk, up_, du, dn, Dn[i]);
+    }
     {
       LR lo, k0, n0;
+      Real du[4], dn[4];
       interp(0, false, lo);
       halo_d(true, lo);
       interp(1, true, k0);
@@ -506,17 +559,8 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
       } else {
         interp(2, true, n0);
       }
-      solve_row(0, lo, k0, n0, Dn[0]);
-    }
-#pragma unroll
-    for (int i = 1; i < H; ++i) {
-      if (!(FULL ? (i == H - 1) : (i == hr - 1))) continue;
-      LR lp, lk, up_;
-      interp(i, true, lp);
-      interp(i + 1, true, lk);
-      interp(H + 1, false, up_);
-      halo_d(false, up_);
-      solve_row(i, lp, lk, up_, Dn[i]);
+      row_diff(lo, k0, du);
+      solve_row(0, lo, k0, n0, du, dn, Dn[0]);
     }
     if (act) {
       const int xe = ((strip * 2 + (t & 1)) * 2) * xstride;
@@ -531,18 +575,24 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
         if ((r & 1) == 0) TG::put(lane_at(urow(X, xe + xstride + r * W * NW), xb_u), top, tag);  // upper: even
       }
     }
-    // ---- interior rows, sliding window of interpolated old rows
+    // ---- interior rows, sliding window of interpolated old rows (lp - lk of
+    // a row is ln - lk of the row below negated, exactly)
     if (FULL ? (H > 2) : (hr > 2)) {
-      LR a, b, d;
-      interp(1, true, a);
-      interp(2, true, b);
+      LR wa, wb, d;  // interpolated LDS rows i, i + 1, i + 2
+      Real dw[4];    // ln - lk of the last row solved
+      interp(1, true, wa);
+      interp(2, true, wb);
+      row_diff(wb, wa, dw);
 #pragma unroll
       for (int i = 1; i < H - 1; ++i) {
         if (!FULL && i >= hr - 1) break;
+        Real du[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) du[m] = -dw[m];
         interp(i + 2, true, d);
-        solve_row(i, a, b, d, Dn[i]);
-        a = b;
-        b = d;
+        solve_row(i, wa, wb, d, du, dw, Dn[i]);
+        wa = wb;
+        wb = d;
       }
     }
     lds_barrier();  // every thread has read the old plane
