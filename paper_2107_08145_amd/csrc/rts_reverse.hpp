@@ -258,15 +258,21 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
       for (int m = 0; m < 3; ++m) lc[ST::qh(s, m)] = has_src ? TG::value(hw[s][m]) : Real(0);
   };
   // before overwriting ring entry (k+1) % kRevRing (tag k+1-kRevRing), its
-  // reader must have taken it: its progress word is at least k+1-kRevRing
+  // reader must have taken it: its progress word is at least k+1-kRevRing.
+  // Progress only grows, so the last value read stands until a step needs
+  // more (a device-scope load costs a memory round trip: once per several
+  // steps instead of every step).
+  int seen = 0;
   auto ring_free = [&](int k) __attribute__((always_inline)) {
     const int need = k + 1 - kRevRing;
-    if (!has_dst || need < 1) return;
-    if (__builtin_amdgcn_readfirstlane(ld_dev(progress + dst)) >= need) return;
+    if (!has_dst || need <= seen) return;
+    seen = __builtin_amdgcn_readfirstlane(ld_dev(progress + dst));
+    if (seen >= need) return;
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     for (;;) {
       __builtin_amdgcn_s_sleep(1);
-      if (__builtin_amdgcn_readfirstlane(ld_dev(progress + dst)) >= need) break;
+      seen = __builtin_amdgcn_readfirstlane(ld_dev(progress + dst));
+      if (seen >= need) break;
       if (timed_out(t0)) break;
     }
   };
@@ -401,8 +407,8 @@ __device__ __forceinline__ void run_rev_strip(const RevArgs& A, CTask& T, CAdjTa
       for (int i = 0; i < H; ++i)
         if (i == top) do_row(i);
     }
+    if (k + 1 < K) ring_free(k);  // (every wave: the check is uniform)
     if (act && k + 1 < K) {
-      ring_free(k);
       const int xe = (strip * kRevRing + ((k + 1) % kRevRing)) * xstride;
       const uint32_t tag = (uint32_t)(k + 1);
 #pragma unroll
