@@ -165,8 +165,6 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
   const Real csc = UNI ? hds[0] : Real(1);
   const bool zp = T.z_planes != 0;
   const int bc_up = zp ? -1 : 0, bc_dn = zp ? -1 : T.n_rows - 1;
-  // the strip holds a boundary row (a uniform flag: the rows of most strips are all integrated)
-  const bool strip_bc = !zp && (r0 == 0 || r0 + hr == T.n_rows);
 
   const Real* chi = gptr(reinterpret_cast<const Real*>(A.ws) + T.chi_off);
   const Real* Sv = gptr(T.transposed ? reinterpret_cast<const Real*>(A.ws) + T.s_off
@@ -477,7 +475,6 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
         }
       }
       const int gr = r0 + i;  // boundary rows (rows are z): set, not integrated
-      if (__builtin_expect(strip_bc, false)) {
       if (gr == bc_up) {
         const Real v = fmad((Real)T.bu_a, spv, (Real)T.bu_b);
         out[0] = v; out[2] = v;
@@ -485,7 +482,6 @@ __device__ __forceinline__ void run_strip(const SweepArgs& A, CTask& T, const in
       if (gr == bc_dn) {
         const Real v = fmad((Real)T.bd_a, spv, (Real)T.bd_b);
         out[1] = v; out[3] = v;
-      }
       }
     };
     // halo D of the slots that look at the halo row (even: lower, odd: upper).
