@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void rts_block_init(BlockArgs A) {
 // One iteration: grid.x = block (blocks of the task's box beyond its count
 // return), grid.y = task.
 template <class Real>
-__global__ __launch_bounds__(256) void rts_block_sweep(BlockArgs A) {
+__global__ __launch_bounds__(1024) void rts_block_sweep(BlockArgs A) {
   constexpr int R = kMaxRaysPerTask;
   const Task& T = A.tasks[blockIdx.y];
   const int nbc = T.nblk[0], nbr = T.nblk[1], nbp = T.nblk[2];
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void rts_block_sweep(BlockArgs A) {
     __syncthreads();  // this plane of the field is complete for the next one
   }
   if (tw) {
-    __shared__ double red[2][4];
+    __shared__ double red[2][16];
     for (int off = 32; off >= 1; off >>= 1) {
       dmax = fmax(dmax, __shfl_xor(dmax, off));
       imax = fmax(imax, __shfl_xor(imax, off));
@@ -214,15 +214,16 @@ hipError_t launch_block_init(const BlockArgs& a, int64_t max_cells, hipStream_t 
 }
 
 template <class Real>
-hipError_t launch_block_sweep(const BlockArgs& a, int max_blocks, hipStream_t st) {
+hipError_t launch_block_sweep(const BlockArgs& a, int max_blocks, int threads, hipStream_t st) {
+  if (threads < 64 || threads > 1024 || threads % 64) return hipErrorInvalidValue;
   const dim3 grid((unsigned)max_blocks, (unsigned)a.ntasks);
-  rts_block_sweep<Real><<<grid, dim3(256), 0, st>>>(a);
+  rts_block_sweep<Real><<<grid, dim3((unsigned)threads), 0, st>>>(a);
   return hipGetLastError();
 }
 
 template hipError_t launch_block_init<float>(const BlockArgs&, int64_t, hipStream_t);
 template hipError_t launch_block_init<double>(const BlockArgs&, int64_t, hipStream_t);
-template hipError_t launch_block_sweep<float>(const BlockArgs&, int, hipStream_t);
-template hipError_t launch_block_sweep<double>(const BlockArgs&, int, hipStream_t);
+template hipError_t launch_block_sweep<float>(const BlockArgs&, int, int, hipStream_t);
+template hipError_t launch_block_sweep<double>(const BlockArgs&, int, int, hipStream_t);
 
 }  // namespace rts
