@@ -507,7 +507,7 @@ struct RevShape;
 template <> struct RevShape<float, 0> { static constexpr int H = 4, T = 128, W0 = 3, W1 = 3; };
 template <> struct RevShape<float, 1> { static constexpr int H = 6, T = 256, W0 = 2, W1 = 2; };
 template <> struct RevShape<float, 2> { static constexpr int H = 6, T = 512, W0 = 1, W1 = 2; };
-template <> struct RevShape<float, 3> { static constexpr int H = 3, T = 768, W0 = 3, W1 = 3; };
+template <> struct RevShape<float, 3> { static constexpr int H = 4, T = 768, W0 = 3, W1 = 3; };
 template <> struct RevShape<float, 4> { static constexpr int H = 2, T = 1024, W0 = 4, W1 = 4; };
 template <> struct RevShape<double, 0> { static constexpr int H = 2, T = 128, W0 = 2, W1 = 2; };
 template <> struct RevShape<double, 1> { static constexpr int H = 2, T = 256, W0 = 2, W1 = 2; };
